@@ -1,0 +1,174 @@
+/*
+ * lp.h - C ABI of the MI355X (gfx950) neighbourhood-based link predictor.
+ *
+ * Implements the prediction of Sahu, "A Fast Parallel Approach for
+ * Neighborhood-based Link Prediction by Disregarding Large Hubs"
+ * (arXiv 2401.11415): for every source vertex a, two-hop accumulation of the
+ * common neighbours it shares with each second-order vertex c (Section 4.1),
+ * optionally disregarding intermediates whose degree exceeds a hub limit
+ * (DLH, Section 4.2), scoring by one of nine local measures (Section 3.1),
+ * and selection of the top-scoring predicted edges (Section 4.1.6 and the
+ * merging phase of Algorithm 1).
+ *
+ * Conventions for every entry point
+ *  - Vertex ids are int32 in [0, n); a graph is simple and undirected, given
+ *    as CSR with every row sorted ascending and both arc directions present.
+ *  - Every call returns an lp_status; on failure it writes no partial output,
+ *    sets *out_count (where there is one) to 0, and records a message that
+ *    lp_last_error() returns on the same thread.
+ *  - "Device or host pointer": either memory type is accepted; the library
+ *    checks with hipPointerGetAttributes and copies as needed.
+ *  - Work is enqueued on hip_stream (a hipStream_t; NULL = the null stream).
+ *    lp_predict and lp_query return after the stream has finished the call.
+ *  - A graph is not thread-safe: a second call on the same graph while one is
+ *    running on another thread returns LP_ERR_BUSY.
+ *  - No C++ exception crosses this boundary.
+ */
+#ifndef LP_H
+#define LP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lp_graph lp_graph; /* opaque; owns all device memory of one graph */
+
+typedef enum {
+  LP_OK = 0,
+  LP_ERR_INVALID_ARGUMENT = 1, /* a scalar argument or pointer is out of its domain */
+  LP_ERR_INVALID_GRAPH = 2,    /* the CSR violates the conventions above */
+  LP_ERR_OUT_OF_MEMORY = 3,    /* device memory exhausted; the graph stays usable */
+  LP_ERR_DEVICE = 4,           /* a HIP runtime call failed */
+  LP_ERR_BUSY = 5              /* the graph is in use by another thread */
+} lp_status;
+
+/* The nine measures of Section 3.1 (equations CN ... RA).  With h the number
+ * of explored common neighbours and d_v the observed degree:
+ *   CN  h                      JC  h / (d_a + d_c - h)   (union, Section 4.1.2)
+ *   SI  h / (d_a + d_c)        SC  h / sqrt(d_a * d_c)
+ *   HP  h / min(d_a, d_c)      HD  h / max(d_a, d_c)
+ *   LHN h / (d_a * d_c)
+ *   AA  sum over explored common neighbours b of 1 / ln(d_b)
+ *   RA  sum over explored common neighbours b of 1 / d_b
+ * Scores are evaluated in FP64 and returned rounded to FP32 (Section 5.1:
+ * 32-bit floats for scores). */
+typedef enum {
+  LP_CN = 0, LP_JC = 1, LP_SI = 2, LP_SC = 3, LP_HP = 4,
+  LP_HD = 5, LP_LHN = 6, LP_AA = 7, LP_RA = 8
+} lp_measure;
+
+/* hub_limit value meaning "no limit": every intermediate is explored, i.e.
+ * the improved baseline IBase (Section 4.4 treats IBase as L_H = infinity). */
+#define LP_HUB_NONE INT64_MAX
+
+/* lp_graph_create flags */
+#define LP_VALIDATE 1u /* check sortedness, duplicates, self-loops and symmetry */
+
+/*
+ * Copy a CSR graph to the device and build the resident structures
+ * (degree-ordered relabelling and per-arc two-hop bookkeeping).
+ *   n        number of vertices, 0 <= n <= INT32_MAX.
+ *   offsets  n+1 int64, offsets[0] == 0, non-decreasing, offsets[n] = arcs
+ *            (twice the undirected edge count, < 2^32).  Device or host pointer.
+ *   indices  offsets[n] int32 neighbour ids.  Device or host pointer.
+ *   flags    0 or LP_VALIDATE.
+ *   out      receives the new graph; unchanged on failure.
+ * Ownership: the inputs are copied; the caller keeps them.  Offsets and index
+ * ranges are always checked (LP_ERR_INVALID_GRAPH); LP_VALIDATE adds the
+ * semantic checks.  Results on a graph that breaks the conventions without
+ * LP_VALIDATE are unspecified (but memory-safe).
+ */
+lp_status lp_graph_create(int64_t n, const int64_t *offsets, const int32_t *indices,
+                          uint32_t flags, lp_graph **out);
+
+/* Release every device allocation of g.  NULL is accepted. */
+lp_status lp_graph_destroy(lp_graph *g);
+
+/* Number of vertices and arcs, and the device bytes the graph holds. */
+lp_status lp_graph_info(const lp_graph *g, int64_t *n, int64_t *arcs, int64_t *max_degree,
+                        int64_t *device_bytes);
+
+/*
+ * Whole-graph link prediction (Algorithm 1, predictLinks).
+ *   m                measure.
+ *   hub_limit        L_H: an intermediate b is explored iff d_b <= hub_limit
+ *                    (Section 4.2.1); LP_HUB_NONE gives IBase.  Must be >= 0.
+ *   k                N_P, the maximum number of edges to predict, >= 0.
+ *   score_threshold  S_th: only pairs whose FP32 score is strictly greater are
+ *                    predicted (Algorithm 1, scoring phase); finite and >= 0.
+ *   out_a, out_c     k int32 each: predicted edges (a, c) with a < c, original
+ *                    vertex ids.  Device or host pointers, caller-owned.
+ *   out_score        k float: FP32 scores.  Device or host pointer.
+ *   out_count        host pointer; receives k' = min(k, number of candidates).
+ * Candidates are unordered non-adjacent pairs with at least one explored common
+ * neighbour (Sections 4.1.1 and 4.1.4).  Rows are written in the order
+ * (score desc, a asc, c asc), which fixes one of the equally correct answers
+ * when scores tie (Section 4.2.3 notes that ties make the choice arbitrary).
+ */
+lp_status lp_predict(lp_graph *g, lp_measure m, int64_t hub_limit, int64_t k,
+                     float score_threshold, int32_t *out_a, int32_t *out_c, float *out_score,
+                     int64_t *out_count, void *hip_stream);
+
+/*
+ * Per-vertex recommendation (the ranked candidate list of Section 3: the
+ * top-k links for one vertex).  For each sources[i], its candidates are every
+ * c != s that is not a neighbour of s and shares at least one explored common
+ * neighbour with s; the top k_q by (score desc, c asc) are returned.
+ *   sources          n_sources int32 vertex ids (repeats allowed).  Device or
+ *                    host pointer.
+ *   k_q              > 0, results per source.
+ *   out_c, out_score n_sources * k_q entries; row i holds out_count[i] results.
+ *   out_count        n_sources int32.  Device or host pointer.
+ */
+lp_status lp_query(lp_graph *g, const int32_t *sources, int64_t n_sources, lp_measure m,
+                   int64_t hub_limit, int32_t k_q, float score_threshold, int32_t *out_c,
+                   float *out_score, int32_t *out_count, void *hip_stream);
+
+/*
+ * Order-independent digest of the whole candidate set for hub limit L (the
+ * prediction orientation, unordered pairs): out[0] = number of candidates,
+ * out[1] = sum of h, out[2] = sum over candidates of mix64(a, c, h) modulo
+ * 2^64 with original ids a < c, out[3] = wedges explored.  mix64 is the
+ * SplitMix64 finaliser of ((a << 32) | c) XOR (h * 0x9E3779B97F4A7C15).
+ * Used to verify exact counts at sizes where the candidate set cannot be
+ * listed.  out is a host pointer to 4 uint64.
+ */
+lp_status lp_fingerprint(lp_graph *g, int64_t hub_limit, uint64_t *out, void *hip_stream);
+
+/* Tuning knobs of the scheduler; 0 keeps the default.  Values apply to later
+ * calls on g.  lds_wedge_cap caps the per-source wedge count handled with an
+ * LDS table (larger sources use the global-memory table); global_slots caps
+ * the global table size per workgroup (larger sources run in several hash
+ * partitions); sample_budget is the wedge budget of the sampling pass that
+ * sets the top-k filter threshold (0 disables sampling). */
+typedef struct {
+  int64_t lds_wedge_cap;
+  int64_t global_slots;
+  int64_t sample_budget;
+  int64_t reserved[5];
+} lp_tuning;
+lp_status lp_set_tuning(lp_graph *g, const lp_tuning *t);
+
+/* Statistics of the last lp_predict / lp_fingerprint on g (host pointer). */
+typedef struct {
+  uint64_t wedges;            /* two-hop paths accumulated */
+  uint64_t sources;           /* sources with at least one wedge */
+  uint64_t bucket_sources[8]; /* sources per scheduling bucket */
+  uint64_t appended;          /* candidates written to the selection buffer */
+  uint64_t retries;           /* extra passes after a threshold estimate missed */
+  double ms_plan, ms_accumulate, ms_select, ms_total; /* device time per phase */
+} lp_stats;
+lp_status lp_last_stats(const lp_graph *g, lp_stats *out);
+
+/* Human-readable name of a status, and the detail of the last failure on the
+ * calling thread ("" if none).  Both return static / thread-local storage. */
+const char *lp_status_string(lp_status s);
+const char *lp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LP_H */

@@ -66,6 +66,9 @@ def _load():
     lib.oracle_predict.restype = i64
     lib.oracle_predict.argtypes = [i64, vp, vp, i64, ctypes.c_int, i64, f32, ctypes.c_int,
                                    vp, vp, vp, vp]
+    lib.oracle_predict_sources.restype = i64
+    lib.oracle_predict_sources.argtypes = [i64, vp, vp, i64, ctypes.c_int, i64, f32, ctypes.c_int,
+                                           vp, i64, vp, vp, vp, vp]
     lib.oracle_query.restype = ctypes.c_int
     lib.oracle_query.argtypes = [i64, vp, vp, i64, ctypes.c_int, vp, i64, i32, f32,
                                  ctypes.c_int, vp, vp, vp, vp]
@@ -156,6 +159,25 @@ def predict(g, L, m, k: int, s_th: float = 0.0, threads: int = 0):
                            s32.ctypes.data, s64.ctypes.data)
     if r < 0:
         raise MemoryError("oracle_predict")
+    return {"a": a[:r], "c": c[:r], "s32": s32[:r], "s64": s64[:r]}
+
+
+def predict_sources(g, L, m, k: int, sources, s_th: float = 0.0, threads: int = 0):
+    """Top-k among the candidates owned by the given sources (pairs a < c with
+    a in sources): dict with a, c, s32, s64."""
+    lib = _load()
+    off, idx = _arrays(g)
+    src = np.ascontiguousarray(sources, dtype=np.int32)
+    kk = max(int(k), 0)
+    a = np.zeros(max(kk, 1), np.int32)
+    c = np.zeros(max(kk, 1), np.int32)
+    s32 = np.zeros(max(kk, 1), np.float32)
+    s64 = np.zeros(max(kk, 1), np.float64)
+    r = lib.oracle_predict_sources(g.n, off.ctypes.data, idx.ctypes.data, _hub(L), measure_id(m),
+                                   kk, float(s_th), int(threads), src.ctypes.data, src.shape[0],
+                                   a.ctypes.data, c.ctypes.data, s32.ctypes.data, s64.ctypes.data)
+    if r < 0:
+        raise MemoryError("oracle_predict_sources")
     return {"a": a[:r], "c": c[:r], "s32": s32[:r], "s64": s64[:r]}
 
 

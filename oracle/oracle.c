@@ -302,9 +302,24 @@ static int get_threads(int nthreads) {
  * writes the list in order (fp32 score desc, a asc, c asc); -1 on allocation
  * failure.
  */
+int64_t oracle_predict_sources(int64_t n, const int64_t *off, const int32_t *idx, int64_t L,
+                               int m, int64_t k, float s_th, int nthreads, const int32_t *sources,
+                               int64_t ns, int32_t *out_a, int32_t *out_c, float *out_s32,
+                               double *out_s64);
+
 int64_t oracle_predict(int64_t n, const int64_t *off, const int32_t *idx, int64_t L, int m,
                        int64_t k, float s_th, int nthreads, int32_t *out_a, int32_t *out_c,
                        float *out_s32, double *out_s64) {
+  return oracle_predict_sources(n, off, idx, L, m, k, s_th, nthreads, NULL, n, out_a, out_c,
+                                out_s32, out_s64);
+}
+
+/* The same restricted to the sources listed (all vertices when sources is
+ * NULL): the candidates owned by those sources, top k of them. */
+int64_t oracle_predict_sources(int64_t n, const int64_t *off, const int32_t *idx, int64_t L,
+                               int m, int64_t k, float s_th, int nthreads, const int32_t *sources,
+                               int64_t ns, int32_t *out_a, int32_t *out_c, float *out_s32,
+                               double *out_s64) {
   int T = get_threads(nthreads);
   plist_t *P = (plist_t *)calloc((size_t)T, sizeof(plist_t));
   int failed = 0;
@@ -328,7 +343,8 @@ int64_t oracle_predict(int64_t n, const int64_t *off, const int32_t *idx, int64_
         failed = 1;
       } else {
 #pragma omp for schedule(dynamic, 2048)
-        for (int64_t a = 0; a < n; a++) {
+        for (int64_t i = 0; i < ns; i++) {
+          const int64_t a = sources ? sources[i] : i;
           fill_source(&tb, off, idx, L, m, a, 0);
           for (int64_t i = 0; i < tb.nkeys; i++) {
             int64_t c = tb.keys[i];

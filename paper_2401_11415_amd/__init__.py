@@ -1,0 +1,231 @@
+"""MI355X (gfx950) neighbourhood-based link prediction: Python binding of liblp.so.
+
+Argument marshalling only: every step of the prediction runs in the HIP
+kernels of ``csrc/`` behind the C ABI of ``include/lp.h``.  PyTorch provides
+device memory for outputs and the HIP stream.  The binding fails loudly when
+the native library is missing; there is no CPU fallback.
+
+Method: Sahu, "A Fast Parallel Approach for Neighborhood-based Link Prediction
+by Disregarding Large Hubs" (arXiv 2401.11415): two-hop common-neighbour
+accumulation per source (Section 4.1), hub limit L_H on intermediates
+(Section 4.2), the nine measures of Section 3.1, top-N_P prediction
+(Algorithm 1).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = ["MEASURES", "HUB_NONE", "LpError", "Graph", "predict", "query", "fingerprint",
+           "set_tuning", "last_stats", "library_path", "load"]
+
+MEASURES = ("CN", "JC", "SI", "SC", "HP", "HD", "LHN", "AA", "RA")
+HUB_NONE = (1 << 63) - 1  # L_H = infinity: IBase
+LP_VALIDATE = 1
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = os.path.join(_HERE, "liblp.so")
+_lib = None
+
+
+class LpError(RuntimeError):
+    def __init__(self, status: int, name: str, detail: str):
+        super().__init__(f"{name}: {detail}")
+        self.status = status
+        self.name = name
+        self.detail = detail
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("lds_wedge_cap", ctypes.c_int64), ("global_slots", ctypes.c_int64),
+                ("sample_budget", ctypes.c_int64), ("reserved", ctypes.c_int64 * 5)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("wedges", ctypes.c_uint64), ("sources", ctypes.c_uint64),
+                ("bucket_sources", ctypes.c_uint64 * 8), ("appended", ctypes.c_uint64),
+                ("retries", ctypes.c_uint64), ("ms_plan", ctypes.c_double),
+                ("ms_accumulate", ctypes.c_double), ("ms_select", ctypes.c_double),
+                ("ms_total", ctypes.c_double)]
+
+
+def library_path() -> str:
+    return _LIB
+
+
+def load():
+    """Load liblp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        raise ImportError(f"{_LIB} is missing: build it with paper_2401_11415_amd/build.py")
+    lib = ctypes.CDLL(_LIB)
+    vp, i64, i32, u32, f32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_float
+    st = ctypes.c_int
+    lib.lp_graph_create.restype = st
+    lib.lp_graph_create.argtypes = [i64, vp, vp, u32, ctypes.POINTER(vp)]
+    lib.lp_graph_destroy.restype = st
+    lib.lp_graph_destroy.argtypes = [vp]
+    lib.lp_graph_info.restype = st
+    lib.lp_graph_info.argtypes = [vp, vp, vp, vp, vp]
+    lib.lp_predict.restype = st
+    lib.lp_predict.argtypes = [vp, ctypes.c_int, i64, i64, f32, vp, vp, vp, vp, vp]
+    lib.lp_query.restype = st
+    lib.lp_query.argtypes = [vp, vp, i64, ctypes.c_int, i64, i32, f32, vp, vp, vp, vp]
+    lib.lp_fingerprint.restype = st
+    lib.lp_fingerprint.argtypes = [vp, i64, vp, vp]
+    lib.lp_set_tuning.restype = st
+    lib.lp_set_tuning.argtypes = [vp, ctypes.POINTER(_Tuning)]
+    lib.lp_last_stats.restype = st
+    lib.lp_last_stats.argtypes = [vp, ctypes.POINTER(_Stats)]
+    lib.lp_status_string.restype = ctypes.c_char_p
+    lib.lp_status_string.argtypes = [ctypes.c_int]
+    lib.lp_last_error.restype = ctypes.c_char_p
+    lib.lp_last_error.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != 0:
+        lib = load()
+        raise LpError(status, lib.lp_status_string(status).decode(), lib.lp_last_error().decode())
+
+
+def _measure(m) -> int:
+    if isinstance(m, str):
+        return MEASURES.index(m.upper())
+    return int(m)
+
+
+def _hub(L) -> int:
+    return HUB_NONE if L is None else int(L)
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(x):
+    """Data pointer of a numpy array or torch tensor (host or device)."""
+    if isinstance(x, np.ndarray):
+        return ctypes.c_void_p(x.ctypes.data)
+    return ctypes.c_void_p(x.data_ptr())
+
+
+class Graph:
+    """A CSR graph resident on the current HIP device (lp_graph)."""
+
+    def __init__(self, offsets, indices, validate: bool = False):
+        lib = load()
+        off = offsets
+        idx = indices
+        if isinstance(off, np.ndarray):
+            off = np.ascontiguousarray(off, dtype=np.int64)
+        if isinstance(idx, np.ndarray):
+            idx = np.ascontiguousarray(idx, dtype=np.int32)
+            if idx.size == 0:
+                idx = np.zeros(1, np.int32)
+        n = int(off.shape[0]) - 1
+        h = ctypes.c_void_p()
+        _check(lib.lp_graph_create(n, _ptr(off), _ptr(idx), LP_VALIDATE if validate else 0,
+                                   ctypes.byref(h)))
+        self._h = h
+        self.n = n
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("graph is closed")
+        return self._h
+
+    def info(self):
+        n, arcs, dmax, nbytes = (ctypes.c_int64() for _ in range(4))
+        _check(load().lp_graph_info(self.handle, ctypes.byref(n), ctypes.byref(arcs),
+                                    ctypes.byref(dmax), ctypes.byref(nbytes)))
+        return {"n": n.value, "arcs": arcs.value, "max_degree": dmax.value,
+                "device_bytes": nbytes.value}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            load().lp_graph_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def predict(g: Graph, measure, hub_limit, k: int, score_threshold: float = 0.0, out=None,
+            stream=None):
+    """Top-k predicted edges: (a, c, score) int32/int32/float32 CUDA tensors of
+    length k' = min(k, candidates), sorted by (score desc, a asc, c asc)."""
+    import torch
+    lib = load()
+    k = int(k)
+    if out is None:
+        dev = torch.device("cuda", torch.cuda.current_device())
+        out = (torch.empty(max(k, 1), dtype=torch.int32, device=dev),
+               torch.empty(max(k, 1), dtype=torch.int32, device=dev),
+               torch.empty(max(k, 1), dtype=torch.float32, device=dev))
+    a, c, s = out
+    cnt = ctypes.c_int64(0)
+    _check(lib.lp_predict(g.handle, _measure(measure), _hub(hub_limit), k, float(score_threshold),
+                          _ptr(a), _ptr(c), _ptr(s), ctypes.byref(cnt), _stream(stream)))
+    n = cnt.value
+    return a[:n], c[:n], s[:n]
+
+
+def query(g: Graph, sources, measure, hub_limit, k_q: int, score_threshold: float = 0.0,
+          stream=None):
+    """Per-source top-k_q recommendations: (c [ns, k_q] int32, score [ns, k_q]
+    float32, count [ns] int32) CUDA tensors; row i holds count[i] entries."""
+    import torch
+    lib = load()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if isinstance(sources, np.ndarray) or isinstance(sources, (list, tuple)):
+        src = torch.as_tensor(np.asarray(sources, dtype=np.int32), device=dev)
+    else:
+        src = sources.to(device=dev, dtype=torch.int32).contiguous()
+    ns = int(src.shape[0])
+    k_q = int(k_q)
+    oc = torch.empty((max(ns, 1), k_q), dtype=torch.int32, device=dev)
+    os_ = torch.empty((max(ns, 1), k_q), dtype=torch.float32, device=dev)
+    on = torch.zeros(max(ns, 1), dtype=torch.int32, device=dev)
+    _check(lib.lp_query(g.handle, _ptr(src), ns, _measure(measure), _hub(hub_limit), k_q,
+                        float(score_threshold), _ptr(oc), _ptr(os_), _ptr(on), _stream(stream)))
+    return oc[:ns], os_[:ns], on[:ns]
+
+
+def fingerprint(g: Graph, hub_limit, stream=None):
+    """(|C_L|, sum h, sum mix64(a, c, h) mod 2^64, wedges) over all candidates."""
+    out = (ctypes.c_uint64 * 4)()
+    _check(load().lp_fingerprint(g.handle, _hub(hub_limit), out, _stream(stream)))
+    return tuple(int(x) for x in out)
+
+
+def set_tuning(g: Graph, lds_wedge_cap: int = 0, global_slots: int = 0, sample_budget: int = 0):
+    t = _Tuning(lds_wedge_cap, global_slots, sample_budget)
+    _check(load().lp_set_tuning(g.handle, ctypes.byref(t)))
+
+
+def last_stats(g: Graph) -> dict:
+    s = _Stats()
+    _check(load().lp_last_stats(g.handle, ctypes.byref(s)))
+    return {"wedges": s.wedges, "sources": s.sources,
+            "bucket_sources": list(s.bucket_sources)[:5], "appended": s.appended,
+            "retries": s.retries, "ms_plan": s.ms_plan, "ms_accumulate": s.ms_accumulate,
+            "ms_select": s.ms_select, "ms_total": s.ms_total}

@@ -1,0 +1,140 @@
+// lp_common.h - internal definitions shared by the HIP translation units of
+// liblp.so: error handling, device buffers, the resident graph object and the
+// entry points of the device primitives.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "lp.h"
+
+namespace lp {
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+
+lp_status set_error(lp_status s, const char* fmt, ...);
+lp_status from_hip(hipError_t e, const char* what);
+void clear_error();
+
+#define LP_TRY(expr)                          \
+  do {                                        \
+    lp_status _s = (expr);                    \
+    if (_s != LP_OK) return _s;               \
+  } while (0)
+
+#define LP_HIP(expr)                                   \
+  do {                                                 \
+    hipError_t _e = (expr);                            \
+    if (_e != hipSuccess) return ::lp::from_hip(_e, #expr); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Device memory
+// ---------------------------------------------------------------------------
+
+// A growable device allocation.  ensure() keeps the contents only when no
+// reallocation is needed.
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  lp_status ensure(size_t bytes);
+  void release();
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Pinned host staging for small device -> host reads.
+struct HostBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  lp_status ensure(size_t bytes);
+  void release();
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// ---------------------------------------------------------------------------
+// Resident graph.  Vertices are relabelled by ascending (degree, original id);
+// "new" ids below are ranks in that order.  Ownership of an unordered pair by
+// its lower-ranked endpoint leaves every candidate, count and score unchanged
+// (a pair is reported with original ids) but makes the large-degree endpoint
+// the one that does little work.
+// ---------------------------------------------------------------------------
+
+constexpr int kNumBuckets = 6;  // scheduling buckets of the accumulation
+
+struct Workspace {
+  // plan
+  DevBuf cnt, wedges, lists, counters, stats;
+  // candidate buffers (score bits, original a, original c) and selection
+  DevBuf cand_s, cand_a, cand_c;
+  DevBuf tmp_s[2], tmp_a[2], tmp_c[2];
+  DevBuf hist, sel_state, sort_tmp[3], sort_counts, scan_tmp;
+  DevBuf global_tab;
+  unsigned global_slabs = 0;  // accumulator slabs in global_tab
+  // query
+  DevBuf q_src, q_cnt, q_wedges, q_rows, q_out;
+  HostBuf host_stats;
+};
+
+}  // namespace lp
+
+struct lp_graph {
+  int device = 0;
+  int64_t n = 0;
+  int64_t arcs = 0;
+  int64_t max_deg = 0;
+  int fixed_shift = 40;  // AA/RA sums are accumulated as fixed point with this many fraction bits
+  // device arrays in the relabelled id space
+  uint32_t* off = nullptr;       // n+1 row offsets
+  uint32_t* adj = nullptr;       // arcs, each row ascending
+  uint32_t* sufstart = nullptr;  // arc (a->b): first position in row b holding an id > a
+  uint32_t* psum = nullptr;      // arc (a->b): inclusive per-row prefix of |{c in row b : c > a}|
+  uint32_t* deg = nullptr;       // n, non-decreasing
+  uint32_t* below = nullptr;     // n, number of neighbours with a smaller id
+  uint32_t* perm = nullptr;      // n, new id -> original id
+  uint32_t* rank = nullptr;      // n, original id -> new id
+  std::vector<uint32_t> host_deg;  // copy of deg (sorted), for hub boundaries
+  int64_t device_bytes = 0;
+  lp::Workspace ws;
+  lp_tuning tuning{};
+  lp_stats last{};
+  std::atomic<int> busy{0};
+};
+
+namespace lp {
+
+// Number of relabelled vertices whose degree is <= L (they form a prefix).
+uint32_t hub_start(const lp_graph* g, int64_t L);
+
+// ---------------------------------------------------------------------------
+// Device primitives (prim.hip)
+// ---------------------------------------------------------------------------
+
+// exclusive scan of n uint32 into out (n entries), optional total
+lp_status scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, DevBuf& tmp,
+                             hipStream_t st);
+// inclusive scan of n uint32 into uint64 out
+lp_status scan_inclusive_u32_u64(const uint32_t* in, uint64_t* out, int64_t n, DevBuf& tmp,
+                                 hipStream_t st);
+
+// Stable LSD radix sort of n records with up to three uint32 words, ordered
+// ascending by the (possibly complemented) key words, most significant first.
+struct SortSpec {
+  uint32_t* w[3];       // record words (sorted in place)
+  int nwords;           // 1..3
+  int nkeys;            // the first nkeys words are the key, word 0 most significant
+  int key_bits[3];      // significant bits per key word (<= 32)
+  bool invert[3];       // complement this key word (descending order)
+};
+lp_status radix_sort(const SortSpec& spec, int64_t n, DevBuf tmp[3], DevBuf& counts,
+                     DevBuf& scan_tmp, hipStream_t st);
+
+int num_cus();
+
+}  // namespace lp

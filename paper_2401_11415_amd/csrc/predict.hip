@@ -1,0 +1,1364 @@
+// predict.hip - the hot path: per-source two-hop accumulation (IBase / DLH),
+// first-order exclusion, fused scoring, candidate filtering and top-k.
+//
+// Method (Sahu, arXiv 2401.11415, Section 4.1 and 4.2, Algorithm 1): for
+// every source a, every explored intermediate b in Gamma_a (d_b <= L_H) and
+// every c in Gamma_b with c > a, count the path a-b-c under key c (or add the
+// AA / RA weight of b); drop keys that are first-order neighbours of a; score
+// each remaining key; keep the best N_P pairs overall.
+//
+// GPU design (gfx950, wave64):
+//  * plan: for each source the number of explored arcs (a prefix of its row,
+//    since rows are sorted by degree rank) and its exact wedge count U(a);
+//    sources are bucketed by U(a).
+//  * accumulation: one group of G lanes per source with an open-addressing
+//    hash table in LDS sized 2*U(a) (G = 16, 64, 256 for growing U).  The
+//    wedges of a chunk of G arcs are enumerated as one flat index space so
+//    that lanes read consecutive ids of the same neighbour list (coalesced).
+//    Sources whose table would not fit are split into hash partitions
+//    processed one after the other; the largest sources use a dense
+//    accumulator in global memory.
+//  * scoring is fused into the table sweep; survivors of S_th and of a key
+//    threshold tau are appended with one atomic per wave.
+//  * top-k: MSD radix select over the 96-bit key (score bits, ~a, ~c), then a
+//    stable LSD radix sort of the k winners.  tau is estimated from a sampled
+//    subset of sources so that only about k candidates are ever written.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "kernels.h"
+
+namespace lp {
+
+// ---------------------------------------------------------------------------
+// Plan
+// ---------------------------------------------------------------------------
+
+constexpr int kBucketTiny = 0;   // U <= 32:    16 lanes, 64 slots
+constexpr int kBucketSmall = 1;  // U <= 256:   64 lanes, 512 slots
+constexpr int kBucketMid = 2;    // U <= 2048:  256 lanes, 4096 slots
+constexpr int kBucketLarge = 3;  // U <= cap:   256 lanes, 16384 (8192 weighted) slots, partitions
+constexpr int kBucketHuge = 4;   // U > cap:    dense accumulator in global memory
+constexpr int kBuckets = 5;
+
+struct PlanOut {
+  unsigned long long wedges;
+  unsigned long long sources;
+  uint32_t count[kBuckets];
+  uint32_t bad_source;
+};
+
+__device__ inline uint32_t lower_bound_dev(const uint32_t* __restrict__ a, uint32_t lo, uint32_t hi,
+                                           uint32_t x) {
+  while (lo < hi) {
+    uint32_t mid = lo + ((hi - lo) >> 1);
+    if (a[mid] < x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ inline int bucket_of(uint32_t U, uint32_t lds_cap) {
+  if (U == 0) return -1;
+  if (U > lds_cap) return kBucketHuge;
+  if (U <= 32) return kBucketTiny;
+  if (U <= 256) return kBucketSmall;
+  if (U <= 2048) return kBucketMid;
+  return kBucketLarge;
+}
+
+// Append `a` to list[b] for every lane, one atomic per (wave, bucket).
+__device__ inline void bucket_append(int b, uint32_t a, uint32_t* lists, uint64_t stride,
+                                     uint32_t* counts) {
+#pragma unroll
+  for (int k = 0; k < kBuckets; k++) {
+    const uint64_t m = __ballot(b == k);
+    if (m == 0) continue;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    uint32_t base = 0;
+    if (lane_id() == leader) base = atomicAdd(&counts[k], (uint32_t)__popcll(m));
+    base = __shfl(base, leader);
+    if (b == k) lists[(uint64_t)k * stride + base + (uint32_t)__popcll(m & lanemask_lt())] = a;
+  }
+}
+
+__global__ __launch_bounds__(256) void plan_kernel(GView g, uint32_t hub_start, uint32_t lds_cap,
+                                                   uint32_t* __restrict__ cnt,
+                                                   uint32_t* __restrict__ wedges,
+                                                   uint32_t* __restrict__ lists,
+                                                   PlanOut* __restrict__ out) {
+  const uint32_t a = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t U = 0;
+  int b = -1;
+  if (a < g.n) {
+    const uint32_t e0 = g.off[a], e1 = g.off[a + 1];
+    const uint32_t k = lower_bound_dev(g.adj, e0, e1, hub_start) - e0;
+    U = k ? g.psum[e0 + k - 1] : 0u;
+    cnt[a] = k;
+    wedges[a] = U;
+    b = bucket_of(U, lds_cap);
+  }
+  bucket_append(b, a, lists, g.n, out->count);
+  unsigned long long w = U, s = U ? 1ull : 0ull;
+  for (int o = 32; o >= 1; o >>= 1) {
+    w += __shfl_xor(w, o);
+    s += __shfl_xor(s, o);
+  }
+  if (lane_id() == 0 && s) {
+    atomicAdd(&out->wedges, w);
+    atomicAdd(&out->sources, s);
+  }
+}
+
+// query: map sources to new ids, explored prefix and an upper bound of the
+// wedges (all of Gamma_b, b explored), one workgroup per query
+__global__ __launch_bounds__(256) void query_plan_kernel(GView g, uint32_t hub_start,
+                                                         uint32_t lds_cap,
+                                                         const int32_t* __restrict__ src,
+                                                         const uint32_t* __restrict__ rank,
+                                                         uint32_t nq, uint32_t* __restrict__ qnew,
+                                                         uint32_t* __restrict__ cnt,
+                                                         uint32_t* __restrict__ wedges,
+                                                         uint32_t* __restrict__ lists,
+                                                         PlanOut* __restrict__ out) {
+  __shared__ unsigned long long part[4];
+  for (uint32_t q = blockIdx.x; q < nq; q += gridDim.x) {
+    const int32_t so = src[q];
+    const bool ok = so >= 0 && (uint32_t)so < g.n;
+    if (!ok && threadIdx.x == 0) atomicOr(&out->bad_source, 1u);
+    const uint32_t s = ok ? rank[so] : 0u;
+    const uint32_t e0 = g.off[s], e1 = g.off[s + 1];
+    const uint32_t k = ok ? lower_bound_dev(g.adj, e0, e1, hub_start) - e0 : 0u;
+    unsigned long long sum = 0;
+    for (uint32_t j = threadIdx.x; j < k; j += blockDim.x) sum += g.deg[g.adj[e0 + j]];
+    for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o);
+    if (lane_id() == 0) part[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      unsigned long long tot = part[0] + part[1] + part[2] + part[3];
+      uint32_t U = tot > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)tot;
+      int b = bucket_of(U, lds_cap);
+      if (threadIdx.x == 0) {
+        qnew[q] = s;
+        cnt[q] = k;
+        wedges[q] = U;
+        atomicAdd(&out->wedges, (unsigned long long)U);
+        if (U) atomicAdd(&out->sources, 1ull);
+      }
+      bucket_append(threadIdx.x == 0 ? b : -1, q, lists, nq, out->count);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Work lists: which list entries a launch processes.
+//   phase 0: all; 1: every stride-th (the sample); 2: the others.
+// ---------------------------------------------------------------------------
+
+struct WorkList {
+  const uint32_t* list;
+  uint32_t count;
+  uint32_t stride;
+  int phase;
+};
+
+__device__ inline uint32_t work_count(const WorkList& w) {
+  if (w.phase == 0 || w.stride <= 1) return w.phase == 2 ? 0u : w.count;
+  const uint32_t ns = (w.count + w.stride - 1) / w.stride;
+  return w.phase == 1 ? ns : w.count - ns;
+}
+
+__device__ inline uint32_t work_item(const WorkList& w, uint32_t i) {
+  if (w.phase == 0 || w.stride <= 1) return w.list[i];
+  if (w.phase == 1) return w.list[i * w.stride];
+  const uint32_t s1 = w.stride - 1;
+  return w.list[(i / s1) * w.stride + (i % s1) + 1];
+}
+
+// Per-source setup shared by the kernels.
+struct Src {
+  uint32_t a;       // relabelled id
+  uint32_t a_key;   // predict: original id; query: query index
+  uint32_t a_orig;  // original id
+  uint32_t e0, e1;  // row
+  uint32_t na;      // explored arcs (prefix of the row)
+  uint32_t U;       // wedges (predict: exact; query: upper bound)
+};
+
+template <bool kQuery>
+__device__ inline Src load_src(const GView& g, const uint32_t* cnt, const uint32_t* wedges,
+                               const uint32_t* qnew, uint32_t item) {
+  Src s;
+  if (kQuery) {
+    s.a = qnew[item];
+    s.a_key = item;
+    s.na = cnt[item];
+    s.U = wedges[item];
+  } else {
+    s.a = item;
+    s.a_key = 0;
+    s.na = cnt[item];
+    s.U = wedges[item];
+  }
+  s.e0 = g.off[s.a];
+  s.e1 = g.off[s.a + 1];
+  s.a_orig = g.perm[s.a];
+  if (!kQuery) s.a_key = s.a_orig;
+  return s;
+}
+
+// Load the chunk of arcs [cb, cb + G) of source s into the group scratch:
+// flat start index (excl), position of the first c in adj (start), weight.
+// Returns the flat range [lo, hi) of the chunk.
+template <int G, bool kQuery, bool kW>
+__device__ inline void load_chunk(const GView& g, const Emit& E, const Src& s, uint32_t cb,
+                                  uint32_t* s_excl, uint32_t* s_start, uint64_t* s_w,
+                                  uint32_t* scan_tmp, uint32_t* lo, uint32_t* hi) {
+  const int gl = threadIdx.x & (G - 1);
+  const uint32_t j = cb + gl;
+  const bool valid = j < s.na;
+  uint32_t start = 0, len = 0;
+  uint64_t w = 0;
+  if (valid) {
+    const uint32_t e = s.e0 + j;
+    if (kQuery) {
+      const uint32_t b = g.adj[e];
+      start = g.off[b];
+      len = g.off[b + 1] - start;
+      if (kW) w = weight_of(E.measure, len, E.shift);
+    } else {
+      start = g.sufstart[e];
+      if (kW) w = weight_of(E.measure, g.deg[g.adj[e]], E.shift);
+    }
+  }
+  if (kQuery) {
+    uint32_t total;
+    const uint32_t ex = group_exclusive_scan<G>(len, scan_tmp, &total);
+    s_excl[gl] = valid ? ex : kEmpty32;
+    *lo = 0;
+    *hi = total;
+  } else {
+    const uint32_t e = s.e0 + j;
+    const uint32_t ex = valid ? (j == 0 ? 0u : g.psum[e - 1]) : kEmpty32;
+    s_excl[gl] = ex;
+    *lo = cb == 0 ? 0u : g.psum[s.e0 + cb - 1];
+    const uint32_t last = (cb + G < s.na ? cb + G : s.na) - 1;
+    *hi = g.psum[s.e0 + last];
+  }
+  s_start[gl] = start;
+  if (kW) s_w[gl] = w;
+}
+
+// ---------------------------------------------------------------------------
+// LDS-table accumulation: G lanes per source, SLOTS slots per table.
+// ---------------------------------------------------------------------------
+
+template <int G, int SLOTS, bool kW>
+struct LdsTab {
+  static constexpr int NG = 256 / G;
+  uint64_t tab[kW ? 1 : NG * SLOTS];
+  uint32_t keys[kW ? NG * SLOTS : 1];
+  uint64_t vals[kW ? NG * SLOTS : 1];
+  uint32_t excl[NG][G];
+  uint32_t start[NG][G];
+  uint64_t w[kW ? NG : 1][kW ? G : 1];
+  uint32_t scan_tmp[4];
+  int ovf[NG];
+};
+
+template <int G, int SLOTS, bool kW, bool kQuery>
+__global__ __launch_bounds__(256) void acc_lds_kernel(GView g, Emit E, const uint32_t* __restrict__ cnt,
+                                                      const uint32_t* __restrict__ wedges,
+                                                      const uint32_t* __restrict__ qnew,
+                                                      WorkList wl) {
+  constexpr int NG = 256 / G;
+  __shared__ LdsTab<G, SLOTS, kW> L;
+  const int grp = threadIdx.x / G;
+  const int gl = threadIdx.x & (G - 1);
+  uint64_t* tab = L.tab + (kW ? 0 : grp * SLOTS);
+  uint32_t* keys = L.keys + (kW ? grp * SLOTS : 0);
+  uint64_t* vals = L.vals + (kW ? grp * SLOTS : 0);
+  uint32_t* s_excl = L.excl[grp];
+  uint32_t* s_start = L.start[grp];
+  uint64_t* s_w = kW ? L.w[grp] : nullptr;
+  FpAcc fa;
+  const uint32_t total = work_count(wl);
+  for (uint32_t i = blockIdx.x * NG + grp; i < total; i += gridDim.x * NG) {
+    const Src s = load_src<kQuery>(g, cnt, wedges, qnew, work_item(wl, i));
+    // partitions: P = 2^lgP so that each partition's table is at most half full
+    uint32_t lgP = 0;
+    while (((uint64_t)s.U * 2 >> lgP) > (uint64_t)SLOTS) lgP++;
+    const uint32_t per = (uint32_t)(((uint64_t)s.U + (1u << lgP) - 1) >> lgP);
+    uint32_t lgS = 4;
+    while ((1u << lgS) < 2 * per && (1u << lgS) < (uint32_t)SLOTS) lgS++;
+    const uint32_t S = 1u << lgS, mask = S - 1;
+    const uint32_t da = s.e1 - s.e0;
+    for (uint32_t pass = 0; pass < (1u << lgP); pass++) {
+      for (uint32_t t = gl; t < S; t += G) {
+        if (kW) {
+          keys[t] = kEmpty32;
+          vals[t] = 0;
+        } else {
+          tab[t] = kEmpty64;
+        }
+      }
+      if (gl == 0) L.ovf[grp] = 0;
+      group_sync<G>();
+      // accumulate the wedges of this source
+      for (uint32_t cb = 0; cb < s.na; cb += G) {
+        uint32_t lo, hi;
+        load_chunk<G, kQuery, kW>(g, E, s, cb, s_excl, s_start, s_w, L.scan_tmp, &lo, &hi);
+        group_sync<G>();
+        for (uint32_t f = lo + gl; f < hi; f += G) {
+          const int jj = seg_search<G>(s_excl, f);
+          const uint32_t c = g.adj[s_start[jj] + (f - s_excl[jj])];
+          if (kQuery && c == s.a) continue;
+          const uint32_t hc = c * kHashMul;
+          if (lgP && (hc >> (32 - lgP)) != pass) continue;
+          uint32_t h = (hc << lgP) >> (32 - lgS);
+          bool done = false;
+          if (kW) {
+            const uint64_t w = s_w[jj];
+            for (uint32_t probe = 0; probe < S; probe++) {
+              const uint32_t old = atomicCAS(&keys[h], kEmpty32, c);
+              if (old == kEmpty32 || old == c) {
+                atomicAdd((unsigned long long*)&vals[h], (unsigned long long)w);
+                done = true;
+                break;
+              }
+              h = (h + 1) & mask;
+            }
+          } else {
+            const uint64_t want = ((uint64_t)c << 32) | 1ull;
+            for (uint32_t probe = 0; probe < S; probe++) {
+              const uint64_t old = atomicCAS((unsigned long long*)&tab[h], kEmpty64, want);
+              if (old == kEmpty64) {
+                done = true;
+                break;
+              }
+              if ((uint32_t)(old >> 32) == c) {
+                atomicAdd((unsigned long long*)&tab[h], 1ull);
+                done = true;
+                break;
+              }
+              h = (h + 1) & mask;
+            }
+          }
+          if (!done) L.ovf[grp] = 1;
+        }
+        group_sync<G>();
+      }
+      // first-order neighbours are not candidates (predict: only ids > a can be keys)
+      const uint32_t x0 = kQuery ? s.e0 : s.e0 + g.below[s.a];
+      for (uint32_t e = x0 + gl; e < s.e1; e += G) {
+        const uint32_t b = g.adj[e];
+        const uint32_t hb = b * kHashMul;
+        if (lgP && (hb >> (32 - lgP)) != pass) continue;
+        uint32_t h = (hb << lgP) >> (32 - lgS);
+        for (uint32_t probe = 0; probe < S; probe++) {
+          if (kW) {
+            const uint32_t k = keys[h];
+            if (k == b) {
+              vals[h] = 0;
+              break;
+            }
+            if (k == kEmpty32) break;
+          } else {
+            const uint64_t v = tab[h];
+            const uint32_t k = (uint32_t)(v >> 32);
+            if (k == b) {
+              tab[h] = (uint64_t)b << 32;
+              break;
+            }
+            if (k == kEmpty32) break;
+          }
+          h = (h + 1) & mask;
+        }
+      }
+      group_sync<G>();
+      if (L.ovf[grp]) {
+        // the table filled up: hand the rest of this source to the global path
+        if (gl == 0) {
+          const uint32_t slot = atomicAdd(E.ovf_count, 1u);
+          if (slot < E.ovf_cap) {
+            E.ovf[2 * slot] = kQuery ? s.a_key : s.a;
+            E.ovf[2 * slot + 1] = pass | (lgP << 8);
+          } else {
+            atomicOr(E.err, kErrOvfList);
+          }
+        }
+        group_sync<G>();
+        break;
+      }
+      // score every key of this partition
+      for (uint32_t t = gl; t < S; t += G) {
+        uint32_t c, h = 0;
+        uint64_t wsum = 0;
+        bool valid;
+        if (kW) {
+          c = keys[t];
+          wsum = vals[t];
+          valid = c != kEmpty32 && wsum != 0;
+        } else {
+          const uint64_t v = tab[t];
+          c = (uint32_t)(v >> 32);
+          h = (uint32_t)v;
+          valid = c != kEmpty32 && h != 0;
+        }
+        emit_one<kQuery>(E, g, valid, s.a_orig, s.a_key, da, valid ? c : 0u, h, wsum, fa);
+      }
+      group_sync<G>();
+    }
+  }
+  flush_fp(E, fa);
+}
+
+// ---------------------------------------------------------------------------
+// Dense accumulator in global memory (the paper's per-thread table: a value
+// per vertex plus a key list), one workgroup per source.  Used for sources
+// whose wedge count exceeds the LDS capacity and for partitions handed over
+// by an overflowing LDS table.
+// ---------------------------------------------------------------------------
+
+struct SpaItem {
+  const uint32_t* ovf;  // if non-null: (source, pass | lgP << 8) records
+  uint32_t ovf_begin, ovf_end;
+};
+
+template <bool kW, bool kQuery>
+__global__ __launch_bounds__(256) void acc_spa_kernel(GView g, Emit E, const uint32_t* __restrict__ cnt,
+                                                      const uint32_t* __restrict__ wedges,
+                                                      const uint32_t* __restrict__ qnew,
+                                                      WorkList wl, SpaItem ov, char* spa_acc,
+                                                      uint32_t* spa_keys) {
+  __shared__ uint32_t s_excl[256], s_start[256], scan_tmp[4];
+  __shared__ uint64_t s_w[kW ? 256 : 1];
+  __shared__ uint32_t nkeys;
+  // one 8-byte-per-vertex accumulator slab per workgroup, whatever the measure:
+  // counts use its first half, so every slab stays zero between calls
+  char* slab = spa_acc + (uint64_t)blockIdx.x * g.n * 8;
+  uint32_t* H = reinterpret_cast<uint32_t*>(slab);
+  unsigned long long* HW = reinterpret_cast<unsigned long long*>(slab);
+  uint32_t* K = spa_keys + (uint64_t)blockIdx.x * g.n;
+  FpAcc fa;
+  const uint32_t total = ov.ovf ? (ov.ovf_end - ov.ovf_begin) : work_count(wl);
+  for (uint32_t i = blockIdx.x; i < total; i += gridDim.x) {
+    uint32_t item, p0 = 0, lgP = 0;
+    if (ov.ovf) {
+      item = ov.ovf[2 * (ov.ovf_begin + i)];
+      const uint32_t pl = ov.ovf[2 * (ov.ovf_begin + i) + 1];
+      p0 = pl & 0xFFu;
+      lgP = pl >> 8;
+    } else {
+      item = work_item(wl, i);
+    }
+    const Src s = load_src<kQuery>(g, cnt, wedges, qnew, item);
+    const uint32_t da = s.e1 - s.e0;
+    if (threadIdx.x == 0) nkeys = 0;
+    __syncthreads();
+    for (uint32_t cb = 0; cb < s.na; cb += 256) {
+      uint32_t lo, hi;
+      load_chunk<256, kQuery, kW>(g, E, s, cb, s_excl, s_start, s_w, scan_tmp, &lo, &hi);
+      __syncthreads();
+      for (uint32_t f = lo + threadIdx.x; f < hi; f += 256) {
+        const int jj = seg_search<256>(s_excl, f);
+        const uint32_t c = g.adj[s_start[jj] + (f - s_excl[jj])];
+        if (kQuery && c == s.a) continue;
+        if (lgP && ((c * kHashMul) >> (32 - lgP)) < p0) continue;
+        bool first;
+        if (kW) first = atomicAdd(&HW[c], (unsigned long long)s_w[jj]) == 0ull;
+        else first = atomicAdd(&H[c], 1u) == 0u;
+        if (first)
+          __hip_atomic_store(&K[atomicAdd(&nkeys, 1u)], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      __syncthreads();
+    }
+    const uint32_t x0 = kQuery ? s.e0 : s.e0 + g.below[s.a];
+    for (uint32_t e = x0 + threadIdx.x; e < s.e1; e += 256) {
+      const uint32_t b = g.adj[e];
+      if (kW) __hip_atomic_store(&HW[b], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      else __hip_atomic_store(&H[b], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __threadfence();
+    __syncthreads();
+    const uint32_t nk = nkeys;
+    for (uint32_t t = threadIdx.x; t < ((nk + 63) & ~63u); t += 256) {
+      const bool in = t < nk;
+      uint32_t c = 0, h = 0;
+      uint64_t wsum = 0;
+      bool valid = false;
+      if (in) {
+        c = __hip_atomic_load(&K[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (kW) {
+          wsum = __hip_atomic_exchange(&HW[c], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          valid = wsum != 0;
+        } else {
+          h = __hip_atomic_exchange(&H[c], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          valid = h != 0;
+        }
+      }
+      emit_one<kQuery>(E, g, valid, s.a_orig, s.a_key, da, c, h, wsum, fa);
+    }
+    __threadfence();
+    __syncthreads();
+  }
+  flush_fp(E, fa);
+}
+
+// ---------------------------------------------------------------------------
+// Radix select over the candidate buffer: the k largest keys
+// (score bits, ~a, ~c), 9 digit steps of 11 / 11 / 10 bits per key word.
+// ---------------------------------------------------------------------------
+
+struct SelState {
+  unsigned long long n_cur;  // entries in the working set
+  unsigned long long k_rem;  // entries still to take from it
+  unsigned long long n_out;  // entries emitted
+  unsigned long long n_next;
+  uint32_t digit;
+  uint32_t take_all;  // the boundary bin is taken whole
+  uint32_t done;
+  uint32_t prefix[3];  // boundary key digits found so far (key words, bits above the step)
+  uint32_t pad;
+};
+
+__device__ inline void step_geom(int step, int* word, int* shift, int* bits) {
+  *word = step / 3;
+  const int r = step % 3;
+  *shift = r == 0 ? 21 : (r == 1 ? 10 : 0);
+  *bits = r == 2 ? 10 : 11;
+}
+
+__device__ inline uint32_t key_word(uint32_t s, uint32_t a, uint32_t c, int word) {
+  return word == 0 ? s : (word == 1 ? ~a : ~c);
+}
+
+__global__ __launch_bounds__(256) void sel_hist_kernel(const uint32_t* __restrict__ ks,
+                                                       const uint32_t* __restrict__ ka,
+                                                       const uint32_t* __restrict__ kc,
+                                                       const SelState* __restrict__ st, int step,
+                                                       uint32_t* __restrict__ hist) {
+  __shared__ uint32_t lh[2048];
+  if (st->done) return;
+  const unsigned long long n = st->n_cur;
+  int word, shift, bits;
+  step_geom(step, &word, &shift, &bits);
+  const uint32_t mask = (1u << bits) - 1;
+  for (int i = threadIdx.x; i < 2048; i += 256) lh[i] = 0;
+  __syncthreads();
+  for (unsigned long long i = (unsigned long long)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (unsigned long long)gridDim.x * 256) {
+    const uint32_t kw = word == 0 ? ks[i] : (word == 1 ? ~ka[i] : ~kc[i]);
+    atomicAdd(&lh[(kw >> shift) & mask], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 2048; i += 256)
+    if (lh[i]) atomicAdd(&hist[i], lh[i]);
+}
+
+__global__ __launch_bounds__(64) void sel_pick_kernel(SelState* st, int step, uint32_t* hist) {
+  if (st->done) return;
+  int word, shift, bits;
+  step_geom(step, &word, &shift, &bits);
+  if (threadIdx.x == 0) {
+    const unsigned long long k = st->k_rem;
+    unsigned long long above = 0;
+    int d = (1 << bits) - 1;
+    for (; d >= 0; d--) {
+      if (above + hist[d] >= k) break;
+      above += hist[d];
+    }
+    if (d < 0) d = 0;  // cannot happen when n_cur >= k
+    st->digit = (uint32_t)d;
+    st->take_all = (above + hist[d] == k) ? 1u : 0u;
+    st->k_rem = k - above;
+    st->prefix[word] |= ((uint32_t)d) << shift;
+    st->n_next = 0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 2048; i += 64) hist[i] = 0;
+}
+
+__device__ inline unsigned long long wave_slot(bool pred, unsigned long long* counter) {
+  const uint64_t m = __ballot(pred);
+  if (m == 0) return 0;
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  unsigned long long base = 0;
+  if (lane_id() == leader) base = atomicAdd(counter, (unsigned long long)__popcll(m));
+  base = __shfl(base, leader);
+  return base + (unsigned long long)__popcll(m & lanemask_lt());
+}
+
+__global__ __launch_bounds__(256) void sel_partition_kernel(
+    const uint32_t* __restrict__ ks, const uint32_t* __restrict__ ka, const uint32_t* __restrict__ kc,
+    SelState* st, int step, uint32_t* __restrict__ ns, uint32_t* __restrict__ na,
+    uint32_t* __restrict__ nc, uint32_t* __restrict__ os, uint32_t* __restrict__ oa,
+    uint32_t* __restrict__ oc) {
+  if (st->done) return;
+  const unsigned long long n = st->n_cur;
+  int word, shift, bits;
+  step_geom(step, &word, &shift, &bits);
+  const uint32_t mask = (1u << bits) - 1;
+  const uint32_t dsel = st->digit;
+  const bool take_all = st->take_all != 0;
+  const unsigned long long n_round = (n + 63) & ~63ull;
+  for (unsigned long long i = (unsigned long long)blockIdx.x * 256 + threadIdx.x; i < n_round;
+       i += (unsigned long long)gridDim.x * 256) {
+    const bool in = i < n;
+    uint32_t s = 0, a = 0, c = 0, d = 0;
+    if (in) {
+      s = ks[i];
+      a = ka[i];
+      c = kc[i];
+      d = (key_word(s, a, c, word) >> shift) & mask;
+    }
+    const bool to_out = in && (d > dsel || (take_all && d == dsel));
+    const bool to_next = in && !take_all && d == dsel;
+    const unsigned long long po = wave_slot(to_out, &st->n_out);
+    const unsigned long long pn = wave_slot(to_next, &st->n_next);
+    if (to_out) {
+      os[po] = s;
+      oa[po] = a;
+      oc[po] = c;
+    }
+    if (to_next) {
+      ns[pn] = s;
+      na[pn] = a;
+      nc[pn] = c;
+    }
+  }
+}
+
+__global__ void sel_advance_kernel(SelState* st, int last_step) {
+  if (st->done) return;
+  if (st->take_all || last_step) {
+    st->done = 1;
+    return;
+  }
+  st->n_cur = st->n_next;
+}
+
+__global__ void sel_init_kernel(SelState* st, const unsigned long long* count,
+                                unsigned long long cap, unsigned long long base,
+                                unsigned long long k) {
+  unsigned long long n = *count;
+  if (n > cap) n = cap;
+  n = n > base ? n - base : 0;
+  st->n_cur = n;
+  st->n_out = 0;
+  st->n_next = 0;
+  st->prefix[0] = st->prefix[1] = st->prefix[2] = 0;
+  st->take_all = 0;
+  st->digit = 0;
+  st->k_rem = k < n ? k : n;
+  st->done = (k >= n) ? 2u : 0u;  // 2: everything is selected (copied separately)
+}
+
+__global__ void sel_copy_all_kernel(const uint32_t* __restrict__ ks, const uint32_t* __restrict__ ka,
+                                    const uint32_t* __restrict__ kc, SelState* st,
+                                    uint32_t* __restrict__ os, uint32_t* __restrict__ oa,
+                                    uint32_t* __restrict__ oc) {
+  if (st->done != 2) return;
+  const unsigned long long n = st->n_cur;
+  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (unsigned long long)gridDim.x * blockDim.x) {
+    os[i] = ks[i];
+    oa[i] = ka[i];
+    oc[i] = kc[i];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->n_out = n;
+}
+
+// tau from the boundary prefix: the k-th largest key is >= prefix (remaining bits 0)
+__global__ void sel_tau_kernel(const SelState* st, uint32_t* tau) {
+  if (st->done == 2 || st->n_cur == 0) {
+    tau[0] = tau[1] = tau[2] = 0;
+    return;
+  }
+  tau[0] = st->prefix[0];
+  tau[1] = st->prefix[1];
+  tau[2] = st->prefix[2];
+}
+
+__global__ void write_out_kernel(const uint32_t* __restrict__ s, const uint32_t* __restrict__ a,
+                                 const uint32_t* __restrict__ c, unsigned long long k,
+                                 int32_t* __restrict__ oa, int32_t* __restrict__ oc,
+                                 float* __restrict__ os) {
+  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < k;
+       i += (unsigned long long)gridDim.x * blockDim.x) {
+    oa[i] = (int32_t)a[i];
+    oc[i] = (int32_t)c[i];
+    os[i] = __uint_as_float(s[i]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Query result: per query index, the first k_q entries of its sorted segment
+// ---------------------------------------------------------------------------
+
+__global__ void query_take_kernel(const uint32_t* __restrict__ s, const uint32_t* __restrict__ c,
+                                  const uint32_t* __restrict__ seg_start,
+                                  const uint32_t* __restrict__ seg_count, uint32_t nq, int32_t kq,
+                                  int32_t* __restrict__ out_c, float* __restrict__ out_s,
+                                  int32_t* __restrict__ out_count) {
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (uint64_t)nq * kq;
+       t += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t q = (uint32_t)(t / (uint32_t)kq), j = (uint32_t)(t % (uint32_t)kq);
+    const uint32_t m = seg_count[q] < (uint32_t)kq ? seg_count[q] : (uint32_t)kq;
+    if (j == 0) out_count[q] = (int32_t)m;
+    if (j < m) {
+      out_c[t] = (int32_t)c[seg_start[q] + j];
+      out_s[t] = __uint_as_float(s[seg_start[q] + j]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host orchestration
+// ---------------------------------------------------------------------------
+
+static GView view_of(const lp_graph* g) {
+  GView v;
+  v.off = g->off;
+  v.adj = g->adj;
+  v.sufstart = g->sufstart;
+  v.psum = g->psum;
+  v.deg = g->deg;
+  v.below = g->below;
+  v.perm = g->perm;
+  v.n = (uint32_t)g->n;
+  return v;
+}
+
+static unsigned grid_for(uint64_t items, int per_block, unsigned cap_blocks) {
+  uint64_t b = (items + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > cap_blocks) b = cap_blocks;
+  return (unsigned)b;
+}
+
+struct AccConfig {
+  uint32_t lds_cap;   // wedges above which a source uses the global path
+  unsigned spa_wgs;   // workgroups (dense accumulators) of the global path
+};
+
+static AccConfig acc_config(const lp_graph* g) {
+  AccConfig c;
+  c.lds_cap = g->tuning.lds_wedge_cap > 0 ? (uint32_t)std::min<int64_t>(g->tuning.lds_wedge_cap, 1u << 30)
+                                          : 65536u;
+  c.spa_wgs = (unsigned)(g->tuning.global_slots > 0 ? g->tuning.global_slots : num_cus());
+  return c;
+}
+
+// Launch the accumulation of one work list in the given bucket.
+template <bool kW, bool kQuery>
+static lp_status launch_bucket(lp_graph* g, int bucket, const GView& gv, const Emit& E,
+                               const uint32_t* cnt, const uint32_t* wedges, const uint32_t* qnew,
+                               WorkList wl, uint64_t nitems, hipStream_t st) {
+  if (nitems == 0) return LP_OK;
+  const unsigned cus = (unsigned)num_cus();
+  switch (bucket) {
+    case kBucketTiny:
+      hipLaunchKernelGGL((acc_lds_kernel<16, 64, kW, kQuery>), dim3(grid_for(nitems, 16, cus * 16)),
+                         dim3(256), 0, st, gv, E, cnt, wedges, qnew, wl);
+      break;
+    case kBucketSmall:
+      hipLaunchKernelGGL((acc_lds_kernel<64, 512, kW, kQuery>), dim3(grid_for(nitems, 4, cus * 16)),
+                         dim3(256), 0, st, gv, E, cnt, wedges, qnew, wl);
+      break;
+    case kBucketMid:
+      hipLaunchKernelGGL((acc_lds_kernel<256, 4096, kW, kQuery>), dim3(grid_for(nitems, 1, cus * 8)),
+                         dim3(256), 0, st, gv, E, cnt, wedges, qnew, wl);
+      break;
+    case kBucketLarge:
+      hipLaunchKernelGGL((acc_lds_kernel<256, kW ? 8192 : 16384, kW, kQuery>),
+                         dim3(grid_for(nitems, 1, cus * 2)), dim3(256), 0, st, gv, E, cnt, wedges,
+                         qnew, wl);
+      break;
+    default:
+      return set_error(LP_ERR_INVALID_ARGUMENT, "bad bucket");
+  }
+  LP_HIP(hipGetLastError());
+  return LP_OK;
+}
+
+template <bool kW, bool kQuery>
+static lp_status launch_spa(lp_graph* g, const GView& gv, const Emit& E, const uint32_t* cnt,
+                            const uint32_t* wedges, const uint32_t* qnew, WorkList wl,
+                            SpaItem ov, uint64_t nitems, hipStream_t st) {
+  if (nitems == 0) return LP_OK;
+  AccConfig cfg = acc_config(g);
+  const size_t n = (size_t)g->n;
+  Workspace& w = g->ws;
+  // pool: cfg.spa_wgs slabs of 8n accumulator bytes, then as many key lists of 4n
+  const size_t need = (size_t)cfg.spa_wgs * n * 12;
+  if (w.global_tab.cap < need || w.global_slabs != cfg.spa_wgs) {
+    w.global_tab.release();
+    LP_TRY(w.global_tab.ensure(need));
+    LP_HIP(hipMemsetAsync(w.global_tab.p, 0, (size_t)cfg.spa_wgs * n * 8, st));
+    w.global_slabs = cfg.spa_wgs;
+  }
+  // the accumulators are left zeroed by every workgroup; the key lists need no init
+  char* base = w.global_tab.as<char>();
+  uint32_t* spa_keys = reinterpret_cast<uint32_t*>(base + (size_t)cfg.spa_wgs * n * 8);
+  const unsigned wgs = (unsigned)std::min<uint64_t>(cfg.spa_wgs, nitems);
+  hipLaunchKernelGGL((acc_spa_kernel<kW, kQuery>), dim3(wgs), dim3(256), 0, st, gv, E, cnt, wedges,
+                     qnew, wl, ov, base, spa_keys);
+  LP_HIP(hipGetLastError());
+  return LP_OK;
+}
+
+// The whole accumulation for one phase (all buckets, then overflow records).
+template <bool kW, bool kQuery>
+static lp_status run_phase(lp_graph* g, const GView& gv, const Emit& E, const uint32_t* cnt,
+                           const uint32_t* wedges, const uint32_t* qnew, const uint32_t* lists,
+                           uint64_t list_stride, const uint32_t* counts_host, uint32_t stride,
+                           int phase, uint32_t* ovf_host_count, hipStream_t st) {
+  for (int b = 0; b < kBuckets; b++) {
+    WorkList wl{lists + (uint64_t)b * list_stride, counts_host[b], stride, phase};
+    uint64_t items;
+    if (phase == 0 || stride <= 1) items = phase == 2 ? 0 : counts_host[b];
+    else {
+      uint64_t ns = (counts_host[b] + stride - 1) / stride;
+      items = phase == 1 ? ns : counts_host[b] - ns;
+    }
+    if (b == kBucketHuge) {
+      LP_TRY((launch_spa<kW, kQuery>(g, gv, E, cnt, wedges, qnew, wl, SpaItem{nullptr, 0, 0}, items, st)));
+    } else {
+      LP_TRY((launch_bucket<kW, kQuery>(g, b, gv, E, cnt, wedges, qnew, wl, items, st)));
+    }
+  }
+  // overflow records written by this phase's LDS kernels
+  uint32_t ovf_total = 0;
+  LP_HIP(hipMemcpyAsync(&ovf_total, E.ovf_count, 4, hipMemcpyDeviceToHost, st));
+  LP_HIP(hipStreamSynchronize(st));
+  if (ovf_total > E.ovf_cap) return set_error(LP_ERR_OUT_OF_MEMORY, "overflow list exhausted");
+  if (ovf_total > *ovf_host_count) {
+    WorkList none{nullptr, 0, 1, 0};
+    SpaItem ov{E.ovf, *ovf_host_count, ovf_total};
+    LP_TRY((launch_spa<kW, kQuery>(g, gv, E, cnt, wedges, qnew, none, ov, ovf_total - *ovf_host_count, st)));
+    *ovf_host_count = ovf_total;
+  }
+  return LP_OK;
+}
+
+template <bool kQuery>
+static lp_status run_phase_any(lp_graph* g, const GView& gv, const Emit& E, const uint32_t* cnt,
+                               const uint32_t* wedges, const uint32_t* qnew, const uint32_t* lists,
+                               uint64_t list_stride, const uint32_t* counts_host, uint32_t stride,
+                               int phase, uint32_t* ovf_host_count, hipStream_t st) {
+  if (E.measure == LP_AA || E.measure == LP_RA)
+    return run_phase<true, kQuery>(g, gv, E, cnt, wedges, qnew, lists, list_stride, counts_host,
+                                   stride, phase, ovf_host_count, st);
+  return run_phase<false, kQuery>(g, gv, E, cnt, wedges, qnew, lists, list_stride, counts_host,
+                                  stride, phase, ovf_host_count, st);
+}
+
+// Radix select of the k largest keys among entries [base, count) of the
+// candidate buffer, into ws.tmp_*[1] ... the winners end in (os, oa, oc).
+static lp_status run_select(lp_graph* g, const uint32_t* cs, const uint32_t* ca, const uint32_t* cc,
+                            unsigned long long* count_dev, unsigned long long cap,
+                            unsigned long long base, unsigned long long k, uint32_t* os,
+                            uint32_t* oa, uint32_t* oc, uint32_t* tau_out, hipStream_t st) {
+  Workspace& w = g->ws;
+  LP_TRY(w.sel_state.ensure(sizeof(SelState) + 64));
+  LP_TRY(w.hist.ensure(2048 * 4));
+  SelState* sst = w.sel_state.as<SelState>();
+  uint32_t* hist = w.hist.as<uint32_t>();
+  LP_HIP(hipMemsetAsync(hist, 0, 2048 * 4, st));
+  hipLaunchKernelGGL(sel_init_kernel, dim3(1), dim3(1), 0, st, sst, (const unsigned long long*)count_dev,
+                     cap, base, k);
+  LP_HIP(hipGetLastError());
+  const unsigned cus = (unsigned)num_cus();
+  const unsigned grid = cus * 4;
+  const uint32_t* in_s = cs + base;
+  const uint32_t* in_a = ca + base;
+  const uint32_t* in_c = cc + base;
+  hipLaunchKernelGGL(sel_copy_all_kernel, dim3(grid), dim3(256), 0, st, in_s, in_a, in_c, sst, os,
+                     oa, oc);
+  LP_HIP(hipGetLastError());
+  int ping = 0;
+  for (int step = 0; step < 9; step++) {
+    uint32_t* nxt_s = w.tmp_s[ping].as<uint32_t>();
+    uint32_t* nxt_a = w.tmp_a[ping].as<uint32_t>();
+    uint32_t* nxt_c = w.tmp_c[ping].as<uint32_t>();
+    hipLaunchKernelGGL(sel_hist_kernel, dim3(grid), dim3(256), 0, st, in_s, in_a, in_c, sst, step,
+                       hist);
+    hipLaunchKernelGGL(sel_pick_kernel, dim3(1), dim3(64), 0, st, sst, step, hist);
+    hipLaunchKernelGGL(sel_partition_kernel, dim3(grid), dim3(256), 0, st, in_s, in_a, in_c, sst,
+                       step, nxt_s, nxt_a, nxt_c, os, oa, oc);
+    hipLaunchKernelGGL(sel_advance_kernel, dim3(1), dim3(1), 0, st, sst, step == 8 ? 1 : 0);
+    LP_HIP(hipGetLastError());
+    in_s = nxt_s;
+    in_a = nxt_a;
+    in_c = nxt_c;
+    ping ^= 1;
+  }
+  if (tau_out) {
+    hipLaunchKernelGGL(sel_tau_kernel, dim3(1), dim3(1), 0, st, (const SelState*)sst, tau_out);
+    LP_HIP(hipGetLastError());
+  }
+  return LP_OK;
+}
+
+static lp_status ensure_select_bufs(Workspace& w, uint64_t cap) {
+  for (int i = 0; i < 2; i++) {
+    LP_TRY(w.tmp_s[i].ensure(cap * 4));
+    LP_TRY(w.tmp_a[i].ensure(cap * 4));
+    LP_TRY(w.tmp_c[i].ensure(cap * 4));
+  }
+  return LP_OK;
+}
+
+// Sort (s desc, a asc, c asc) in place; id_bits bounds the a / c words.
+static lp_status sort_keys(lp_graph* g, uint32_t* s, uint32_t* a, uint32_t* c, uint64_t k,
+                           int a_bits, int c_bits, hipStream_t st) {
+  Workspace& w = g->ws;
+  SortSpec sp{};
+  sp.w[0] = s;
+  sp.w[1] = a;
+  sp.w[2] = c;
+  sp.nwords = 3;
+  sp.nkeys = 3;
+  sp.key_bits[0] = 32;
+  sp.key_bits[1] = a_bits;
+  sp.key_bits[2] = c_bits;
+  sp.invert[0] = true;
+  sp.invert[1] = false;
+  sp.invert[2] = false;
+  return radix_sort(sp, (int64_t)k, w.sort_tmp, w.sort_counts, w.scan_tmp, st);
+}
+
+static int id_bits(uint64_t n) {
+  int b = 1;
+  while (b < 32 && ((uint64_t)1 << b) < n) b++;
+  return b;
+}
+
+struct PlanResult {
+  PlanOut out;
+  uint32_t hub;
+};
+
+static lp_status run_plan(lp_graph* g, int64_t L, PlanResult* pr, hipStream_t st) {
+  Workspace& w = g->ws;
+  const uint64_t n = (uint64_t)g->n;
+  LP_TRY(w.cnt.ensure(std::max<uint64_t>(n, 1) * 4));
+  LP_TRY(w.wedges.ensure(std::max<uint64_t>(n, 1) * 4));
+  LP_TRY(w.lists.ensure(std::max<uint64_t>(n, 1) * 4 * kBuckets));
+  LP_TRY(w.stats.ensure(sizeof(PlanOut) + 64));
+  LP_TRY(w.host_stats.ensure(4096));
+  pr->hub = hub_start(g, L);
+  PlanOut* d_out = w.stats.as<PlanOut>();
+  LP_HIP(hipMemsetAsync(d_out, 0, sizeof(PlanOut), st));
+  const AccConfig cfg = acc_config(g);
+  if (n > 0) {
+    hipLaunchKernelGGL(plan_kernel, dim3(grid_for(n, 256, 0x7FFFFFFF)), dim3(256), 0, st, view_of(g),
+                       pr->hub, cfg.lds_cap, w.cnt.as<uint32_t>(), w.wedges.as<uint32_t>(),
+                       w.lists.as<uint32_t>(), d_out);
+    LP_HIP(hipGetLastError());
+  }
+  PlanOut* h = w.host_stats.as<PlanOut>();
+  LP_HIP(hipMemcpyAsync(h, d_out, sizeof(PlanOut), hipMemcpyDeviceToHost, st));
+  LP_HIP(hipStreamSynchronize(st));
+  pr->out = *h;
+  return LP_OK;
+}
+
+struct Timer {
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  Timer() {
+    for (auto& e : ev) (void)hipEventCreate(&e);
+  }
+  ~Timer() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+  float ms(int a, int b) {
+    float t = 0;
+    if (hipEventElapsedTime(&t, ev[a], ev[b]) != hipSuccess) {
+      (void)hipGetLastError();
+      return 0;
+    }
+    return t;
+  }
+};
+
+static lp_status ensure_ovf(Workspace& w, uint32_t** ovf, uint32_t** ovf_count, uint32_t* cap,
+                            uint32_t** err, unsigned long long** count, unsigned long long** fp,
+                            uint32_t** tau, hipStream_t st) {
+  const uint32_t ocap = 1u << 16;
+  LP_TRY(w.counters.ensure(4096 + (size_t)ocap * 8));
+  char* base = w.counters.as<char>();
+  *count = reinterpret_cast<unsigned long long*>(base);   // [0]
+  *fp = reinterpret_cast<unsigned long long*>(base + 64);  // [3]
+  *ovf_count = reinterpret_cast<uint32_t*>(base + 128);
+  *err = reinterpret_cast<uint32_t*>(base + 192);
+  *tau = reinterpret_cast<uint32_t*>(base + 256);          // [3]
+  *ovf = reinterpret_cast<uint32_t*>(base + 4096);
+  *cap = ocap;
+  LP_HIP(hipMemsetAsync(base, 0, 4096, st));
+  return LP_OK;
+}
+
+// number of buffer entries whose key is >= tau
+__global__ __launch_bounds__(256) void count_ge_kernel(const uint32_t* __restrict__ ks,
+                                                       const uint32_t* __restrict__ ka,
+                                                       const uint32_t* __restrict__ kc,
+                                                       unsigned long long n, const uint32_t* tau,
+                                                       unsigned long long* out) {
+  const uint32_t t0 = tau[0], t1 = tau[1], t2 = tau[2];
+  unsigned long long c = 0;
+  for (unsigned long long i = (unsigned long long)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (unsigned long long)gridDim.x * 256) {
+    const uint32_t s = ks[i], a = ~ka[i], x = ~kc[i];
+    c += (s > t0 || (s == t0 && (a > t1 || (a == t1 && x >= t2)))) ? 1ull : 0ull;
+  }
+  for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o);
+  if (lane_id() == 0 && c) atomicAdd(out, c);
+}
+
+lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int32_t* out_a,
+                      int32_t* out_c, float* out_score, int64_t* out_count, hipStream_t st) {
+  Workspace& w = g->ws;
+  lp_stats& S = g->last;
+  S = lp_stats{};
+  *out_count = 0;
+  Timer tm;
+  LP_HIP(hipEventRecord(tm.ev[0], st));
+  PlanResult pr;
+  LP_TRY(run_plan(g, L, &pr, st));
+  LP_HIP(hipEventRecord(tm.ev[1], st));
+  S.wedges = pr.out.wedges;
+  S.sources = pr.out.sources;
+  for (int b = 0; b < kBuckets; b++) S.bucket_sources[b] = pr.out.count[b];
+  const GView gv = view_of(g);
+  uint32_t *ovf, *ovf_count, *err, *tau;
+  unsigned long long *count, *fp;
+  uint32_t ovf_cap;
+  LP_TRY(ensure_ovf(w, &ovf, &ovf_count, &ovf_cap, &err, &count, &fp, &tau, st));
+  if (k == 0 || pr.out.wedges == 0 || g->n == 0) {
+    LP_HIP(hipEventRecord(tm.ev[2], st));
+    LP_HIP(hipEventRecord(tm.ev[3], st));
+    LP_HIP(hipStreamSynchronize(st));
+    S.ms_plan = tm.ms(0, 1);
+    S.ms_total = tm.ms(0, 3);
+    return LP_OK;
+  }
+  const uint64_t total_w = pr.out.wedges;
+  const uint64_t budget = g->tuning.sample_budget > 0 ? (uint64_t)g->tuning.sample_budget
+                                                      : (g->tuning.sample_budget < 0 ? 0 : (1ull << 24));
+  // Sampling pays off only when candidates far outnumber k: a sampled subset
+  // of sources (every stride-th of each bucket) is scored first, without a
+  // threshold; tau is then a lower bound of its r-th best key with
+  // r = 1.5 k / stride, and the remaining sources only keep keys >= tau.
+  const bool sample = budget > 0 && total_w > budget && total_w > 8ull * (uint64_t)k;
+  uint32_t stride = 1;
+  if (sample) {
+    const uint64_t s = (total_w + budget - 1) / budget;
+    stride = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(s, 2), 1u << 20);
+  }
+  uint64_t cap = sample ? 2 * (total_w / stride) + 4 * (uint64_t)k + (1u << 20) : total_w;
+  cap = std::min<uint64_t>(cap, total_w);
+  cap = std::min<uint64_t>(cap, (1ull << 32) - 1);
+  const uint64_t kcap = std::min<uint64_t>((uint64_t)k, cap);
+  LP_TRY(w.cand_s.ensure(cap * 4));
+  LP_TRY(w.cand_a.ensure(cap * 4));
+  LP_TRY(w.cand_c.ensure(cap * 4));
+  LP_TRY(ensure_select_bufs(w, cap));
+  LP_TRY(w.q_out.ensure(kcap * 12 + 64));
+  LP_TRY(w.q_cnt.ensure(cap * 12 + 64));  // outputs of the threshold selections
+  uint32_t* os = w.q_out.as<uint32_t>();
+  uint32_t* oa = os + kcap;
+  uint32_t* oc = oa + kcap;
+  uint32_t* ts = w.q_cnt.as<uint32_t>();
+  uint32_t* ta = ts + cap;
+  uint32_t* tc = ta + cap;
+  Emit E{};
+  E.measure = m;
+  E.shift = g->fixed_shift;
+  E.s_th = s_th;
+  E.tau = tau;
+  E.out_s = w.cand_s.as<uint32_t>();
+  E.out_a = w.cand_a.as<uint32_t>();
+  E.out_c = w.cand_c.as<uint32_t>();
+  E.out_count = count;
+  E.cap = cap;
+  E.fp = fp;
+  E.ovf = ovf;
+  E.ovf_count = ovf_count;
+  E.ovf_cap = ovf_cap;
+  E.err = err;
+  const uint32_t* lists = w.lists.as<uint32_t>();
+  const uint32_t* cnt = w.cnt.as<uint32_t>();
+  const uint32_t* wed = w.wedges.as<uint32_t>();
+  uint32_t ovf_host = 0;
+  unsigned long long n_sample = 0;
+  if (sample) {
+    LP_TRY(run_phase_any<false>(g, gv, E, cnt, wed, nullptr, lists, (uint64_t)g->n, pr.out.count,
+                                stride, 1, &ovf_host, st));
+    LP_HIP(hipMemcpyAsync(&n_sample, count, 8, hipMemcpyDeviceToHost, st));
+    LP_HIP(hipStreamSynchronize(st));
+    if (n_sample > cap) return set_error(LP_ERR_OUT_OF_MEMORY, "sample exceeded its buffer");
+  }
+  unsigned long long r_target =
+      (unsigned long long)std::ceil(1.5 * (double)k / (double)stride) + 64;
+  bool need_tau = sample;
+  for (uint64_t retries = 0;; retries++) {
+    if (retries > 40) return set_error(LP_ERR_DEVICE, "top-k threshold did not converge");
+    if (sample) {
+      LP_HIP(hipMemcpyAsync(count, &n_sample, 8, hipMemcpyHostToDevice, st));
+      if (need_tau) {
+        if (r_target >= n_sample) LP_HIP(hipMemsetAsync(tau, 0, 12, st));
+        else
+          LP_TRY(run_select(g, E.out_s, E.out_a, E.out_c, count, cap, 0, r_target, ts, ta, tc, tau, st));
+      }
+      LP_TRY(run_phase_any<false>(g, gv, E, cnt, wed, nullptr, lists, (uint64_t)g->n, pr.out.count,
+                                  stride, 2, &ovf_host, st));
+    } else {
+      LP_TRY(run_phase_any<false>(g, gv, E, cnt, wed, nullptr, lists, (uint64_t)g->n, pr.out.count,
+                                  1, 0, &ovf_host, st));
+    }
+    if (retries == 0) LP_HIP(hipEventRecord(tm.ev[2], st));
+    unsigned long long n_total = 0;
+    uint32_t tau_h[3] = {0, 0, 0};
+    LP_HIP(hipMemcpyAsync(&n_total, count, 8, hipMemcpyDeviceToHost, st));
+    LP_HIP(hipMemcpyAsync(tau_h, tau, 12, hipMemcpyDeviceToHost, st));
+    LP_HIP(hipStreamSynchronize(st));
+    if (n_total > cap) {
+      if (!sample)
+        return set_error(LP_ERR_OUT_OF_MEMORY, "candidate buffer overflow (%llu > %llu)",
+                         (unsigned long long)n_total, (unsigned long long)cap);
+      // the buffer holds >= k real candidates: its k-th best key is a safe tau
+      LP_TRY(run_select(g, E.out_s, E.out_a, E.out_c, count, cap, 0, (unsigned long long)k, ts, ta,
+                        tc, tau, st));
+      need_tau = false;
+      continue;
+    }
+    const bool tau_zero = (tau_h[0] | tau_h[1] | tau_h[2]) == 0;
+    if (!tau_zero) {
+      // every candidate >= tau is in the buffer; the answer is there iff
+      // at least k of them are
+      unsigned long long* ge = fp;  // scratch counter
+      LP_HIP(hipMemsetAsync(ge, 0, 8, st));
+      hipLaunchKernelGGL(count_ge_kernel, dim3(grid_for(n_total, 256, num_cus() * 4)), dim3(256), 0,
+                         st, E.out_s, E.out_a, E.out_c, n_total, (const uint32_t*)tau, ge);
+      LP_HIP(hipGetLastError());
+      unsigned long long nge = 0;
+      LP_HIP(hipMemcpyAsync(&nge, ge, 8, hipMemcpyDeviceToHost, st));
+      LP_HIP(hipStreamSynchronize(st));
+      if (nge < (unsigned long long)k) {
+        r_target = r_target >= n_sample / 4 ? n_sample : r_target * 4;
+        need_tau = true;
+        continue;
+      }
+    }
+    S.appended = n_total;
+    S.retries = retries;
+    LP_TRY(run_select(g, E.out_s, E.out_a, E.out_c, count, cap, 0, (unsigned long long)k, os, oa, oc,
+                      nullptr, st));
+    SelState hs;
+    LP_HIP(hipMemcpyAsync(&hs, w.sel_state.p, sizeof(SelState), hipMemcpyDeviceToHost, st));
+    LP_HIP(hipStreamSynchronize(st));
+    const uint64_t kout = hs.n_out;
+    if (kout != std::min<uint64_t>((uint64_t)k, n_total))
+      return set_error(LP_ERR_DEVICE, "selection returned %llu of %llu keys",
+                       (unsigned long long)kout, (unsigned long long)std::min<uint64_t>(k, n_total));
+    LP_TRY(sort_keys(g, os, oa, oc, kout, id_bits((uint64_t)g->n), id_bits((uint64_t)g->n), st));
+    LP_HIP(hipEventRecord(tm.ev[3], st));
+    hipPointerAttribute_t at;
+    const bool dev_out =
+        hipPointerGetAttributes(&at, out_a) == hipSuccess && at.type == hipMemoryTypeDevice &&
+        hipPointerGetAttributes(&at, out_c) == hipSuccess && at.type == hipMemoryTypeDevice &&
+        hipPointerGetAttributes(&at, out_score) == hipSuccess && at.type == hipMemoryTypeDevice;
+    (void)hipGetLastError();
+    if (kout > 0) {
+      if (dev_out) {
+        hipLaunchKernelGGL(write_out_kernel, dim3(grid_for(kout, 256, 65536)), dim3(256), 0, st, os,
+                           oa, oc, (unsigned long long)kout, out_a, out_c, out_score);
+        LP_HIP(hipGetLastError());
+      } else {
+        int32_t* xa = reinterpret_cast<int32_t*>(ts);
+        int32_t* xc = xa + kout;
+        float* xs = reinterpret_cast<float*>(xc + kout);
+        hipLaunchKernelGGL(write_out_kernel, dim3(grid_for(kout, 256, 65536)), dim3(256), 0, st, os,
+                           oa, oc, (unsigned long long)kout, xa, xc, xs);
+        LP_HIP(hipGetLastError());
+        LP_HIP(hipMemcpyAsync(out_a, xa, kout * 4, hipMemcpyDefault, st));
+        LP_HIP(hipMemcpyAsync(out_c, xc, kout * 4, hipMemcpyDefault, st));
+        LP_HIP(hipMemcpyAsync(out_score, xs, kout * 4, hipMemcpyDefault, st));
+      }
+    }
+    uint32_t herr = 0;
+    LP_HIP(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, st));
+    LP_HIP(hipStreamSynchronize(st));
+    if (herr) return set_error(LP_ERR_DEVICE, "device error flags 0x%x", herr);
+    *out_count = (int64_t)kout;
+    S.ms_plan = tm.ms(0, 1);
+    S.ms_accumulate = tm.ms(1, 2);
+    S.ms_select = tm.ms(2, 3);
+    S.ms_total = tm.ms(0, 3);
+    return LP_OK;
+  }
+}
+
+lp_status run_fingerprint(lp_graph* g, int64_t L, uint64_t* out, hipStream_t st) {
+  Workspace& w = g->ws;
+  lp_stats& S = g->last;
+  S = lp_stats{};
+  PlanResult pr;
+  LP_TRY(run_plan(g, L, &pr, st));
+  S.wedges = pr.out.wedges;
+  S.sources = pr.out.sources;
+  for (int b = 0; b < kBuckets; b++) S.bucket_sources[b] = pr.out.count[b];
+  uint32_t *ovf, *ovf_count, *err, *tau;
+  unsigned long long *count, *fp;
+  uint32_t ovf_cap;
+  LP_TRY(ensure_ovf(w, &ovf, &ovf_count, &ovf_cap, &err, &count, &fp, &tau, st));
+  Emit E{};
+  E.measure = LP_CN;
+  E.shift = g->fixed_shift;
+  E.s_th = 0;
+  E.tau = tau;
+  E.out_count = count;
+  E.fp_mode = 1;
+  E.fp = fp;
+  E.ovf = ovf;
+  E.ovf_count = ovf_count;
+  E.ovf_cap = ovf_cap;
+  E.err = err;
+  uint32_t ovf_host = 0;
+  if (pr.out.wedges)
+    LP_TRY(run_phase_any<false>(g, view_of(g), E, w.cnt.as<uint32_t>(), w.wedges.as<uint32_t>(),
+                                nullptr, w.lists.as<uint32_t>(), (uint64_t)g->n, pr.out.count, 1, 0,
+                                &ovf_host, st));
+  unsigned long long h[3];
+  uint32_t herr = 0;
+  LP_HIP(hipMemcpyAsync(h, fp, 24, hipMemcpyDeviceToHost, st));
+  LP_HIP(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, st));
+  LP_HIP(hipStreamSynchronize(st));
+  if (herr) return set_error(LP_ERR_DEVICE, "device error flags 0x%x", herr);
+  out[0] = h[0];
+  out[1] = h[1];
+  out[2] = h[2];
+  out[3] = pr.out.wedges;
+  return LP_OK;
+}
+
+lp_status run_query(lp_graph* g, const int32_t* sources, int64_t nq, int m, int64_t L, int32_t kq,
+                    float s_th, int32_t* out_c, float* out_score, int32_t* out_count,
+                    hipStream_t st) {
+  Workspace& w = g->ws;
+  if (nq == 0) return LP_OK;
+  const uint64_t Q = (uint64_t)nq;
+  // sources to device (validated on the host side by the caller)
+  LP_TRY(w.q_src.ensure(Q * 4));
+  LP_HIP(hipMemcpyAsync(w.q_src.p, sources, Q * 4, hipMemcpyDefault, st));
+  // per query: new id, explored arcs, wedge bound; bucket lists over query indices
+  LP_TRY(w.q_rows.ensure(Q * 4 * (3 + kBuckets) + 256));
+  uint32_t* qnew = w.q_rows.as<uint32_t>();
+  uint32_t* qcnt = qnew + Q;
+  uint32_t* qwed = qcnt + Q;
+  uint32_t* qlists = qwed + Q;
+  LP_TRY(w.stats.ensure(sizeof(PlanOut) + 64));
+  LP_TRY(w.host_stats.ensure(4096));
+  PlanOut* d_out = w.stats.as<PlanOut>();
+  LP_HIP(hipMemsetAsync(d_out, 0, sizeof(PlanOut), st));
+  const uint32_t hub = hub_start(g, L);
+  const AccConfig cfg = acc_config(g);
+  const GView gv = view_of(g);
+  hipLaunchKernelGGL(query_plan_kernel, dim3(grid_for(Q, 1, 65536)), dim3(256), 0, st, gv, hub,
+                     cfg.lds_cap, w.q_src.as<int32_t>(), g->rank, (uint32_t)Q, qnew, qcnt, qwed,
+                     qlists, d_out);
+  LP_HIP(hipGetLastError());
+  PlanOut* hp = w.host_stats.as<PlanOut>();
+  LP_HIP(hipMemcpyAsync(hp, d_out, sizeof(PlanOut), hipMemcpyDeviceToHost, st));
+  LP_HIP(hipStreamSynchronize(st));
+  const PlanOut po = *hp;
+  if (po.bad_source) return set_error(LP_ERR_INVALID_ARGUMENT, "a source id is outside [0, n)");
+  uint64_t cap = std::max<uint64_t>(po.wedges, 1);
+  if (cap > (1ull << 32) - 1) return set_error(LP_ERR_OUT_OF_MEMORY, "query batch too large");
+  LP_TRY(w.cand_s.ensure(cap * 4));
+  LP_TRY(w.cand_a.ensure(cap * 4));
+  LP_TRY(w.cand_c.ensure(cap * 4));
+  LP_TRY(w.q_cnt.ensure(Q * 8 + 64));
+  uint32_t* seg_count = w.q_cnt.as<uint32_t>();
+  uint32_t* seg_start = seg_count + Q;
+  LP_HIP(hipMemsetAsync(seg_count, 0, Q * 4, st));
+  uint32_t *ovf, *ovf_count, *err, *tau;
+  unsigned long long *count, *fp;
+  uint32_t ovf_cap;
+  LP_TRY(ensure_ovf(w, &ovf, &ovf_count, &ovf_cap, &err, &count, &fp, &tau, st));
+  Emit E{};
+  E.measure = m;
+  E.shift = g->fixed_shift;
+  E.s_th = s_th;
+  E.tau = tau;
+  E.out_s = w.cand_s.as<uint32_t>();
+  E.out_a = w.cand_a.as<uint32_t>();
+  E.out_c = w.cand_c.as<uint32_t>();
+  E.out_count = count;
+  E.cap = cap;
+  E.q_count = seg_count;
+  E.fp = fp;
+  E.ovf = ovf;
+  E.ovf_count = ovf_count;
+  E.ovf_cap = ovf_cap;
+  E.err = err;
+  uint32_t ovf_host = 0;
+  if (po.wedges)
+    LP_TRY(run_phase_any<true>(g, gv, E, qcnt, qwed, qnew, qlists, Q, po.count, 1, 0, &ovf_host, st));
+  unsigned long long n_total = 0;
+  LP_HIP(hipMemcpyAsync(&n_total, count, 8, hipMemcpyDeviceToHost, st));
+  LP_HIP(hipStreamSynchronize(st));
+  if (n_total > cap) return set_error(LP_ERR_DEVICE, "query candidate overflow");
+  // sort by (query index asc, score desc, c asc)
+  if (n_total > 1) {
+    SortSpec sp{};
+    sp.w[0] = E.out_a;
+    sp.w[1] = E.out_s;
+    sp.w[2] = E.out_c;
+    sp.nwords = 3;
+    sp.nkeys = 3;
+    sp.key_bits[0] = id_bits(Q);
+    sp.key_bits[1] = 32;
+    sp.key_bits[2] = id_bits((uint64_t)g->n);
+    sp.invert[0] = false;
+    sp.invert[1] = true;
+    sp.invert[2] = false;
+    LP_TRY(radix_sort(sp, (int64_t)n_total, w.sort_tmp, w.sort_counts, w.scan_tmp, st));
+  }
+  LP_TRY(scan_exclusive_u32(seg_count, seg_start, (int64_t)Q, w.scan_tmp, st));
+  // outputs (device or host)
+  hipPointerAttribute_t at;
+  bool dev_out = hipPointerGetAttributes(&at, out_c) == hipSuccess && at.type == hipMemoryTypeDevice &&
+                 hipPointerGetAttributes(&at, out_score) == hipSuccess && at.type == hipMemoryTypeDevice &&
+                 hipPointerGetAttributes(&at, out_count) == hipSuccess && at.type == hipMemoryTypeDevice;
+  (void)hipGetLastError();
+  const uint64_t tot = Q * (uint64_t)kq;
+  int32_t* dc = out_c;
+  float* ds = out_score;
+  int32_t* dn = out_count;
+  if (!dev_out) {
+    LP_TRY(w.sort_tmp[0].ensure(tot * 8 + Q * 4 + 64));
+    dc = w.sort_tmp[0].as<int32_t>();
+    ds = reinterpret_cast<float*>(dc + tot);
+    dn = reinterpret_cast<int32_t*>(ds + tot);
+  }
+  hipLaunchKernelGGL(query_take_kernel, dim3(grid_for(tot, 256, 65536)), dim3(256), 0, st,
+                     E.out_s, E.out_c, seg_start, seg_count, (uint32_t)Q, kq, dc, ds, dn);
+  LP_HIP(hipGetLastError());
+  if (!dev_out) {
+    LP_HIP(hipMemcpyAsync(out_c, dc, tot * 4, hipMemcpyDefault, st));
+    LP_HIP(hipMemcpyAsync(out_score, ds, tot * 4, hipMemcpyDefault, st));
+    LP_HIP(hipMemcpyAsync(out_count, dn, Q * 4, hipMemcpyDefault, st));
+  }
+  uint32_t herr = 0;
+  LP_HIP(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, st));
+  LP_HIP(hipStreamSynchronize(st));
+  if (herr) return set_error(LP_ERR_DEVICE, "device error flags 0x%x", herr);
+  return LP_OK;
+}
+
+}  // namespace lp

@@ -1,0 +1,288 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Every case prints its name before touching the device.  Inputs are seeded
+synthetic graphs from ``synth``; expected values come from ``oracle`` only."""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from lpcheck import (EXACT_MEASURES, assert_same_candidates, assert_same_list, assert_same_query,
+                     assert_sorted_unique, assert_topk_acceptance, say, to_np)
+
+pytestmark = pytest.mark.gpu
+
+MEAS = oracle.MEASURES
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def lp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2401_11415_amd as m
+    m.load()
+    return m
+
+
+def run_predict(lp, g, m, L, k, s_th=0.0, host=False):
+    if host:
+        out = (np.zeros(max(k, 1), np.int32), np.zeros(max(k, 1), np.int32),
+               np.zeros(max(k, 1), np.float32))
+        a, c, s = lp.predict(g, m, L, k, s_th, out=out)
+        return a, c, s
+    a, c, s = lp.predict(g, m, L, k, s_th)
+    return to_np(a), to_np(c), to_np(s)
+
+
+def total_candidates(gr, L):
+    return oracle.fingerprint(gr, L)[0]
+
+
+CLOSED = {
+    "star": (6, [(0, i) for i in range(1, 6)]),
+    "path": (6, [(i, i + 1) for i in range(5)]),
+    "k34": (7, [(a, b) for a in range(3) for b in range(3, 7)]),
+    "c4": (4, [(0, 1), (1, 2), (2, 3), (3, 0)]),
+    "k5": (5, list(itertools.combinations(range(5), 2))),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CLOSED))
+def test_closed_forms(lp, name):
+    n, edges = CLOSED[name]
+    gr = synth.from_edges(n, edges)
+    say(f"[gpu] closed form {name}")
+    with lp.Graph(gr.offsets, gr.indices, validate=True) as g:
+        for m in MEAS:
+            for L in (None, 1, 2, 3, 4, 5):
+                bf = oracle.bruteforce(gr, L, m)
+                got = run_predict(lp, g, m, L, 100)
+                assert_same_candidates(got, bf, m, f"{name}/{m}/L={L}")
+
+
+def test_worked_example(lp):
+    path = os.path.join(HERE, "golden", "worked_example_dlh.txt")
+    n, edges, sets = None, [], {}
+    for line in open(path):
+        line = line.split("#")[0].strip()
+        if not line:
+            continue
+        t = line.split()
+        if t[0] == "n":
+            n = int(t[1])
+        elif t[0] == "edges":
+            edges = [tuple(int(x) for x in e.split("-")) for e in t[1:]]
+        elif t[0] == "second_order":
+            sets[None if t[1] == "inf" else int(t[1])] = {int(x) for x in t[2:]}
+    gr = synth.from_edges(n, edges)
+    say("[gpu] worked example")
+    with lp.Graph(gr.offsets, gr.indices, validate=True) as g:
+        for L, want in sets.items():
+            c, s, cnt = lp.query(g, [1], "CN", L, 100)
+            got = set(to_np(c)[0][: int(cnt[0])].tolist())
+            assert got == want, (L, got, want)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+@pytest.mark.parametrize("kind", ["er", "cl"])
+def test_random_graphs_all_candidates(lp, seed, kind):
+    gr = synth.random_graph(150, 0.06, seed) if kind == "er" else synth.chung_lu(3000, 10.0, 2.2, seed)
+    say(f"[gpu] random {kind} seed={seed} n={gr.n} m={gr.m}")
+    with lp.Graph(gr.offsets, gr.indices, validate=True) as g:
+        for L in (2, 8, 64, None):
+            tot = total_candidates(gr, L)
+            for m in MEAS:
+                ref = oracle.predict(gr, L, m, tot + 5)
+                got = run_predict(lp, g, m, L, tot + 5)
+                assert_same_list(got, ref, m, f"{kind}{seed}/{m}/L={L}")
+
+
+@pytest.fixture(scope="module")
+def config1():
+    g = synth.chung_lu_10k(1)
+    obs, held = synth.holdout(g, 0.1, 1)
+    return obs, held.shape[0]
+
+
+@pytest.mark.parametrize("L", [256, None])
+def test_config1_jaccard_topk(lp, config1, L):
+    gr, k = config1
+    say(f"[gpu] config1 JC L={L} k={k}")
+    ref = oracle.predict(gr, L, "JC", k)
+    with lp.Graph(gr.offsets, gr.indices) as g:
+        got = run_predict(lp, g, "JC", L, k)
+        assert_same_list(got, ref, "JC", f"config1/JC/L={L}")
+        st = lp.last_stats(g)
+        assert st["wedges"] == oracle.wedges(gr, L)
+
+
+@pytest.mark.parametrize("m", MEAS)
+def test_config1_measures(lp, config1, m):
+    gr, k = config1
+    say(f"[gpu] config1 {m} L=256")
+    with lp.Graph(gr.offsets, gr.indices) as g:
+        for L in (32, 256):
+            ref = oracle.predict(gr, L, m, k)
+            got = run_predict(lp, g, m, L, k)
+            assert_same_list(got, ref, m, f"config1/{m}/L={L}")
+
+
+@pytest.mark.parametrize("L", [0, 1, 2, 16, 256, None])
+def test_config1_fingerprint(lp, config1, L):
+    gr, _ = config1
+    say(f"[gpu] config1 fingerprint L={L}")
+    with lp.Graph(gr.offsets, gr.indices) as g:
+        assert lp.fingerprint(g, L) == oracle.fingerprint(gr, L)
+
+
+def test_global_path_and_partitions(lp, config1):
+    """Force the dense global accumulator (tiny LDS cap), and exercise hash
+    partitions with a graph whose sources own > 8192 wedges."""
+    gr, k = config1
+    say("[gpu] forced global path")
+    with lp.Graph(gr.offsets, gr.indices) as g:
+        for cap in (1, 40, 300):
+            lp.set_tuning(g, lds_wedge_cap=cap)
+            for m in ("JC", "RA"):
+                ref = oracle.predict(gr, 256, m, k)
+                got = run_predict(lp, g, m, 256, k)
+                assert_same_list(got, ref, m, f"cap={cap}/{m}")
+            assert lp.fingerprint(g, None) == oracle.fingerprint(gr, None)
+            st = lp.last_stats(g)
+            assert st["bucket_sources"][4] > 0
+    say("[gpu] hash partitions K_{5,4000}")
+    kb = synth.from_edges(4005, [(h, 5 + i) for h in range(5) for i in range(4000)])
+    with lp.Graph(kb.offsets, kb.indices) as g:
+        for m in ("JC", "AA", "CN"):
+            ref = oracle.predict(kb, None, m, 3000)
+            got = run_predict(lp, g, m, None, 3000)
+            assert_same_list(got, ref, m, f"K5,4000/{m}")
+        assert lp.fingerprint(g, None) == oracle.fingerprint(kb, None)
+        st = lp.last_stats(g)
+        assert st["bucket_sources"][3] > 0
+
+
+def test_sampled_threshold_path(lp, config1):
+    """The top-k threshold estimated from a sample, including its retries."""
+    gr, k = config1
+    say("[gpu] sampled threshold")
+    with lp.Graph(gr.offsets, gr.indices) as g:
+        for budget in (20000, 200000):
+            lp.set_tuning(g, sample_budget=budget)
+            for m in ("JC", "CN", "AA", "LHN"):
+                for kk in (50, k, 3 * k):
+                    ref = oracle.predict(gr, 256, m, kk)
+                    got = run_predict(lp, g, m, 256, kk)
+                    assert_same_list(got, ref, m, f"budget={budget}/{m}/k={kk}")
+
+
+@pytest.mark.parametrize("m", ["JC", "SC", "AA", "RA", "HP"])
+def test_query(lp, config1, m):
+    gr, _ = config1
+    src = synth.sample_sources(gr, 60, seed=3, top=6)
+    src = np.concatenate([src, src[:3]])  # repeats are allowed
+    say(f"[gpu] query {m} ns={src.shape[0]}")
+    with lp.Graph(gr.offsets, gr.indices) as g:
+        for L, kq in ((256, 10), (None, 7), (256, 20000)):
+            ref = oracle.query(gr, L, m, src, kq)
+            c, s, cnt = lp.query(g, src, m, L, kq)
+            c, s, cnt = to_np(c), to_np(s), to_np(cnt)
+            for i in range(src.shape[0]):
+                row = (c[i][: cnt[i]], s[i][: cnt[i]])
+                assert_same_query(row, ref[i], m, f"query {m} L={L} src={src[i]}")
+
+
+def test_query_global_path(lp, config1):
+    gr, _ = config1
+    src = synth.sample_sources(gr, 20, seed=5, top=4)
+    say("[gpu] query global path")
+    with lp.Graph(gr.offsets, gr.indices) as g:
+        lp.set_tuning(g, lds_wedge_cap=64)
+        for m in ("JC", "AA"):
+            ref = oracle.query(gr, None, m, src, 50)
+            c, s, cnt = lp.query(g, src, m, None, 50)
+            c, s, cnt = to_np(c), to_np(s), to_np(cnt)
+            for i in range(src.shape[0]):
+                assert_same_query((c[i][: cnt[i]], s[i][: cnt[i]]), ref[i], m, f"q-global {m}")
+
+
+def test_determinism(lp, config1):
+    gr, k = config1
+    say("[gpu] determinism")
+    with lp.Graph(gr.offsets, gr.indices) as g:
+        for m in ("JC", "AA"):
+            r1 = run_predict(lp, g, m, 256, k)
+            r2 = run_predict(lp, g, m, 256, k)
+            for x, y in zip(r1, r2):
+                assert np.array_equal(x, y)
+
+
+def test_edge_cases(lp, config1):
+    gr, k = config1
+    say("[gpu] edge cases")
+    with lp.Graph(gr.offsets, gr.indices) as g:
+        a, c, s = run_predict(lp, g, "JC", 256, 0)
+        assert a.shape[0] == 0
+        for L in (0, 1):
+            a, c, s = run_predict(lp, g, "CN", L, 100)
+            assert a.shape[0] == 0
+        # threshold: strictly above
+        ref = oracle.predict(gr, 256, "JC", k, 0.25)
+        got = run_predict(lp, g, "JC", 256, k, 0.25)
+        assert_same_list(got, ref, "JC", "s_th=0.25")
+        assert np.all(got[2] > 0.25)
+        # host output pointers
+        ref = oracle.predict(gr, 256, "SC", 500)
+        got = run_predict(lp, g, "SC", 256, 500, host=True)
+        assert_same_list(got, ref, "SC", "host outputs")
+        # more than all candidates
+        tot = total_candidates(gr, 16)
+        ref = oracle.predict(gr, 16, "HD", tot + 1000)
+        got = run_predict(lp, g, "HD", 16, tot + 1000)
+        assert got[0].shape[0] == tot
+        assert_same_list(got, ref, "HD", "k > |C|")
+    # graphs with nothing to predict
+    for n, edges in ((0, []), (5, []), (3, [(0, 1)]), (4, [(0, 1), (2, 3)])):
+        gr0 = synth.from_edges(n, edges) if n else synth.Graph(np.zeros(1, np.int64), np.zeros(0, np.int32))
+        with lp.Graph(gr0.offsets, gr0.indices, validate=True) as g:
+            a, c, s = run_predict(lp, g, "JC", None, 10)
+            assert a.shape[0] == 0
+            assert lp.fingerprint(g, None) == (0, 0, 0, 0)
+
+
+def test_invalid_inputs(lp):
+    say("[gpu] invalid inputs")
+    good = synth.from_edges(4, [(0, 1), (1, 2), (2, 3)])
+
+    def create(off, idx, validate=True):
+        return lp.Graph(np.asarray(off, np.int64), np.asarray(idx, np.int32), validate=validate)
+
+    with pytest.raises(lp.LpError) as e:
+        create([0, 2, 1, 3], [1, 2, 0], validate=False)  # offsets decrease
+    assert e.value.name == "LP_ERR_INVALID_GRAPH"
+    with pytest.raises(lp.LpError):
+        create([0, 1, 2], [1, 7], validate=False)  # index out of range
+    with pytest.raises(lp.LpError):
+        create([0, 1, 3], [1, 0, 1])  # self loop 1-1
+    with pytest.raises(lp.LpError):
+        create([0, 2, 4, 6], [2, 1, 0, 2, 0, 1])  # unsorted row
+    with pytest.raises(lp.LpError):
+        create([0, 2, 3, 4], [1, 1, 0, 0])  # duplicate edge
+    with pytest.raises(lp.LpError):
+        create([0, 1, 1, 2], [1, 0])  # asymmetric: 0->1 but 1 has no arcs
+    with lp.Graph(good.offsets, good.indices, validate=True) as g:
+        for bad in (dict(m=9), dict(L=-1), dict(k=-1), dict(s=-0.5), dict(s=float("nan"))):
+            with pytest.raises(lp.LpError) as e:
+                lp.predict(g, bad.get("m", 1), bad.get("L", 2), bad.get("k", 5), bad.get("s", 0.0))
+            assert e.value.name == "LP_ERR_INVALID_ARGUMENT"
+        with pytest.raises(lp.LpError):
+            lp.query(g, [0, 9], "JC", 2, 5)
+        with pytest.raises(lp.LpError):
+            lp.query(g, [0], "JC", 2, 0)
+        # the graph stays usable after errors
+        a, c, s = lp.predict(g, "CN", None, 10)
+        assert to_np(a).tolist() == [0, 1] and to_np(c).tolist() == [2, 3]
