@@ -2,10 +2,13 @@
 //
 // Input: a simple undirected graph in CSR form (Section 3: G(V, E); Section
 // 5.1: 32-bit vertex ids).  The resident form relabels vertices by ascending
-// (degree, original id) and stores, for every arc a->b, where the part of row
-// b holding ids greater than a starts (Algorithm 1, scanEdges skips c <= a) and
-// the running per-row total of those suffix lengths, so that the number of
-// two-hop paths a source owns is available in O(log d) time.
+// (degree, original id), so that the explored intermediates of a source (degree
+// <= L_H, Section 4.2.1) form a prefix of its row.  For the prediction
+// orientation (Algorithm 1, scanEdges skips c <= a) it keeps a compacted
+// "two-hop arc list" per source: the arcs a->b whose row b holds some id > a,
+// with the position where that part of row b starts and the running total of
+// its lengths, so that the number of wedges a source owns for any hub limit is
+// one binary search away and no work is spent on arcs without wedges.
 #include <algorithm>
 #include <cstring>
 
@@ -159,6 +162,34 @@ __global__ void row_prefix_kernel(const uint32_t* __restrict__ off, const uint32
   }
 }
 
+__global__ void nz_flag_kernel(const uint32_t* __restrict__ suflen, int64_t arcs,
+                               uint32_t* __restrict__ flag) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p <= arcs;
+       p += (int64_t)gridDim.x * blockDim.x)
+    flag[p] = (p < arcs && suflen[p] > 0) ? 1u : 0u;
+}
+
+__global__ void nz_compact_kernel(const uint32_t* __restrict__ pos, const uint32_t* __restrict__ suflen,
+                                  const uint32_t* __restrict__ adj, const uint32_t* __restrict__ sufstart,
+                                  const uint32_t* __restrict__ psum, int64_t arcs,
+                                  uint32_t* __restrict__ hb, uint32_t* __restrict__ hstart,
+                                  uint32_t* __restrict__ hpsum) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < arcs;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    if (suflen[p] == 0) continue;
+    const uint32_t q = pos[p];
+    hb[q] = adj[p];
+    hstart[q] = sufstart[p];
+    hpsum[q] = psum[p];
+  }
+}
+
+__global__ void nz_offsets_kernel(const uint32_t* __restrict__ off, const uint32_t* __restrict__ pos,
+                                  int64_t n, uint32_t* __restrict__ hoff) {
+  int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a <= n) hoff[a] = pos[off[a]];
+}
+
 __global__ void below_kernel(const uint32_t* __restrict__ off, const uint32_t* __restrict__ adj,
                              int64_t n, uint32_t* __restrict__ below) {
   int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -180,7 +211,8 @@ uint32_t hub_start(const lp_graph* g, int64_t L) {
 }
 
 static void free_graph_arrays(lp_graph* g) {
-  uint32_t** arrs[] = {&g->off, &g->adj, &g->sufstart, &g->psum, &g->deg, &g->below, &g->perm, &g->rank};
+  uint32_t** arrs[] = {&g->off, &g->adj, &g->hoff, &g->hb, &g->hstart, &g->hpsum,
+                       &g->deg, &g->below, &g->perm, &g->rank};
   for (auto p : arrs) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
@@ -188,7 +220,7 @@ static void free_graph_arrays(lp_graph* g) {
 }
 
 struct TempBufs {
-  DevBuf b[12];
+  DevBuf b[16];
   ~TempBufs() {
     for (auto& x : b) x.release();
   }
@@ -262,9 +294,8 @@ lp_status build_graph(int64_t n, const int64_t* offsets, const int32_t* indices,
   LP_HIP(hipMalloc((void**)&g->perm, nb));
   LP_HIP(hipMalloc((void**)&g->rank, nb));
   LP_HIP(hipMalloc((void**)&g->adj, ab));
-  LP_HIP(hipMalloc((void**)&g->sufstart, ab));
-  LP_HIP(hipMalloc((void**)&g->psum, ab));
-  g->device_bytes = (int64_t)(5 * nb + 3 * ab);
+  LP_HIP(hipMalloc((void**)&g->hoff, nb));
+  g->device_bytes = (int64_t)(6 * nb + ab);
 
   // 1. degrees and the (degree, id) order
   LP_TRY(d_ids.ensure(nb));
@@ -309,15 +340,49 @@ lp_status build_graph(int64_t n, const int64_t* offsets, const int32_t* indices,
     const uint32_t* arow = d_key.as<uint32_t>();
 
     // 3. suffix starts, lengths and per-row running totals
+    DevBuf& d_sufstart = t.b[9];
+    DevBuf& d_psum = t.b[10];
+    DevBuf& d_pos = t.b[11];
     LP_TRY(d_suflen.ensure(ab));
+    LP_TRY(d_sufstart.ensure(ab));
+    LP_TRY(d_psum.ensure(ab));
     hipLaunchKernelGGL(suffix_kernel, dim3(gb), dim3(kThreads), 0, st, g->off, g->adj, arow, arcs,
-                       validate ? 1 : 0, g->sufstart, d_suflen.as<uint32_t>(), err);
+                       validate ? 1 : 0, d_sufstart.as<uint32_t>(), d_suflen.as<uint32_t>(), err);
     LP_HIP(hipGetLastError());
     LP_TRY(d_incl.ensure((size_t)arcs * 8));
     LP_TRY(scan_inclusive_u32_u64(d_suflen.as<uint32_t>(), d_incl.as<uint64_t>(), arcs, scan_tmp, st));
     hipLaunchKernelGGL(row_prefix_kernel, dim3(gb), dim3(kThreads), 0, st, g->off, arow,
-                       d_suflen.as<uint32_t>(), d_incl.as<uint64_t>(), arcs, g->psum);
+                       d_suflen.as<uint32_t>(), d_incl.as<uint64_t>(), arcs, d_psum.as<uint32_t>());
     LP_HIP(hipGetLastError());
+    // 4. keep the arcs with a non-empty suffix (order preserved)
+    LP_TRY(d_pos.ensure((size_t)(arcs + 1) * 8));
+    uint32_t* flag = d_pos.as<uint32_t>();
+    uint32_t* pos = flag + (arcs + 1);
+    hipLaunchKernelGGL(nz_flag_kernel, dim3(gb), dim3(kThreads), 0, st, d_suflen.as<uint32_t>(), arcs,
+                       flag);
+    LP_HIP(hipGetLastError());
+    LP_TRY(scan_exclusive_u32(flag, pos, arcs + 1, scan_tmp, st));
+    uint32_t H = 0;
+    LP_HIP(hipMemcpyAsync(&H, pos + arcs, 4, hipMemcpyDeviceToHost, st));
+    LP_HIP(hipStreamSynchronize(st));
+    size_t hbytes = (size_t)std::max<uint32_t>(H, 1) * 4;
+    LP_HIP(hipMalloc((void**)&g->hb, hbytes));
+    LP_HIP(hipMalloc((void**)&g->hstart, hbytes));
+    LP_HIP(hipMalloc((void**)&g->hpsum, hbytes));
+    g->device_bytes += (int64_t)(3 * hbytes);
+    g->harcs = H;
+    hipLaunchKernelGGL(nz_compact_kernel, dim3(gb), dim3(kThreads), 0, st, pos,
+                       d_suflen.as<uint32_t>(), g->adj, d_sufstart.as<uint32_t>(),
+                       d_psum.as<uint32_t>(), arcs, g->hb, g->hstart, g->hpsum);
+    LP_HIP(hipGetLastError());
+    hipLaunchKernelGGL(nz_offsets_kernel, dim3(blocks_for(n + 1)), dim3(kThreads), 0, st, g->off, pos,
+                       n, g->hoff);
+    LP_HIP(hipGetLastError());
+  } else {
+    LP_HIP(hipMemsetAsync(g->hoff, 0, nb, st));
+    LP_HIP(hipMalloc((void**)&g->hb, 4));
+    LP_HIP(hipMalloc((void**)&g->hstart, 4));
+    LP_HIP(hipMalloc((void**)&g->hpsum, 4));
   }
   if (n > 0) {
     hipLaunchKernelGGL(below_kernel, dim3(blocks_for(n)), dim3(kThreads), 0, st, g->off, g->adj, n,

@@ -14,8 +14,10 @@ constexpr uint32_t kHashMul = 0x9E3779B1u;            // Fibonacci hashing multi
 struct GView {
   const uint32_t* off;
   const uint32_t* adj;
-  const uint32_t* sufstart;
-  const uint32_t* psum;
+  const uint32_t* hoff;    // two-hop arc list (arcs with wedges c > a)
+  const uint32_t* hb;
+  const uint32_t* hstart;
+  const uint32_t* hpsum;
   const uint32_t* deg;
   const uint32_t* below;
   const uint32_t* perm;
@@ -86,19 +88,64 @@ struct FpAcc {
   unsigned long long cnt = 0, sh = 0, sm = 0;
 };
 
-// Score one (source, c) entry and append it if it survives S_th and tau.
-// Must be called by every active lane of the wave at the same point (the
-// append is aggregated with a ballot); lanes with valid == false pass through.
+// Per-wave staging of surviving candidates in LDS: survivors are collected
+// here and copied to the global buffer with one atomic per flush, instead of
+// one device-scope atomic per (wave, sweep step) with any survivor.
+struct Stage {
+  uint32_t* s;    // [cap] score bits
+  uint32_t* a;    // [cap]
+  uint32_t* c;    // [cap]
+  uint32_t* cnt;  // entries held (one LDS word per wave)
+  uint32_t cap;
+};
+
+// The staged count is shared by the lanes of a wave through LDS: atomic
+// accesses keep the compiler from reusing a lane's own stale copy.
+__device__ inline uint32_t stage_count(const Stage& S) {
+  return __hip_atomic_load(S.cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+__device__ inline void stage_set_count(const Stage& S, uint32_t v) {
+  __hip_atomic_store(S.cnt, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+// Copy the staged entries out; callable with any set of active lanes.
+__device__ inline void stage_flush(const Emit& E, const Stage& S) {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  const uint32_t n = stage_count(S);
+  if (n == 0) return;
+  const uint64_t act = __ballot(true);
+  const int leader = __ffsll((unsigned long long)act) - 1;
+  const uint32_t nact = (uint32_t)__popcll(act);
+  const uint32_t ar = (uint32_t)__popcll(act & lanemask_lt());
+  unsigned long long base = 0;
+  if (lane_id() == leader) base = atomicAdd(E.out_count, (unsigned long long)n);
+  base = __shfl(base, leader);
+  for (uint32_t j = ar; j < n; j += nact) {
+    const unsigned long long pos = base + j;
+    if (pos < E.cap) {
+      E.out_s[pos] = S.s[j];
+      E.out_a[pos] = S.a[j];
+      E.out_c[pos] = S.c[j];
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  if (lane_id() == leader) stage_set_count(S, 0u);
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+}
+
+// Score one (source, c) entry and stage it if it survives S_th and tau.
+// Must be called by every active lane of the wave at the same point (ranks
+// come from a ballot); lanes with valid == false pass through.
 //   kQuery: a_key = query index, the pair is (source, c) ordered by c only.
+//   dc: degree of c (needed by the normalised measures), loaded by the caller.
 template <bool kQuery>
-__device__ inline void emit_one(const Emit& E, const GView& g, bool valid, uint32_t a_orig,
-                                uint32_t a_key, uint32_t da, uint32_t c, uint32_t h, uint64_t wsum,
-                                FpAcc& fa) {
+__device__ inline void emit_one(const Emit& E, const GView& g, const Stage& S, bool valid,
+                                uint32_t a_orig, uint32_t a_key, uint32_t da, uint32_t c,
+                                uint32_t dc, uint32_t h, uint64_t wsum, FpAcc& fa) {
   bool keep = false;
   uint32_t sb = 0, ka = 0, kc = 0;
   bool have_ids = false;
   if (valid) {
-    const uint32_t dc = needs_dc(E.measure) ? g.deg[c] : 0u;
     const double s = score_of(E.measure, h, wsum, da, dc, E.shift);
     const float f = (float)s;
     sb = __float_as_uint(f);
@@ -134,10 +181,9 @@ __device__ inline void emit_one(const Emit& E, const GView& g, bool valid, uint3
   if (E.fp_mode) return;
   const uint64_t m = __ballot(keep);
   if (m == 0) return;
-  const int leader = __ffsll((unsigned long long)m) - 1;
-  unsigned long long base = 0;
-  if (lane_id() == leader) base = atomicAdd(E.out_count, (unsigned long long)__popcll(m));
-  base = __shfl(base, leader);
+  const uint32_t nk = (uint32_t)__popcll(m);
+  if (stage_count(S) + nk > S.cap) stage_flush(E, S);
+  const uint32_t base = stage_count(S);
   if (keep) {
     if (!have_ids) {
       const uint32_t co = g.perm[c];
@@ -149,14 +195,15 @@ __device__ inline void emit_one(const Emit& E, const GView& g, bool valid, uint3
         kc = a_orig < co ? co : a_orig;
       }
     }
-    const unsigned long long pos = base + (unsigned long long)__popcll(m & lanemask_lt());
-    if (pos < E.cap) {
-      E.out_s[pos] = sb;
-      E.out_a[pos] = ka;
-      E.out_c[pos] = kc;
-    }
+    const uint32_t j = base + (uint32_t)__popcll(m & lanemask_lt());
+    S.s[j] = sb;
+    S.a[j] = ka;
+    S.c[j] = kc;
     if (kQuery && E.q_count) atomicAdd(&E.q_count[a_key], 1u);
   }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  if (lane_id() == __ffsll((unsigned long long)m) - 1) stage_set_count(S, base + nk);
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 }
 
 __device__ inline void flush_fp(const Emit& E, FpAcc& fa) {
@@ -188,7 +235,7 @@ __device__ inline void group_sync() {
 // Exclusive prefix sum of one value per lane within a group of G lanes
 // (G <= 64: shuffles inside the wave; G > 64: through LDS).
 template <int G>
-__device__ inline uint32_t group_exclusive_scan(uint32_t v, uint32_t* lds_tmp /*[G/64]*/,
+__device__ inline uint32_t group_exclusive_scan(uint32_t v, uint32_t* lds_tmp /*[G / 64]*/,
                                                 uint32_t* total) {
   const int gl = threadIdx.x & (G - 1);
   if constexpr (G <= 64) {

@@ -93,8 +93,13 @@ struct lp_graph {
   // device arrays in the relabelled id space
   uint32_t* off = nullptr;       // n+1 row offsets
   uint32_t* adj = nullptr;       // arcs, each row ascending
-  uint32_t* sufstart = nullptr;  // arc (a->b): first position in row b holding an id > a
-  uint32_t* psum = nullptr;      // arc (a->b): inclusive per-row prefix of |{c in row b : c > a}|
+  // two-hop arc list: for every source a, the arcs a->b (b ascending) whose row
+  // b holds at least one id > a, i.e. that contribute wedges a-b-c with c > a
+  uint32_t* hoff = nullptr;    // n+1 offsets into the list
+  uint32_t* hb = nullptr;      // b
+  uint32_t* hstart = nullptr;  // first position in adj (row b) holding an id > a
+  uint32_t* hpsum = nullptr;   // inclusive running total of those suffix lengths within the row
+  int64_t harcs = 0;
   uint32_t* deg = nullptr;       // n, non-decreasing
   uint32_t* below = nullptr;     // n, number of neighbours with a smaller id
   uint32_t* perm = nullptr;      // n, new id -> original id

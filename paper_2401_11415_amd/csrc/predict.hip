@@ -91,9 +91,9 @@ __global__ __launch_bounds__(256) void plan_kernel(GView g, uint32_t hub_start, 
   uint32_t U = 0;
   int b = -1;
   if (a < g.n) {
-    const uint32_t e0 = g.off[a], e1 = g.off[a + 1];
-    const uint32_t k = lower_bound_dev(g.adj, e0, e1, hub_start) - e0;
-    U = k ? g.psum[e0 + k - 1] : 0u;
+    const uint32_t h0 = g.hoff[a], h1 = g.hoff[a + 1];
+    const uint32_t k = lower_bound_dev(g.hb, h0, h1, hub_start) - h0;
+    U = k ? g.hpsum[h0 + k - 1] : 0u;
     cnt[a] = k;
     wedges[a] = U;
     b = bucket_of(U, lds_cap);
@@ -181,8 +181,9 @@ struct Src {
   uint32_t a;       // relabelled id
   uint32_t a_key;   // predict: original id; query: query index
   uint32_t a_orig;  // original id
-  uint32_t e0, e1;  // row
-  uint32_t na;      // explored arcs (prefix of the row)
+  uint32_t e0, e1;  // row of a in adj (first-order neighbours)
+  uint32_t h0;      // predict: first explored arc in the two-hop list; query: = e0
+  uint32_t na;      // explored arcs
   uint32_t U;       // wedges (predict: exact; query: upper bound)
 };
 
@@ -190,27 +191,20 @@ template <bool kQuery>
 __device__ inline Src load_src(const GView& g, const uint32_t* cnt, const uint32_t* wedges,
                                const uint32_t* qnew, uint32_t item) {
   Src s;
-  if (kQuery) {
-    s.a = qnew[item];
-    s.a_key = item;
-    s.na = cnt[item];
-    s.U = wedges[item];
-  } else {
-    s.a = item;
-    s.a_key = 0;
-    s.na = cnt[item];
-    s.U = wedges[item];
-  }
+  s.a = kQuery ? qnew[item] : item;
+  s.na = cnt[item];
+  s.U = wedges[item];
   s.e0 = g.off[s.a];
   s.e1 = g.off[s.a + 1];
+  s.h0 = kQuery ? s.e0 : g.hoff[s.a];
   s.a_orig = g.perm[s.a];
-  if (!kQuery) s.a_key = s.a_orig;
+  s.a_key = kQuery ? item : s.a_orig;
   return s;
 }
 
-// Load the chunk of arcs [cb, cb + G) of source s into the group scratch:
-// flat start index (excl), position of the first c in adj (start), weight.
-// Returns the flat range [lo, hi) of the chunk.
+// Load the chunk of explored arcs [cb, cb + G) of source s into the group
+// scratch: flat index of its first wedge (excl), position in adj of its first
+// c (start), weight; the chunk covers flat wedges [*lo, *hi).
 template <int G, bool kQuery, bool kW>
 __device__ inline void load_chunk(const GView& g, const Emit& E, const Src& s, uint32_t cb,
                                   uint32_t* s_excl, uint32_t* s_start, uint64_t* s_w,
@@ -218,62 +212,75 @@ __device__ inline void load_chunk(const GView& g, const Emit& E, const Src& s, u
   const int gl = threadIdx.x & (G - 1);
   const uint32_t j = cb + gl;
   const bool valid = j < s.na;
+  const uint32_t e = s.h0 + j;
   uint32_t start = 0, len = 0;
   uint64_t w = 0;
-  if (valid) {
-    const uint32_t e = s.e0 + j;
-    if (kQuery) {
+  if (kQuery) {
+    if (valid) {
       const uint32_t b = g.adj[e];
       start = g.off[b];
       len = g.off[b + 1] - start;
       if (kW) w = weight_of(E.measure, len, E.shift);
-    } else {
-      start = g.sufstart[e];
-      if (kW) w = weight_of(E.measure, g.deg[g.adj[e]], E.shift);
     }
-  }
-  if (kQuery) {
     uint32_t total;
     const uint32_t ex = group_exclusive_scan<G>(len, scan_tmp, &total);
     s_excl[gl] = valid ? ex : kEmpty32;
     *lo = 0;
     *hi = total;
   } else {
-    const uint32_t e = s.e0 + j;
-    const uint32_t ex = valid ? (j == 0 ? 0u : g.psum[e - 1]) : kEmpty32;
+    uint32_t ex = kEmpty32;
+    if (valid) {
+      start = g.hstart[e];
+      ex = j == 0 ? 0u : g.hpsum[e - 1];
+      if (kW) w = weight_of(E.measure, g.deg[g.hb[e]], E.shift);
+    }
     s_excl[gl] = ex;
-    *lo = cb == 0 ? 0u : g.psum[s.e0 + cb - 1];
     const uint32_t last = (cb + G < s.na ? cb + G : s.na) - 1;
-    *hi = g.psum[s.e0 + last];
+    *lo = cb == 0 ? 0u : g.hpsum[s.h0 + cb - 1];
+    *hi = g.hpsum[s.h0 + last];
   }
   s_start[gl] = start;
   if (kW) s_w[gl] = w;
 }
 
 // ---------------------------------------------------------------------------
-// LDS-table accumulation: G lanes per source, SLOTS slots per table.
+// LDS-table accumulation: groups of G lanes (WGS / G groups per workgroup),
+// one source per group at a time, SLOTS table slots per group.
 // ---------------------------------------------------------------------------
 
-template <int G, int SLOTS, bool kW>
+template <int WGS, int G, int SLOTS, bool kW, int STAGE>
 struct LdsTab {
-  static constexpr int NG = 256 / G;
+  static constexpr int NG = WGS / G;
+  static constexpr int NW = WGS / 64;
+  uint32_t st_s[NW][STAGE];
+  uint32_t st_a[NW][STAGE];
+  uint32_t st_c[NW][STAGE];
+  uint32_t st_n[NW];
   uint64_t tab[kW ? 1 : NG * SLOTS];
   uint32_t keys[kW ? NG * SLOTS : 1];
   uint64_t vals[kW ? NG * SLOTS : 1];
   uint32_t excl[NG][G];
   uint32_t start[NG][G];
   uint64_t w[kW ? NG : 1][kW ? G : 1];
-  uint32_t scan_tmp[4];
+  uint32_t scan_tmp[G > 64 ? G / 64 : 1];
   int ovf[NG];
 };
 
-template <int G, int SLOTS, bool kW, bool kQuery>
-__global__ __launch_bounds__(256) void acc_lds_kernel(GView g, Emit E, const uint32_t* __restrict__ cnt,
+constexpr int kUnrollGather = 4;  // independent wedge loads in flight per lane
+constexpr int kUnrollScore = 4;   // independent degree loads in flight per lane
+
+template <int WGS, int G, int SLOTS, bool kW, bool kQuery, int STAGE>
+__global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, const uint32_t* __restrict__ cnt,
                                                       const uint32_t* __restrict__ wedges,
                                                       const uint32_t* __restrict__ qnew,
                                                       WorkList wl) {
-  constexpr int NG = 256 / G;
-  __shared__ LdsTab<G, SLOTS, kW> L;
+  static_assert(G <= 64 || G == WGS, "multi-wave groups span the workgroup");
+  static_assert(STAGE >= 64, "a stage holds at least one wave of survivors");
+  constexpr int NG = WGS / G;
+  __shared__ LdsTab<WGS, G, SLOTS, kW, STAGE> L;
+  const int wv_id = threadIdx.x >> 6;
+  const Stage SG{L.st_s[wv_id], L.st_a[wv_id], L.st_c[wv_id], &L.st_n[wv_id], (uint32_t)STAGE};
+  if (lane_id() == 0) stage_set_count(SG, 0u);
   const int grp = threadIdx.x / G;
   const int gl = threadIdx.x & (G - 1);
   uint64_t* tab = L.tab + (kW ? 0 : grp * SLOTS);
@@ -283,6 +290,7 @@ __global__ __launch_bounds__(256) void acc_lds_kernel(GView g, Emit E, const uin
   uint32_t* s_start = L.start[grp];
   uint64_t* s_w = kW ? L.w[grp] : nullptr;
   FpAcc fa;
+  const bool want_dc = needs_dc(E.measure);
   const uint32_t total = work_count(wl);
   for (uint32_t i = blockIdx.x * NG + grp; i < total; i += gridDim.x * NG) {
     const Src s = load_src<kQuery>(g, cnt, wedges, qnew, work_item(wl, i));
@@ -305,47 +313,61 @@ __global__ __launch_bounds__(256) void acc_lds_kernel(GView g, Emit E, const uin
       }
       if (gl == 0) L.ovf[grp] = 0;
       group_sync<G>();
-      // accumulate the wedges of this source
+      // accumulate the wedges of this source (this partition's keys)
       for (uint32_t cb = 0; cb < s.na; cb += G) {
         uint32_t lo, hi;
         load_chunk<G, kQuery, kW>(g, E, s, cb, s_excl, s_start, s_w, L.scan_tmp, &lo, &hi);
         group_sync<G>();
-        for (uint32_t f = lo + gl; f < hi; f += G) {
-          const int jj = seg_search<G>(s_excl, f);
-          const uint32_t c = g.adj[s_start[jj] + (f - s_excl[jj])];
-          if (kQuery && c == s.a) continue;
-          const uint32_t hc = c * kHashMul;
-          if (lgP && (hc >> (32 - lgP)) != pass) continue;
-          uint32_t h = (hc << lgP) >> (32 - lgS);
-          bool done = false;
-          if (kW) {
-            const uint64_t w = s_w[jj];
-            for (uint32_t probe = 0; probe < S; probe++) {
-              const uint32_t old = atomicCAS(&keys[h], kEmpty32, c);
-              if (old == kEmpty32 || old == c) {
-                atomicAdd((unsigned long long*)&vals[h], (unsigned long long)w);
-                done = true;
-                break;
-              }
-              h = (h + 1) & mask;
-            }
-          } else {
-            const uint64_t want = ((uint64_t)c << 32) | 1ull;
-            for (uint32_t probe = 0; probe < S; probe++) {
-              const uint64_t old = atomicCAS((unsigned long long*)&tab[h], kEmpty64, want);
-              if (old == kEmpty64) {
-                done = true;
-                break;
-              }
-              if ((uint32_t)(old >> 32) == c) {
-                atomicAdd((unsigned long long*)&tab[h], 1ull);
-                done = true;
-                break;
-              }
-              h = (h + 1) & mask;
+        for (uint32_t f0 = lo + gl; f0 < hi; f0 += G * kUnrollGather) {
+          uint32_t cv[kUnrollGather];
+          uint64_t wv[kUnrollGather];
+#pragma unroll
+          for (int u = 0; u < kUnrollGather; u++) {
+            const uint32_t f = f0 + (uint32_t)(u * G);
+            cv[u] = kEmpty32;
+            wv[u] = 0;
+            if (f < hi) {
+              const int jj = seg_search<G>(s_excl, f);
+              cv[u] = g.adj[s_start[jj] + (f - s_excl[jj])];
+              if (kW) wv[u] = s_w[jj];
             }
           }
-          if (!done) L.ovf[grp] = 1;
+#pragma unroll
+          for (int u = 0; u < kUnrollGather; u++) {
+            const uint32_t c = cv[u];
+            if (c == kEmpty32 || (kQuery && c == s.a)) continue;
+            const uint32_t hc = c * kHashMul;
+            if (lgP && (hc >> (32 - lgP)) != pass) continue;
+            uint32_t h = (hc << lgP) >> (32 - lgS);
+            bool done = false;
+            if (kW) {
+              for (uint32_t probe = 0; probe < S; probe++) {
+                const uint32_t old = atomicCAS(&keys[h], kEmpty32, c);
+                if (old == kEmpty32 || old == c) {
+                  atomicAdd((unsigned long long*)&vals[h], (unsigned long long)wv[u]);
+                  done = true;
+                  break;
+                }
+                h = (h + 1) & mask;
+              }
+            } else {
+              const uint64_t want = ((uint64_t)c << 32) | 1ull;
+              for (uint32_t probe = 0; probe < S; probe++) {
+                const uint64_t old = atomicCAS((unsigned long long*)&tab[h], kEmpty64, want);
+                if (old == kEmpty64) {
+                  done = true;
+                  break;
+                }
+                if ((uint32_t)(old >> 32) == c) {
+                  atomicAdd((unsigned long long*)&tab[h], 1ull);
+                  done = true;
+                  break;
+                }
+                h = (h + 1) & mask;
+              }
+            }
+            if (!done) L.ovf[grp] = 1;
+          }
         }
         group_sync<G>();
       }
@@ -392,25 +414,41 @@ __global__ __launch_bounds__(256) void acc_lds_kernel(GView g, Emit E, const uin
         break;
       }
       // score every key of this partition
-      for (uint32_t t = gl; t < S; t += G) {
-        uint32_t c, h = 0;
-        uint64_t wsum = 0;
-        bool valid;
-        if (kW) {
-          c = keys[t];
-          wsum = vals[t];
-          valid = c != kEmpty32 && wsum != 0;
-        } else {
-          const uint64_t v = tab[t];
-          c = (uint32_t)(v >> 32);
-          h = (uint32_t)v;
-          valid = c != kEmpty32 && h != 0;
+      for (uint32_t t0 = gl; t0 < S; t0 += G * kUnrollScore) {
+        uint32_t cv[kUnrollScore], hv[kUnrollScore], dv[kUnrollScore];
+        uint64_t wv[kUnrollScore];
+        bool ok[kUnrollScore];
+#pragma unroll
+        for (int u = 0; u < kUnrollScore; u++) {
+          const uint32_t t = t0 + (uint32_t)(u * G);
+          ok[u] = false;
+          cv[u] = 0;
+          hv[u] = 0;
+          wv[u] = 0;
+          if (t < S) {
+            if (kW) {
+              cv[u] = keys[t];
+              wv[u] = vals[t];
+              ok[u] = cv[u] != kEmpty32 && wv[u] != 0;
+            } else {
+              const uint64_t v = tab[t];
+              cv[u] = (uint32_t)(v >> 32);
+              hv[u] = (uint32_t)v;
+              ok[u] = cv[u] != kEmpty32 && hv[u] != 0;
+            }
+          }
         }
-        emit_one<kQuery>(E, g, valid, s.a_orig, s.a_key, da, valid ? c : 0u, h, wsum, fa);
+#pragma unroll
+        for (int u = 0; u < kUnrollScore; u++) dv[u] = (ok[u] && want_dc) ? g.deg[cv[u]] : 0u;
+#pragma unroll
+        for (int u = 0; u < kUnrollScore; u++)
+          emit_one<kQuery>(E, g, SG, ok[u], s.a_orig, s.a_key, da, ok[u] ? cv[u] : 0u, dv[u],
+                           hv[u], wv[u], fa);
       }
       group_sync<G>();
     }
   }
+  if (!E.fp_mode) stage_flush(E, SG);
   flush_fp(E, fa);
 }
 
@@ -426,15 +464,23 @@ struct SpaItem {
   uint32_t ovf_begin, ovf_end;
 };
 
+constexpr int kSpaThreads = 1024;
+
 template <bool kW, bool kQuery>
-__global__ __launch_bounds__(256) void acc_spa_kernel(GView g, Emit E, const uint32_t* __restrict__ cnt,
+__global__ __launch_bounds__(kSpaThreads) void acc_spa_kernel(GView g, Emit E, const uint32_t* __restrict__ cnt,
                                                       const uint32_t* __restrict__ wedges,
                                                       const uint32_t* __restrict__ qnew,
                                                       WorkList wl, SpaItem ov, char* spa_acc,
                                                       uint32_t* spa_keys) {
-  __shared__ uint32_t s_excl[256], s_start[256], scan_tmp[4];
-  __shared__ uint64_t s_w[kW ? 256 : 1];
+  constexpr int T = kSpaThreads;
+  constexpr int STAGE = 128;
+  __shared__ uint32_t s_excl[T], s_start[T], scan_tmp[T / 64];
+  __shared__ uint64_t s_w[kW ? T : 1];
   __shared__ uint32_t nkeys;
+  __shared__ uint32_t st_s[T / 64][STAGE], st_a[T / 64][STAGE], st_c[T / 64][STAGE], st_n[T / 64];
+  const int wv_id = threadIdx.x >> 6;
+  const Stage SG{st_s[wv_id], st_a[wv_id], st_c[wv_id], &st_n[wv_id], (uint32_t)STAGE};
+  if (lane_id() == 0) stage_set_count(SG, 0u);
   // one 8-byte-per-vertex accumulator slab per workgroup, whatever the measure:
   // counts use its first half, so every slab stays zero between calls
   char* slab = spa_acc + (uint64_t)blockIdx.x * g.n * 8;
@@ -442,6 +488,7 @@ __global__ __launch_bounds__(256) void acc_spa_kernel(GView g, Emit E, const uin
   unsigned long long* HW = reinterpret_cast<unsigned long long*>(slab);
   uint32_t* K = spa_keys + (uint64_t)blockIdx.x * g.n;
   FpAcc fa;
+  const bool want_dc = needs_dc(E.measure);
   const uint32_t total = ov.ovf ? (ov.ovf_end - ov.ovf_begin) : work_count(wl);
   for (uint32_t i = blockIdx.x; i < total; i += gridDim.x) {
     uint32_t item, p0 = 0, lgP = 0;
@@ -457,25 +504,40 @@ __global__ __launch_bounds__(256) void acc_spa_kernel(GView g, Emit E, const uin
     const uint32_t da = s.e1 - s.e0;
     if (threadIdx.x == 0) nkeys = 0;
     __syncthreads();
-    for (uint32_t cb = 0; cb < s.na; cb += 256) {
+    for (uint32_t cb = 0; cb < s.na; cb += T) {
       uint32_t lo, hi;
-      load_chunk<256, kQuery, kW>(g, E, s, cb, s_excl, s_start, s_w, scan_tmp, &lo, &hi);
+      load_chunk<T, kQuery, kW>(g, E, s, cb, s_excl, s_start, s_w, scan_tmp, &lo, &hi);
       __syncthreads();
-      for (uint32_t f = lo + threadIdx.x; f < hi; f += 256) {
-        const int jj = seg_search<256>(s_excl, f);
-        const uint32_t c = g.adj[s_start[jj] + (f - s_excl[jj])];
-        if (kQuery && c == s.a) continue;
-        if (lgP && ((c * kHashMul) >> (32 - lgP)) < p0) continue;
-        bool first;
-        if (kW) first = atomicAdd(&HW[c], (unsigned long long)s_w[jj]) == 0ull;
-        else first = atomicAdd(&H[c], 1u) == 0u;
-        if (first)
-          __hip_atomic_store(&K[atomicAdd(&nkeys, 1u)], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (uint32_t f0 = lo + threadIdx.x; f0 < hi; f0 += T * kUnrollGather) {
+        uint32_t cv[kUnrollGather];
+        uint64_t wv[kUnrollGather];
+#pragma unroll
+        for (int u = 0; u < kUnrollGather; u++) {
+          const uint32_t f = f0 + (uint32_t)(u * T);
+          cv[u] = kEmpty32;
+          wv[u] = 0;
+          if (f < hi) {
+            const int jj = seg_search<T>(s_excl, f);
+            cv[u] = g.adj[s_start[jj] + (f - s_excl[jj])];
+            if (kW) wv[u] = s_w[jj];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kUnrollGather; u++) {
+          const uint32_t c = cv[u];
+          if (c == kEmpty32 || (kQuery && c == s.a)) continue;
+          if (lgP && ((c * kHashMul) >> (32 - lgP)) < p0) continue;
+          bool first;
+          if (kW) first = atomicAdd(&HW[c], (unsigned long long)wv[u]) == 0ull;
+          else first = atomicAdd(&H[c], 1u) == 0u;
+          if (first)
+            __hip_atomic_store(&K[atomicAdd(&nkeys, 1u)], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
       }
       __syncthreads();
     }
     const uint32_t x0 = kQuery ? s.e0 : s.e0 + g.below[s.a];
-    for (uint32_t e = x0 + threadIdx.x; e < s.e1; e += 256) {
+    for (uint32_t e = x0 + threadIdx.x; e < s.e1; e += T) {
       const uint32_t b = g.adj[e];
       if (kW) __hip_atomic_store(&HW[b], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       else __hip_atomic_store(&H[b], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -483,9 +545,9 @@ __global__ __launch_bounds__(256) void acc_spa_kernel(GView g, Emit E, const uin
     __threadfence();
     __syncthreads();
     const uint32_t nk = nkeys;
-    for (uint32_t t = threadIdx.x; t < ((nk + 63) & ~63u); t += 256) {
+    for (uint32_t t = threadIdx.x; t < ((nk + 63) & ~63u); t += T) {
       const bool in = t < nk;
-      uint32_t c = 0, h = 0;
+      uint32_t c = 0, h = 0, dc = 0;
       uint64_t wsum = 0;
       bool valid = false;
       if (in) {
@@ -497,12 +559,14 @@ __global__ __launch_bounds__(256) void acc_spa_kernel(GView g, Emit E, const uin
           h = __hip_atomic_exchange(&H[c], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           valid = h != 0;
         }
+        if (valid && want_dc) dc = g.deg[c];
       }
-      emit_one<kQuery>(E, g, valid, s.a_orig, s.a_key, da, c, h, wsum, fa);
+      emit_one<kQuery>(E, g, SG, valid, s.a_orig, s.a_key, da, c, dc, h, wsum, fa);
     }
     __threadfence();
     __syncthreads();
   }
+  if (!E.fp_mode) stage_flush(E, SG);
   flush_fp(E, fa);
 }
 
@@ -580,21 +644,18 @@ __global__ __launch_bounds__(64) void sel_pick_kernel(SelState* st, int step, ui
   for (int i = threadIdx.x; i < 2048; i += 64) hist[i] = 0;
 }
 
-__device__ inline unsigned long long wave_slot(bool pred, unsigned long long* counter) {
-  const uint64_t m = __ballot(pred);
-  if (m == 0) return 0;
-  const int leader = __ffsll((unsigned long long)m) - 1;
-  unsigned long long base = 0;
-  if (lane_id() == leader) base = atomicAdd(counter, (unsigned long long)__popcll(m));
-  base = __shfl(base, leader);
-  return base + (unsigned long long)__popcll(m & lanemask_lt());
-}
+constexpr int kSelItems = 16;  // elements per thread per tile of the partition
 
+// Partition the working set around the chosen digit: larger digits go to the
+// output, the boundary digit to the next working set.  One global atomic per
+// counter per tile of 256 * kSelItems elements.
 __global__ __launch_bounds__(256) void sel_partition_kernel(
     const uint32_t* __restrict__ ks, const uint32_t* __restrict__ ka, const uint32_t* __restrict__ kc,
     SelState* st, int step, uint32_t* __restrict__ ns, uint32_t* __restrict__ na,
     uint32_t* __restrict__ nc, uint32_t* __restrict__ os, uint32_t* __restrict__ oa,
     uint32_t* __restrict__ oc) {
+  __shared__ uint32_t w_out[4], w_next[4];
+  __shared__ unsigned long long b_out, b_next;
   if (st->done) return;
   const unsigned long long n = st->n_cur;
   int word, shift, bits;
@@ -602,31 +663,71 @@ __global__ __launch_bounds__(256) void sel_partition_kernel(
   const uint32_t mask = (1u << bits) - 1;
   const uint32_t dsel = st->digit;
   const bool take_all = st->take_all != 0;
-  const unsigned long long n_round = (n + 63) & ~63ull;
-  for (unsigned long long i = (unsigned long long)blockIdx.x * 256 + threadIdx.x; i < n_round;
-       i += (unsigned long long)gridDim.x * 256) {
-    const bool in = i < n;
-    uint32_t s = 0, a = 0, c = 0, d = 0;
-    if (in) {
-      s = ks[i];
-      a = ka[i];
-      c = kc[i];
-      d = (key_word(s, a, c, word) >> shift) & mask;
+  const int lane = lane_id(), wid = threadIdx.x >> 6;
+  constexpr unsigned long long kTile = 256ull * kSelItems;
+  for (unsigned long long t0 = (unsigned long long)blockIdx.x * kTile; t0 < n;
+       t0 += (unsigned long long)gridDim.x * kTile) {
+    uint32_t cls = 0;  // 2 bits per item: 1 = out, 2 = next
+    uint32_t c_out = 0, c_next = 0;
+#pragma unroll
+    for (int j = 0; j < kSelItems; j++) {
+      const unsigned long long i = t0 + (unsigned long long)j * 256 + threadIdx.x;
+      if (i < n) {
+        const uint32_t d = (key_word(ks[i], ka[i], kc[i], word) >> shift) & mask;
+        if (d > dsel || (take_all && d == dsel)) {
+          cls |= 1u << (2 * j);
+          c_out++;
+        } else if (d == dsel) {
+          cls |= 2u << (2 * j);
+          c_next++;
+        }
+      }
     }
-    const bool to_out = in && (d > dsel || (take_all && d == dsel));
-    const bool to_next = in && !take_all && d == dsel;
-    const unsigned long long po = wave_slot(to_out, &st->n_out);
-    const unsigned long long pn = wave_slot(to_next, &st->n_next);
-    if (to_out) {
-      os[po] = s;
-      oa[po] = a;
-      oc[po] = c;
+    // offsets: exclusive scans within the wave, then across the 4 waves
+    uint32_t x_out = c_out, x_next = c_next;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t yo = __shfl_up(x_out, o, 64), yn = __shfl_up(x_next, o, 64);
+      if (lane >= o) {
+        x_out += yo;
+        x_next += yn;
+      }
     }
-    if (to_next) {
-      ns[pn] = s;
-      na[pn] = a;
-      nc[pn] = c;
+    if (lane == 63) {
+      w_out[wid] = x_out;
+      w_next[wid] = x_next;
     }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const uint32_t to = w_out[0] + w_out[1] + w_out[2] + w_out[3];
+      const uint32_t tn = w_next[0] + w_next[1] + w_next[2] + w_next[3];
+      b_out = to ? atomicAdd(&st->n_out, (unsigned long long)to) : 0ull;
+      b_next = tn ? atomicAdd(&st->n_next, (unsigned long long)tn) : 0ull;
+    }
+    __syncthreads();
+    unsigned long long po = b_out + x_out - c_out, pn = b_next + x_next - c_next;
+    for (int w = 0; w < wid; w++) {
+      po += w_out[w];
+      pn += w_next[w];
+    }
+#pragma unroll
+    for (int j = 0; j < kSelItems; j++) {
+      const uint32_t cl = (cls >> (2 * j)) & 3u;
+      if (cl == 0) continue;
+      const unsigned long long i = t0 + (unsigned long long)j * 256 + threadIdx.x;
+      if (cl == 1) {
+        os[po] = ks[i];
+        oa[po] = ka[i];
+        oc[po] = kc[i];
+        po++;
+      } else {
+        ns[pn] = ks[i];
+        na[pn] = ka[i];
+        nc[pn] = kc[i];
+        pn++;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -722,8 +823,10 @@ static GView view_of(const lp_graph* g) {
   GView v;
   v.off = g->off;
   v.adj = g->adj;
-  v.sufstart = g->sufstart;
-  v.psum = g->psum;
+  v.hoff = g->hoff;
+  v.hb = g->hb;
+  v.hstart = g->hstart;
+  v.hpsum = g->hpsum;
   v.deg = g->deg;
   v.below = g->below;
   v.perm = g->perm;
@@ -760,20 +863,20 @@ static lp_status launch_bucket(lp_graph* g, int bucket, const GView& gv, const E
   const unsigned cus = (unsigned)num_cus();
   switch (bucket) {
     case kBucketTiny:
-      hipLaunchKernelGGL((acc_lds_kernel<16, 64, kW, kQuery>), dim3(grid_for(nitems, 16, cus * 16)),
+      hipLaunchKernelGGL((acc_lds_kernel<256, 16, 64, kW, kQuery, 256>), dim3(grid_for(nitems, 16, cus * 16)),
                          dim3(256), 0, st, gv, E, cnt, wedges, qnew, wl);
       break;
     case kBucketSmall:
-      hipLaunchKernelGGL((acc_lds_kernel<64, 512, kW, kQuery>), dim3(grid_for(nitems, 4, cus * 16)),
+      hipLaunchKernelGGL((acc_lds_kernel<256, 64, 512, kW, kQuery, 256>), dim3(grid_for(nitems, 4, cus * 16)),
                          dim3(256), 0, st, gv, E, cnt, wedges, qnew, wl);
       break;
     case kBucketMid:
-      hipLaunchKernelGGL((acc_lds_kernel<256, 4096, kW, kQuery>), dim3(grid_for(nitems, 1, cus * 8)),
+      hipLaunchKernelGGL((acc_lds_kernel<256, 256, 4096, kW, kQuery, kW ? 256 : 112>), dim3(grid_for(nitems, 1, cus * 8)),
                          dim3(256), 0, st, gv, E, cnt, wedges, qnew, wl);
       break;
     case kBucketLarge:
-      hipLaunchKernelGGL((acc_lds_kernel<256, kW ? 8192 : 16384, kW, kQuery>),
-                         dim3(grid_for(nitems, 1, cus * 2)), dim3(256), 0, st, gv, E, cnt, wedges,
+      hipLaunchKernelGGL((acc_lds_kernel<1024, 1024, kW ? 8192 : 16384, kW, kQuery, 64>),
+                         dim3(grid_for(nitems, 1, cus * 2)), dim3(1024), 0, st, gv, E, cnt, wedges,
                          qnew, wl);
       break;
     default:
@@ -803,8 +906,8 @@ static lp_status launch_spa(lp_graph* g, const GView& gv, const Emit& E, const u
   char* base = w.global_tab.as<char>();
   uint32_t* spa_keys = reinterpret_cast<uint32_t*>(base + (size_t)cfg.spa_wgs * n * 8);
   const unsigned wgs = (unsigned)std::min<uint64_t>(cfg.spa_wgs, nitems);
-  hipLaunchKernelGGL((acc_spa_kernel<kW, kQuery>), dim3(wgs), dim3(256), 0, st, gv, E, cnt, wedges,
-                     qnew, wl, ov, base, spa_keys);
+  hipLaunchKernelGGL((acc_spa_kernel<kW, kQuery>), dim3(wgs), dim3(kSpaThreads), 0, st, gv, E, cnt,
+                     wedges, qnew, wl, ov, base, spa_keys);
   LP_HIP(hipGetLastError());
   return LP_OK;
 }
