@@ -23,6 +23,8 @@ __all__ = ["MEASURES", "HUB_NONE", "LpError", "Graph", "predict", "query", "fing
 
 MEASURES = ("CN", "JC", "SI", "SC", "HP", "HD", "LHN", "AA", "RA")
 HUB_NONE = (1 << 63) - 1  # L_H = infinity: IBase
+# scheduling buckets of the accumulation, by wedges per source (lp_stats order)
+BUCKETS = ("tiny", "small", "mid1", "mid2", "large", "global")
 LP_VALIDATE = 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -226,6 +228,6 @@ def last_stats(g: Graph) -> dict:
     s = _Stats()
     _check(load().lp_last_stats(g.handle, ctypes.byref(s)))
     return {"wedges": s.wedges, "sources": s.sources,
-            "bucket_sources": list(s.bucket_sources)[:5], "appended": s.appended,
+            "buckets": dict(zip(BUCKETS, list(s.bucket_sources))), "appended": s.appended,
             "retries": s.retries, "ms_plan": s.ms_plan, "ms_accumulate": s.ms_accumulate,
             "ms_select": s.ms_select, "ms_total": s.ms_total}

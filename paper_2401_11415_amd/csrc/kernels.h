@@ -7,7 +7,6 @@
 namespace lp {
 
 constexpr uint32_t kEmpty32 = 0xFFFFFFFFu;
-constexpr uint64_t kEmpty64 = 0xFFFFFFFF00000000ull;  // key = empty, count = 0
 constexpr uint32_t kHashMul = 0x9E3779B1u;            // Fibonacci hashing multiplier
 
 // Read-only view of the resident graph (relabelled ids).
@@ -38,7 +37,8 @@ struct Emit {
   uint32_t* q_count;       // query: candidates per query index (may be null)
   int fp_mode;             // accumulate the candidate-set digest instead of emitting
   unsigned long long* fp;  // [3] digest accumulators
-  uint32_t* ovf;           // overflow records (source, pass | lgP << 8)
+  uint32_t* ovf;           // overflow records: (pass | P << 8) per entry
+  void* ovf_rec;           // overflow records: the source record per entry
   uint32_t* ovf_count;
   uint32_t ovf_cap;
   uint32_t* err;           // error flags
@@ -84,126 +84,410 @@ __device__ inline uint64_t weight_of(int m, uint32_t db, int shift) {
   return db > 0 ? (uint64_t)llrint(ldexp(1.0 / (double)db, shift)) : 0ull;
 }
 
+// Upper bounds of each measure that need only h and d_a (h <= d_a always;
+// d_c >= h always, and d_c >= d_a when the candidate follows the source in the
+// degree order, "ordered"):
+//   ordered:   JC <= h / (2 d_a - h), SI <= h / (2 d_a), SC, HP, HD <= h / d_a,
+//              LHN <= h / d_a^2
+//   unordered: JC, HD <= h / d_a, SI <= h / (d_a + h), SC <= sqrt(h / d_a),
+//              LHN <= 1 / d_a, HP <= 1
+// CN is h itself.  Rounding to FP32 is monotone, so the FP32 value of a bound
+// bounds the FP32 score.
+__device__ inline float bound_score(int m, uint32_t h, uint32_t da, bool ordered) {
+  const double H = (double)h, A = (double)da;
+  if (ordered) {
+    switch (m) {
+      case LP_CN: return (float)H;
+      case LP_JC: return (float)(H / (2.0 * A - H));
+      case LP_SI: return (float)(H / (2.0 * A));
+      case LP_SC:
+      case LP_HP:
+      case LP_HD: return (float)(H / A);
+      case LP_LHN: return (float)(H / (A * A));
+      default: return 3.0e38f;
+    }
+  }
+  switch (m) {
+    case LP_CN: return (float)H;
+    case LP_JC:
+    case LP_HD: return (float)(H / A);
+    case LP_SI: return (float)(H / (A + H));
+    case LP_SC: return (float)(H / sqrt(A * H));
+    case LP_LHN: return (float)(H / (A * H));
+    default: return 3.0e38f;
+  }
+}
+
+// Smallest count h a candidate of a source of degree da needs for its FP32
+// score to reach the threshold score ts; 0xFFFFFFFF when no candidate of the
+// source can reach it.  AA / RA use min_wsum instead.
+__device__ inline uint32_t min_count(int m, uint32_t ts_bits, uint32_t da, bool ordered) {
+  if (ts_bits == 0 || m == LP_AA || m == LP_RA || (m == LP_HP && !ordered)) return 1u;
+  const float ts = __uint_as_float(ts_bits);
+  const uint32_t hmax = da < 0xFFFFFFu ? da : 0xFFFFFFu;  // h <= d_a; counts stay below 2^24
+  if (hmax == 0 || bound_score(m, hmax, da, ordered) < ts) return 0xFFFFFFFFu;
+  // closed-form estimate of the crossing, then exact correction steps
+  const double t = (double)ts, A = (double)da;
+  double est;
+  switch (m) {
+    case LP_CN: est = t; break;
+    case LP_JC: est = ordered ? 2.0 * t * A / (1.0 + t) : t * A; break;
+    case LP_SI: est = ordered ? 2.0 * t * A : (t < 1.0 ? t * A / (1.0 - t) : A); break;
+    case LP_SC: est = ordered ? t * A : t * t * A; break;
+    case LP_LHN: est = ordered ? t * A * A : 1.0; break;
+    default: est = t * A; break;  // HP, HD
+  }
+  uint32_t h = est < 1.0 ? 1u : (est > (double)hmax ? hmax : (uint32_t)est);
+  while (h < hmax && bound_score(m, h, da, ordered) < ts) h++;
+  while (h > 1 && bound_score(m, h - 1, da, ordered) >= ts) h--;
+  return h;
+}
+
+// Lower edge of the exact scores whose FP32 value can pass the threshold key
+// (score >= ts) and the score threshold (score > s_th): the midpoint between
+// ts and the float below it, or s_th when that is higher.
+__device__ inline double pass_edge(uint32_t ts_bits, float s_th) {
+  double lo = (double)s_th;
+  if (ts_bits != 0) {
+    const double mid = 0.5 * ((double)__uint_as_float(ts_bits - 1u) + (double)__uint_as_float(ts_bits));
+    lo = mid > lo ? mid : lo;
+  }
+  return lo;
+}
+
+// True when the exact score is certainly below lo, tested as h < lo * d (d
+// the measure's denominator) without dividing; the right-hand side is taken
+// 2^-50 low so that its rounding can never reject a score >= lo.
+__device__ inline bool score_below(int m, uint32_t h, uint64_t wsum, uint32_t da, uint32_t dc,
+                                   int shift, double lo) {
+  constexpr double kLow = 1.0 - 0x1p-50;
+  const double H = (double)h;
+  switch (m) {
+    case LP_CN: return H < lo;
+    case LP_JC: return H < lo * (double)((uint64_t)da + dc - h) * kLow;
+    case LP_SI: return H < lo * (double)((uint64_t)da + dc) * kLow;
+    case LP_SC: return H * H < lo * lo * (double)da * (double)dc * kLow;
+    case LP_HP: return H < lo * (double)(da < dc ? da : dc) * kLow;
+    case LP_HD: return H < lo * (double)(da > dc ? da : dc) * kLow;
+    case LP_LHN: return H < lo * (double)da * (double)dc * kLow;
+    default: return ldexp((double)wsum, -shift) < lo * kLow;
+  }
+}
+
+// AA / RA: a fixed-point sum below this cannot reach ts (conservative: sums
+// under the FP32 value just below ts round to at most that value)
+__device__ inline uint64_t min_wsum(int m, uint32_t ts_bits, int shift) {
+  if (ts_bits <= 1u || (m != LP_AA && m != LP_RA)) return 1ull;
+  const double below = (double)__uint_as_float(ts_bits - 1u);  // positive floats: bits are ordered
+  const double est = floor(ldexp(below, shift));
+  return est < 1.0 ? 1ull : (uint64_t)est;
+}
+
+
 struct FpAcc {
   unsigned long long cnt = 0, sh = 0, sm = 0;
 };
 
-// Per-wave staging of surviving candidates in LDS: survivors are collected
-// here and copied to the global buffer with one atomic per flush, instead of
-// one device-scope atomic per (wave, sweep step) with any survivor.
+// Per-wave staging in LDS, two levels.  The table sweep stages candidate
+// entries (c, h or weight sum, source) that pass the source's count bound;
+// their degree / id loads, FP64 scoring and threshold test run in batches
+// (stage_score), off the per-source dependency chain.  Survivors go to a
+// second stage that reaches global memory with one device-scope atomic per
+// batch (stage_out).  All stage calls are made by every lane of a wave at the
+// same point, so the fill counts live in wave-uniform registers.
 struct Stage {
-  uint32_t* s;    // [cap] score bits
-  uint32_t* a;    // [cap]
-  uint32_t* c;    // [cap]
-  uint32_t* cnt;  // entries held (one LDS word per wave)
+  uint32_t* c;   // [cap] candidate (relabelled id)
+  uint32_t* h;   // [cap] count, or low word of the AA / RA sum
+  uint32_t* w2;  // [cap] high word of the AA / RA sum (weighted tables only)
+  uint32_t* k;   // [cap] predict: source's original id; query: query index
+  uint32_t* d;   // [cap] source degree
   uint32_t cap;
+  uint32_t* os;  // [ocap] survivors: score bits
+  uint32_t* oa;  // [ocap] survivors: smaller original id / query index
+  uint32_t* oc;  // [ocap] survivors: larger original id / original id of c
+  uint32_t ocap;
+  uint32_t n = 0;   // candidates held
+  uint32_t on = 0;  // survivors held
 };
 
-// The staged count is shared by the lanes of a wave through LDS: atomic
-// accesses keep the compiler from reusing a lane's own stale copy.
-__device__ inline uint32_t stage_count(const Stage& S) {
-  return __hip_atomic_load(S.cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-}
-__device__ inline void stage_set_count(const Stage& S, uint32_t v) {
-  __hip_atomic_store(S.cnt, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-}
+__device__ inline void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
+__device__ inline uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Copy the staged entries out; callable with any set of active lanes.
-__device__ inline void stage_flush(const Emit& E, const Stage& S) {
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-  const uint32_t n = stage_count(S);
-  if (n == 0) return;
-  const uint64_t act = __ballot(true);
-  const int leader = __ffsll((unsigned long long)act) - 1;
-  const uint32_t nact = (uint32_t)__popcll(act);
-  const uint32_t ar = (uint32_t)__popcll(act & lanemask_lt());
-  unsigned long long base = 0;
-  if (lane_id() == leader) base = atomicAdd(E.out_count, (unsigned long long)n);
-  base = __shfl(base, leader);
-  for (uint32_t j = ar; j < n; j += nact) {
-    const unsigned long long pos = base + j;
-    if (pos < E.cap) {
-      E.out_s[pos] = S.s[j];
-      E.out_a[pos] = S.a[j];
-      E.out_c[pos] = S.c[j];
-    }
-  }
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-  if (lane_id() == leader) stage_set_count(S, 0u);
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-}
-
-// Score one (source, c) entry and stage it if it survives S_th and tau.
-// Must be called by every active lane of the wave at the same point (ranks
-// come from a ballot); lanes with valid == false pass through.
-//   kQuery: a_key = query index, the pair is (source, c) ordered by c only.
-//   dc: degree of c (needed by the normalised measures), loaded by the caller.
+// Copy the survivors to the global buffer.
 template <bool kQuery>
-__device__ inline void emit_one(const Emit& E, const GView& g, const Stage& S, bool valid,
-                                uint32_t a_orig, uint32_t a_key, uint32_t da, uint32_t c,
-                                uint32_t dc, uint32_t h, uint64_t wsum, FpAcc& fa) {
-  bool keep = false;
-  uint32_t sb = 0, ka = 0, kc = 0;
-  bool have_ids = false;
-  if (valid) {
-    const double s = score_of(E.measure, h, wsum, da, dc, E.shift);
-    const float f = (float)s;
-    sb = __float_as_uint(f);
+__device__ inline void stage_out(const Emit& E, Stage& S) {
+  if (S.on == 0) return;
+  wave_fence();
+  unsigned long long base = 0;
+  if (lane_id() == 0) base = atomicAdd(E.out_count, (unsigned long long)S.on);
+  base = __shfl(base, 0);
+  for (uint32_t j = lane_id(); j < S.on; j += 64) {
+    const unsigned long long pos = base + j;
+    const uint32_t a = S.oa[j];
+    if (pos < E.cap) {
+      E.out_s[pos] = S.os[j];
+      E.out_a[pos] = a;
+      E.out_c[pos] = S.oc[j];
+    }
+    if (kQuery && E.q_count) atomicAdd(&E.q_count[a], 1u);
+  }
+  wave_fence();
+  S.on = 0;
+}
+
+// Score the staged candidates; survivors move to the survivor stage.
+template <bool kQuery, bool kW>
+__device__ inline void stage_score(const Emit& E, const GView& g, Stage& S, FpAcc& fa) {
+  if (S.n == 0) return;
+  wave_fence();
+  const bool want_dc = needs_dc(E.measure);
+  const uint32_t t0 = E.tau[0], t1 = E.tau[1], t2 = E.tau[2];
+  const double lo = pass_edge(E.fp_mode ? 0u : t0, E.s_th);
+  for (uint32_t j0 = 0; j0 < S.n; j0 += 64) {
+    const uint32_t j = j0 + lane_id();
+    const bool in = j < S.n;
+    const uint32_t jc = in ? j : 0u;
+    const uint32_t c = S.c[jc], h = S.h[jc], k = S.k[jc], da = S.d[jc];
+    const uint64_t wsum = kW ? (((uint64_t)S.w2[jc] << 32) | h) : 0ull;
+    const uint32_t dc = want_dc ? g.deg[c] : 0u;
+    // most staged candidates fail the threshold: reject those without
+    // dividing and without loading the original id
+    bool live = in;
+    if (!E.fp_mode) live = live & !score_below(E.measure, h, wsum, da, dc, E.shift, lo);
+    uint32_t co = 0, sb = 0;
+    float f = 0.0f;
+    if (live) {
+      co = g.perm[c];
+      f = (float)score_of(E.measure, h, wsum, da, dc, E.shift);
+      sb = __float_as_uint(f);
+    }
+    const uint32_t ka = kQuery ? k : (k < co ? k : co);
+    const uint32_t kc = kQuery ? co : (k < co ? co : k);
+    bool keep = false;
     if (E.fp_mode) {
-      const uint32_t co = g.perm[c];
-      const uint32_t lo = a_orig < co ? a_orig : co, hi = a_orig < co ? co : a_orig;
-      fa.cnt += 1;
-      fa.sh += h;
-      fa.sm += mix64(lo, hi, h);
-    } else {
-      keep = f > E.s_th;
-      if (keep) {
-        const uint32_t ts = E.tau[0];
-        if (sb < ts) {
-          keep = false;
-        } else if (sb == ts) {
-          const uint32_t co = g.perm[c];
-          if (kQuery) {
-            ka = a_key;
-            kc = co;
-            keep = (~kc) >= E.tau[2];
-          } else {
-            ka = a_orig < co ? a_orig : co;
-            kc = a_orig < co ? co : a_orig;
-            const uint32_t na = ~ka, nc = ~kc;
-            keep = na > E.tau[1] || (na == E.tau[1] && nc >= E.tau[2]);
-          }
-          have_ids = true;
-        }
+      if (in) {
+        fa.cnt += 1;
+        fa.sh += h;
+        fa.sm += mix64(ka, kc, h);
       }
+    } else if (live && f > E.s_th) {
+      if (kQuery) keep = sb > t0 || (sb == t0 && (~kc) >= t2);
+      else keep = sb > t0 || (sb == t0 && ((~ka) > t1 || ((~ka) == t1 && (~kc) >= t2)));
     }
+    const uint64_t m = __ballot(keep);
+    const uint32_t nk = (uint32_t)__popcll(m);
+    if (nk == 0) continue;
+    if (S.on + nk > S.ocap) stage_out<kQuery>(E, S);
+    if (keep) {
+      const uint32_t p = S.on + (uint32_t)__popcll(m & lanemask_lt());
+      S.os[p] = sb;
+      S.oa[p] = ka;
+      S.oc[p] = kc;
+    }
+    S.on += nk;
   }
-  if (E.fp_mode) return;
-  const uint64_t m = __ballot(keep);
-  if (m == 0) return;
+  wave_fence();
+  S.n = 0;
+}
+
+// Stage the valid lanes' entries (all lanes of the wave call this together).
+template <bool kQuery, bool kW>
+__device__ inline void stage_add(const Emit& E, const GView& g, Stage& S, bool valid, uint32_t c,
+                                 uint32_t h, uint64_t wsum, uint32_t key, uint32_t da, FpAcc& fa) {
+  const uint64_t m = __ballot(valid);
   const uint32_t nk = (uint32_t)__popcll(m);
-  if (stage_count(S) + nk > S.cap) stage_flush(E, S);
-  const uint32_t base = stage_count(S);
-  if (keep) {
-    if (!have_ids) {
-      const uint32_t co = g.perm[c];
-      if (kQuery) {
-        ka = a_key;
-        kc = co;
-      } else {
-        ka = a_orig < co ? a_orig : co;
-        kc = a_orig < co ? co : a_orig;
-      }
-    }
-    const uint32_t j = base + (uint32_t)__popcll(m & lanemask_lt());
-    S.s[j] = sb;
-    S.a[j] = ka;
-    S.c[j] = kc;
-    if (kQuery && E.q_count) atomicAdd(&E.q_count[a_key], 1u);
+  if (nk == 0) return;
+  if (S.n + nk > S.cap) stage_score<kQuery, kW>(E, g, S, fa);
+  if (valid) {
+    const uint32_t j = S.n + (uint32_t)__popcll(m & lanemask_lt());
+    S.c[j] = c;
+    S.h[j] = kW ? (uint32_t)wsum : h;
+    if (kW) S.w2[j] = (uint32_t)(wsum >> 32);
+    S.k[j] = key;
+    S.d[j] = da;
   }
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-  if (lane_id() == __ffsll((unsigned long long)m) - 1) stage_set_count(S, base + nk);
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  S.n += nk;
+}
+
+// Drain both stages (end of a kernel).
+template <bool kQuery, bool kW>
+__device__ inline void stage_drain(const Emit& E, const GView& g, Stage& S, FpAcc& fa) {
+  stage_score<kQuery, kW>(E, g, S, fa);
+  if (!E.fp_mode) stage_out<kQuery>(E, S);
+}
+
+// ---------------------------------------------------------------------------
+// Open-addressing tables in LDS (linear probing, S slots, keys < 2^31).
+// Every probe loop runs a uniform trip count over the wave; each lane works
+// on K keys at once so that K independent LDS round trips are in flight.
+//   count table:    one 64-bit slot per key, (count << 32) | key
+//   weighted table: keys[S] (32-bit) and vals[S] (64-bit fixed-point sums)
+// A first-order neighbour's entry is flagged with kBlocked in its count or
+// kBlocked64W in its sum, and dropped when the table is swept.
+// ---------------------------------------------------------------------------
+
+constexpr uint32_t kBlocked = 0x80000000u;
+constexpr uint64_t kSlotEmpty = 0x00000000FFFFFFFFull;  // key empty, count 0
+constexpr uint64_t kSlotOne = 1ull << 32;               // count increment
+constexpr uint64_t kBlocked64 = (uint64_t)kBlocked << 32;
+constexpr uint64_t kBlocked64W = 1ull << 63;
+
+__device__ inline uint32_t next_slot(uint32_t h, uint32_t S) { return h + 1 == S ? 0u : h + 1; }
+
+// popcount(M & lanes below this one), in two instructions
+__device__ inline uint32_t rank_lt(uint64_t M) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(M >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)M, 0u));
+}
+
+// Probe from slot h on until key lands (key == kEmpty32: nothing to do);
+// the loop runs until every lane of the wave is done.  False if the table is
+// full for some lane.
+__device__ inline bool probe_count(uint64_t* tab, uint32_t S, uint32_t key, uint32_t h) {
+  for (uint32_t probe = 0; probe < S; probe++) {
+    if (!__any(key != kEmpty32)) return true;
+    uint64_t old = kSlotEmpty;
+    if (key != kEmpty32)
+      old = atomicCAS((unsigned long long*)&tab[h], (unsigned long long)kSlotEmpty,
+                      (unsigned long long)(kSlotOne | key));
+    // lanes without a live key saw old == kSlotEmpty and stay dead
+    const bool same = (key != kEmpty32) & ((uint32_t)old == key);
+    if (same) atomicAdd((unsigned long long*)&tab[h], (unsigned long long)kSlotOne);
+    key = (same | (old == kSlotEmpty)) ? kEmpty32 : key;
+    h = next_slot(h, S);
+  }
+  return !__any(key != kEmpty32);
+}
+
+__device__ inline bool probe_weight(uint32_t* keys, uint64_t* vals, uint32_t S, uint32_t key, uint32_t h,
+                                    uint64_t w) {
+  for (uint32_t probe = 0; probe < S; probe++) {
+    if (!__any(key != kEmpty32)) return true;
+    uint32_t old = 0;
+    if (key != kEmpty32) old = atomicCAS(&keys[h], kEmpty32, key);
+    const bool hit = (key != kEmpty32) & ((old == kEmpty32) | (old == key));
+    if (hit) atomicAdd((unsigned long long*)&vals[h], (unsigned long long)w);
+    key = hit ? kEmpty32 : key;
+    h = next_slot(h, S);
+  }
+  return !__any(key != kEmpty32);
+}
+
+// Per-wave list of insertions whose home slot held another key.  Every key
+// gets one probe where it falls; the few that need more wait here and are
+// probed on in batches of up to 64, so that one long probe sequence does not
+// hold up the 63 other lanes of its window.  Used by all lanes of a wave
+// together; the fill count is wave-uniform.
+template <bool kW>
+struct Retry {
+  uint32_t* key;  // [64]
+  uint32_t* h;    // [64] next slot to probe
+  uint64_t* w;    // [64] weight (weighted tables only)
+  uint32_t n = 0;
+};
+
+template <bool kW>
+__device__ inline bool retry_drain(uint64_t* tab, uint32_t* keys, uint64_t* vals, uint32_t S,
+                                   Retry<kW>& R) {
+  if (R.n == 0) return true;
+  wave_fence();
+  const uint32_t l = (uint32_t)lane_id();
+  const bool in = l < R.n;
+  const uint32_t key = in ? R.key[l] : kEmpty32;
+  const uint32_t h = in ? R.h[l] : 0u;
+  const uint64_t w = (kW && in) ? R.w[l] : 0ull;
+  wave_fence();
+  R.n = 0;
+  return kW ? probe_weight(keys, vals, S, key, h, w) : probe_count(tab, S, key, h);
+}
+
+// Insert one key per lane (kEmpty32: none): count tables add one, weighted
+// tables add w.  False if the table is full for some key.
+template <bool kW>
+__device__ inline bool tab_insert(uint64_t* tab, uint32_t* keys, uint64_t* vals, uint32_t S, uint32_t key,
+                                  uint32_t h, uint64_t w, Retry<kW>& R) {
+  const bool live = key != kEmpty32;
+  bool done;
+  if (kW) {
+    uint32_t old = 0;
+    if (live) old = atomicCAS(&keys[h], kEmpty32, key);
+    done = (old == kEmpty32) | (old == key);
+    if (live & done) atomicAdd((unsigned long long*)&vals[h], (unsigned long long)w);
+  } else {
+    uint64_t old = kSlotEmpty;
+    if (live)
+      old = atomicCAS((unsigned long long*)&tab[h], (unsigned long long)kSlotEmpty,
+                      (unsigned long long)(kSlotOne | key));
+    const bool same = (uint32_t)old == key;
+    if (live & same) atomicAdd((unsigned long long*)&tab[h], (unsigned long long)kSlotOne);
+    done = same | (old == kSlotEmpty);
+  }
+  const bool fail = live & !done;
+  const uint64_t M = __ballot(fail);
+  if (M == 0) return true;
+  const uint32_t nf = (uint32_t)__popcll(M);
+  bool ok = true;
+  if (R.n + nf > 64) ok = retry_drain<kW>(tab, keys, vals, S, R);
+  if (fail) {
+    const uint32_t p = R.n + rank_lt(M);
+    R.key[p] = key;
+    R.h[p] = next_slot(h, S);
+    if (kW) R.w[p] = w;
+  }
+  R.n += nf;
+  return ok;
+}
+
+// Flag a key's entry as a first-order neighbour if the key is present.  Runs
+// after every insertion of the table has completed; no two lanes look for the
+// same key, so plain read-modify-write suffices.
+__device__ inline void tab_block_count(uint64_t* tab, uint32_t S, uint32_t key, uint32_t h, bool act) {
+  for (uint32_t probe = 0; probe < S; probe++) {
+    if (!__any(act)) return;
+    const uint64_t v = tab[h];
+    const bool found = act && (uint32_t)v == key;
+    if (found) tab[h] = v | kBlocked64;
+    act = act && !found && (uint32_t)v != kEmpty32;
+    h = next_slot(h, S);
+  }
+}
+
+__device__ inline void tab_block_weight(const uint32_t* keys, uint64_t* vals, uint32_t S, uint32_t key,
+                                        uint32_t h, bool act) {
+  for (uint32_t probe = 0; probe < S; probe++) {
+    if (!__any(act)) return;
+    const uint32_t k = keys[h];
+    const bool found = act && k == key;
+    if (found) vals[h] |= kBlocked64W;
+    act = act && !found && k != kEmpty32;
+    h = next_slot(h, S);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Run-length decoding of a chunk of arcs into wedges, one wave at a time.
+// Arc j of the chunk covers the flat wedge offsets [excl[j], excl[j + 1]);
+// arcs are never empty.  A wave walks windows of 64 consecutive offsets; lane
+// p takes offset base + p.  j is the (wave-uniform) arc that holds base on
+// entry and base + 64 on exit; mark is a per-wave array of 64 bytes that is
+// zero between calls.  Returns the lane's arc.
+// ---------------------------------------------------------------------------
+
+__device__ inline uint32_t decode_window(const uint32_t* excl, uint32_t narcs, uint8_t* mark,
+                                         uint32_t base, uint32_t& j) {
+  const uint32_t lane = (uint32_t)lane_id();
+  const uint32_t t = j + 1 + lane;
+  if (t < narcs) {
+    const uint32_t pos = excl[t] - base;  // >= 1: arc j holds base
+    if (pos < 64) mark[pos] = 1;
+  }
+  wave_fence();
+  const bool m = mark[lane] != 0;
+  mark[lane] = 0;
+  wave_fence();
+  const uint64_t M = __ballot(m);
+  const uint32_t arc = j + rank_lt(M) + (m ? 1u : 0u);
+  j = uniform(j + (uint32_t)__popcll(M));
+  return arc;
 }
 
 __device__ inline void flush_fp(const Emit& E, FpAcc& fa) {

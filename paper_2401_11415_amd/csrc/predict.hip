@@ -32,15 +32,31 @@
 namespace lp {
 
 // ---------------------------------------------------------------------------
-// Plan
+// Plan: per source, its explored arcs and wedge count, written as a record
+// into the list of its scheduling bucket.
 // ---------------------------------------------------------------------------
 
-constexpr int kBucketTiny = 0;   // U <= 32:    16 lanes, 64 slots
-constexpr int kBucketSmall = 1;  // U <= 256:   64 lanes, 512 slots
-constexpr int kBucketMid = 2;    // U <= 2048:  256 lanes, 4096 slots
-constexpr int kBucketLarge = 3;  // U <= cap:   256 lanes, 16384 (8192 weighted) slots, partitions
-constexpr int kBucketHuge = 4;   // U > cap:    dense accumulator in global memory
-constexpr int kBuckets = 5;
+enum : int {
+  kBucketTiny = 0,   // U <= 32:      16 lanes
+  kBucketSmall = 1,  // U <= 256:     64 lanes
+  kBucketMid1 = 2,   // U <= 1024:    128 lanes
+  kBucketMid2 = 3,   // U <= 4096:    256 lanes
+  kBucketLarge = 4,  // U <= cap:     1024 lanes, hash partitions
+  kBucketHuge = 5,   // U >  cap:     dense accumulator in global memory
+  kBuckets = 6
+};
+
+// One source as the accumulation kernels see it (32 bytes, one load).
+struct SrcRec {
+  uint32_t a;    // relabelled id
+  uint32_t key;  // predict: original id; query: query index
+  uint32_t h0;   // first explored arc (two-hop list for predict, adj for query)
+  uint32_t na;   // explored arcs
+  uint32_t U;    // wedges (predict: exact; query: upper bound)
+  uint32_t x0;   // first-order neighbours to exclude: adj[x0, x1)
+  uint32_t x1;
+  uint32_t da;   // degree
+};
 
 struct PlanOut {
   unsigned long long wedges;
@@ -63,63 +79,117 @@ __device__ inline int bucket_of(uint32_t U, uint32_t lds_cap) {
   if (U > lds_cap) return kBucketHuge;
   if (U <= 32) return kBucketTiny;
   if (U <= 256) return kBucketSmall;
-  if (U <= 2048) return kBucketMid;
+  if (U <= 1024) return kBucketMid1;
+  if (U <= 4096) return kBucketMid2;
   return kBucketLarge;
 }
 
-// Append `a` to list[b] for every lane, one atomic per (wave, bucket).
-__device__ inline void bucket_append(int b, uint32_t a, uint32_t* lists, uint64_t stride,
-                                     uint32_t* counts) {
-#pragma unroll
-  for (int k = 0; k < kBuckets; k++) {
-    const uint64_t m = __ballot(b == k);
-    if (m == 0) continue;
-    const int leader = __ffsll((unsigned long long)m) - 1;
-    uint32_t base = 0;
-    if (lane_id() == leader) base = atomicAdd(&counts[k], (uint32_t)__popcll(m));
-    base = __shfl(base, leader);
-    if (b == k) lists[(uint64_t)k * stride + base + (uint32_t)__popcll(m & lanemask_lt())] = a;
-  }
-}
+constexpr int kPlanItems = 16;  // sources per thread of the plan kernel
 
+// Bucket a tile of 256 * kPlanItems sources with one global atomic per
+// (workgroup, bucket); records land in lists[bucket * stride + position].
 __global__ __launch_bounds__(256) void plan_kernel(GView g, uint32_t hub_start, uint32_t lds_cap,
-                                                   uint32_t* __restrict__ cnt,
-                                                   uint32_t* __restrict__ wedges,
-                                                   uint32_t* __restrict__ lists,
+                                                   SrcRec* __restrict__ lists,
                                                    PlanOut* __restrict__ out) {
-  const uint32_t a = blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t U = 0;
-  int b = -1;
-  if (a < g.n) {
+  __shared__ uint32_t wtot[kBuckets][4];
+  __shared__ uint32_t bbase[kBuckets];
+  __shared__ unsigned long long red_w[4], red_s[4];
+  const int lane = lane_id(), wid = threadIdx.x >> 6;
+  const uint64_t tile = (uint64_t)blockIdx.x * 256 * kPlanItems;
+  uint8_t bk[kPlanItems];
+  uint32_t nb[kBuckets] = {0, 0, 0, 0, 0, 0};
+  unsigned long long w_sum = 0, s_sum = 0;
+#pragma unroll
+  for (int j = 0; j < kPlanItems; j++) {
+    const uint64_t a = tile + (uint64_t)j * 256 + threadIdx.x;
+    bk[j] = 0xFF;
+    if (a < g.n) {
+      const uint32_t h0 = g.hoff[a], h1 = g.hoff[a + 1];
+      uint32_t U = 0;
+      if (h1 > h0) {
+        const uint32_t k = lower_bound_dev(g.hb, h0, h1, hub_start) - h0;
+        U = k ? g.hpsum[h0 + k - 1] : 0u;
+      }
+      const int b = bucket_of(U, lds_cap);
+      if (b >= 0) {
+        bk[j] = (uint8_t)b;
+        nb[b]++;
+        w_sum += U;
+        s_sum += 1;
+      }
+    }
+  }
+  uint32_t excl[kBuckets];
+#pragma unroll
+  for (int b = 0; b < kBuckets; b++) {
+    uint32_t x = nb[b];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    excl[b] = x - nb[b];
+    if (lane == 63) wtot[b][wid] = x;
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    w_sum += __shfl_xor(w_sum, o);
+    s_sum += __shfl_xor(s_sum, o);
+  }
+  if (lane == 0) {
+    red_w[wid] = w_sum;
+    red_s[wid] = s_sum;
+  }
+  __syncthreads();
+  if (threadIdx.x < kBuckets) {
+    const int b = threadIdx.x;
+    const uint32_t t = wtot[b][0] + wtot[b][1] + wtot[b][2] + wtot[b][3];
+    bbase[b] = t ? atomicAdd(&out->count[b], t) : 0u;
+  }
+  if (threadIdx.x == 64) {
+    const unsigned long long ws = red_w[0] + red_w[1] + red_w[2] + red_w[3];
+    const unsigned long long ss = red_s[0] + red_s[1] + red_s[2] + red_s[3];
+    if (ss) {
+      atomicAdd(&out->wedges, ws);
+      atomicAdd(&out->sources, ss);
+    }
+  }
+  __syncthreads();
+  uint32_t pos[kBuckets];
+#pragma unroll
+  for (int b = 0; b < kBuckets; b++) {
+    pos[b] = bbase[b] + excl[b];
+    for (int w = 0; w < wid; w++) pos[b] += wtot[b][w];
+  }
+#pragma unroll
+  for (int j = 0; j < kPlanItems; j++) {
+    if (bk[j] == 0xFF) continue;
+    const uint32_t a = (uint32_t)(tile + (uint64_t)j * 256 + threadIdx.x);
+    // second read of the row bounds: cheap (cached) and keeps registers low
     const uint32_t h0 = g.hoff[a], h1 = g.hoff[a + 1];
     const uint32_t k = lower_bound_dev(g.hb, h0, h1, hub_start) - h0;
-    U = k ? g.hpsum[h0 + k - 1] : 0u;
-    cnt[a] = k;
-    wedges[a] = U;
-    b = bucket_of(U, lds_cap);
-  }
-  bucket_append(b, a, lists, g.n, out->count);
-  unsigned long long w = U, s = U ? 1ull : 0ull;
-  for (int o = 32; o >= 1; o >>= 1) {
-    w += __shfl_xor(w, o);
-    s += __shfl_xor(s, o);
-  }
-  if (lane_id() == 0 && s) {
-    atomicAdd(&out->wedges, w);
-    atomicAdd(&out->sources, s);
+    SrcRec r;
+    r.a = a;
+    r.key = g.perm[a];
+    r.h0 = h0;
+    r.na = k;
+    r.U = g.hpsum[h0 + k - 1];
+    const uint32_t e0 = g.off[a];
+    r.x1 = g.off[a + 1];
+    r.x0 = e0 + g.below[a];
+    r.da = r.x1 - e0;
+#pragma unroll
+    for (int b = 0; b < kBuckets; b++)
+      if (bk[j] == b) lists[(uint64_t)b * g.n + pos[b]++] = r;
   }
 }
 
-// query: map sources to new ids, explored prefix and an upper bound of the
-// wedges (all of Gamma_b, b explored), one workgroup per query
+// query: map sources to new ids, explored prefix of the row and an upper
+// bound of the wedges (all of Gamma_b for explored b), one workgroup per query
 __global__ __launch_bounds__(256) void query_plan_kernel(GView g, uint32_t hub_start,
                                                          uint32_t lds_cap,
                                                          const int32_t* __restrict__ src,
                                                          const uint32_t* __restrict__ rank,
-                                                         uint32_t nq, uint32_t* __restrict__ qnew,
-                                                         uint32_t* __restrict__ cnt,
-                                                         uint32_t* __restrict__ wedges,
-                                                         uint32_t* __restrict__ lists,
+                                                         uint32_t nq, SrcRec* __restrict__ lists,
                                                          PlanOut* __restrict__ out) {
   __shared__ unsigned long long part[4];
   for (uint32_t q = blockIdx.x; q < nq; q += gridDim.x) {
@@ -134,30 +204,37 @@ __global__ __launch_bounds__(256) void query_plan_kernel(GView g, uint32_t hub_s
     for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o);
     if (lane_id() == 0) part[threadIdx.x >> 6] = sum;
     __syncthreads();
-    if (threadIdx.x < 64) {
-      unsigned long long tot = part[0] + part[1] + part[2] + part[3];
-      uint32_t U = tot > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)tot;
-      int b = bucket_of(U, lds_cap);
-      if (threadIdx.x == 0) {
-        qnew[q] = s;
-        cnt[q] = k;
-        wedges[q] = U;
+    if (threadIdx.x == 0) {
+      const unsigned long long tot = part[0] + part[1] + part[2] + part[3];
+      const uint32_t U = tot > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)tot;
+      const int b = bucket_of(U, lds_cap);
+      if (b >= 0) {
+        SrcRec r;
+        r.a = s;
+        r.key = q;
+        r.h0 = e0;
+        r.na = k;
+        r.U = U;
+        r.x0 = e0;
+        r.x1 = e1;
+        r.da = e1 - e0;
+        const uint32_t pos = atomicAdd(&out->count[b], 1u);
+        lists[(uint64_t)b * nq + pos] = r;
         atomicAdd(&out->wedges, (unsigned long long)U);
-        if (U) atomicAdd(&out->sources, 1ull);
+        atomicAdd(&out->sources, 1ull);
       }
-      bucket_append(threadIdx.x == 0 ? b : -1, q, lists, nq, out->count);
     }
     __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
-// Work lists: which list entries a launch processes.
+// Work lists: which records a launch processes.
 //   phase 0: all; 1: every stride-th (the sample); 2: the others.
 // ---------------------------------------------------------------------------
 
 struct WorkList {
-  const uint32_t* list;
+  const SrcRec* list;
   uint32_t count;
   uint32_t stride;
   int phase;
@@ -169,44 +246,26 @@ __device__ inline uint32_t work_count(const WorkList& w) {
   return w.phase == 1 ? ns : w.count - ns;
 }
 
-__device__ inline uint32_t work_item(const WorkList& w, uint32_t i) {
-  if (w.phase == 0 || w.stride <= 1) return w.list[i];
-  if (w.phase == 1) return w.list[i * w.stride];
+__device__ inline uint32_t work_index(const WorkList& w, uint32_t i) {
+  if (w.phase == 0 || w.stride <= 1) return i;
+  if (w.phase == 1) return i * w.stride;
   const uint32_t s1 = w.stride - 1;
-  return w.list[(i / s1) * w.stride + (i % s1) + 1];
+  return (i / s1) * w.stride + (i % s1) + 1;
 }
 
-// Per-source setup shared by the kernels.
-struct Src {
-  uint32_t a;       // relabelled id
-  uint32_t a_key;   // predict: original id; query: query index
-  uint32_t a_orig;  // original id
-  uint32_t e0, e1;  // row of a in adj (first-order neighbours)
-  uint32_t h0;      // predict: first explored arc in the two-hop list; query: = e0
-  uint32_t na;      // explored arcs
-  uint32_t U;       // wedges (predict: exact; query: upper bound)
-};
+__device__ inline SrcRec load_rec(const WorkList& w, uint32_t i) { return w.list[work_index(w, i)]; }
 
-template <bool kQuery>
-__device__ inline Src load_src(const GView& g, const uint32_t* cnt, const uint32_t* wedges,
-                               const uint32_t* qnew, uint32_t item) {
-  Src s;
-  s.a = kQuery ? qnew[item] : item;
-  s.na = cnt[item];
-  s.U = wedges[item];
-  s.e0 = g.off[s.a];
-  s.e1 = g.off[s.a + 1];
-  s.h0 = kQuery ? s.e0 : g.hoff[s.a];
-  s.a_orig = g.perm[s.a];
-  s.a_key = kQuery ? item : s.a_orig;
-  return s;
+// A record that the whole wave works on, held in scalar registers.
+__device__ inline SrcRec uniform_rec(const SrcRec& r) {
+  return SrcRec{uniform(r.a), uniform(r.key), uniform(r.h0), uniform(r.na),
+                uniform(r.U),   uniform(r.x0),  uniform(r.x1), uniform(r.da)};
 }
 
 // Load the chunk of explored arcs [cb, cb + G) of source s into the group
 // scratch: flat index of its first wedge (excl), position in adj of its first
 // c (start), weight; the chunk covers flat wedges [*lo, *hi).
 template <int G, bool kQuery, bool kW>
-__device__ inline void load_chunk(const GView& g, const Emit& E, const Src& s, uint32_t cb,
+__device__ inline void load_chunk(const GView& g, const Emit& E, const SrcRec& s, uint32_t cb,
                                   uint32_t* s_excl, uint32_t* s_start, uint64_t* s_w,
                                   uint32_t* scan_tmp, uint32_t* lo, uint32_t* hi) {
   const int gl = threadIdx.x & (G - 1);
@@ -226,7 +285,7 @@ __device__ inline void load_chunk(const GView& g, const Emit& E, const Src& s, u
     const uint32_t ex = group_exclusive_scan<G>(len, scan_tmp, &total);
     s_excl[gl] = valid ? ex : kEmpty32;
     *lo = 0;
-    *hi = total;
+    *hi = uniform(total);
   } else {
     uint32_t ex = kEmpty32;
     if (valid) {
@@ -236,26 +295,93 @@ __device__ inline void load_chunk(const GView& g, const Emit& E, const Src& s, u
     }
     s_excl[gl] = ex;
     const uint32_t last = (cb + G < s.na ? cb + G : s.na) - 1;
-    *lo = cb == 0 ? 0u : g.hpsum[s.h0 + cb - 1];
-    *hi = g.hpsum[s.h0 + last];
+    *lo = uniform(cb == 0 ? 0u : g.hpsum[s.h0 + cb - 1]);
+    *hi = uniform(g.hpsum[s.h0 + last]);
   }
   s_start[gl] = start;
   if (kW) s_w[gl] = w;
 }
 
+// Table geometry of a source: P hash partitions, S slots each (load <= 2/3).
+__device__ inline void table_geometry(uint32_t U, uint32_t slots, uint32_t* P, uint32_t* S) {
+  const uint64_t need = ((uint64_t)U * 3 + 1) / 2;
+  if (need <= slots) {
+    *P = 1;
+    *S = need < 16 ? 16u : (uint32_t)need;
+    return;
+  }
+  uint32_t p = (uint32_t)((need + slots - 1) / slots);
+  if (p < 1) p = 1;
+  const uint64_t per = ((uint64_t)U + p - 1) / p;
+  uint64_t s = (per * 3 + 1) / 2;
+  if (s < 16) s = 16;
+  if (s > slots) s = slots;
+  *P = p;
+  *S = (uint32_t)s;
+}
+
+// partition of a key (range reduction of its Fibonacci hash) and its home slot
+__device__ inline uint32_t key_part(uint32_t c, uint32_t P) {
+  return (uint32_t)(((uint64_t)(c * kHashMul) * P) >> 32);
+}
+__device__ inline uint32_t key_slot(uint32_t c, uint32_t S) {
+  const uint32_t x = (c ^ (c >> 15)) * 0x2C1B3C6Du;
+  return (uint32_t)(((uint64_t)(x ^ (x >> 12)) * S) >> 32);
+}
+
 // ---------------------------------------------------------------------------
-// LDS-table accumulation: groups of G lanes (WGS / G groups per workgroup),
-// one source per group at a time, SLOTS table slots per group.
+// Shared pieces of the accumulation kernels
+// ---------------------------------------------------------------------------
+
+constexpr int kWin = 4;  // windows of 64 wedges a wave decodes per round
+
+// Walk one wave's slice of a chunk's flat wedge range [lo, hi): the range is
+// cut into NWG slices of whole windows, one per wave of the group (wig =
+// wave's index in the group).  Per round of kWin windows, fn(c, arc, v) gets
+// each lane's wedges c (kEmpty32 where v is false) and their arcs.
+template <int NWG, int GA, typename Fn>
+__device__ inline void walk_chunk(const GView& g, const uint32_t* excl, const uint32_t* start,
+                                  uint32_t narcs, uint32_t lo, uint32_t hi, int wig, uint8_t* mark,
+                                  Fn&& fn) {
+  const uint64_t per = ((uint64_t)(hi - lo) + NWG - 1) / NWG;
+  const uint64_t q = (per + 63) & ~63ull;
+  const uint64_t f0l = (uint64_t)lo + (uint64_t)wig * q;
+  if (f0l >= hi) return;
+  const uint32_t f0 = (uint32_t)f0l;
+  const uint32_t f1 = (uint32_t)(f0l + q < (uint64_t)hi ? f0l + q : (uint64_t)hi);
+  const uint32_t lane = (uint32_t)lane_id();
+  uint32_t j = uniform((uint32_t)seg_search<GA>(excl, f0));
+  for (uint32_t base = f0; base < f1; base += 64 * kWin) {
+    uint32_t arc[kWin], c[kWin];
+    bool v[kWin];
+#pragma unroll
+    for (int u = 0; u < kWin; u++) {
+      const uint32_t b = base + 64u * u;
+      arc[u] = 0;
+      v[u] = false;
+      uint32_t idx = 0;
+      if (b < f1) {
+        arc[u] = decode_window(excl, narcs, mark, b, j);
+        v[u] = b + lane < f1;
+        if (v[u]) idx = start[arc[u]] + (b + lane - excl[arc[u]]);
+      }
+      c[u] = idx;
+    }
+#pragma unroll
+    for (int u = 0; u < kWin; u++) c[u] = v[u] ? g.adj[c[u]] : kEmpty32;
+    fn(c, arc, v);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// LDS-table accumulation: groups of G lanes (G a multiple of 64; WGS / G
+// groups per workgroup), one source per group at a time, up to SLOTS slots.
 // ---------------------------------------------------------------------------
 
 template <int WGS, int G, int SLOTS, bool kW, int STAGE>
 struct LdsTab {
   static constexpr int NG = WGS / G;
   static constexpr int NW = WGS / 64;
-  uint32_t st_s[NW][STAGE];
-  uint32_t st_a[NW][STAGE];
-  uint32_t st_c[NW][STAGE];
-  uint32_t st_n[NW];
   uint64_t tab[kW ? 1 : NG * SLOTS];
   uint32_t keys[kW ? NG * SLOTS : 1];
   uint64_t vals[kW ? NG * SLOTS : 1];
@@ -264,139 +390,97 @@ struct LdsTab {
   uint64_t w[kW ? NG : 1][kW ? G : 1];
   uint32_t scan_tmp[G > 64 ? G / 64 : 1];
   int ovf[NG];
+  uint8_t mark[NW][64];
+  uint32_t rt_key[NW][64];
+  uint32_t rt_h[NW][64];
+  uint64_t rt_w[kW ? NW : 1][64];
+  uint32_t st_c[NW][STAGE];
+  uint32_t st_h[NW][STAGE];
+  uint32_t st_w2[kW ? NW : 1][kW ? STAGE : 1];
+  uint32_t st_k[NW][STAGE];
+  uint32_t st_d[NW][STAGE];
+  uint32_t so_s[NW][64];
+  uint32_t so_a[NW][64];
+  uint32_t so_c[NW][64];
 };
 
-constexpr int kUnrollGather = 4;  // independent wedge loads in flight per lane
-constexpr int kUnrollScore = 4;   // independent degree loads in flight per lane
-
 template <int WGS, int G, int SLOTS, bool kW, bool kQuery, int STAGE>
-__global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, const uint32_t* __restrict__ cnt,
-                                                      const uint32_t* __restrict__ wedges,
-                                                      const uint32_t* __restrict__ qnew,
-                                                      WorkList wl) {
-  static_assert(G <= 64 || G == WGS, "multi-wave groups span the workgroup");
-  static_assert(STAGE >= 64, "a stage holds at least one wave of survivors");
+__global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, WorkList wl) {
+  static_assert(G % 64 == 0 && (G == 64 || G == WGS), "groups are whole waves");
+  static_assert(STAGE >= 64, "a stage holds at least one wave of entries");
   constexpr int NG = WGS / G;
   __shared__ LdsTab<WGS, G, SLOTS, kW, STAGE> L;
-  const int wv_id = threadIdx.x >> 6;
-  const Stage SG{L.st_s[wv_id], L.st_a[wv_id], L.st_c[wv_id], &L.st_n[wv_id], (uint32_t)STAGE};
-  if (lane_id() == 0) stage_set_count(SG, 0u);
-  const int grp = threadIdx.x / G;
+  const int grp = (int)uniform(threadIdx.x / G);
   const int gl = threadIdx.x & (G - 1);
+  const int wv = threadIdx.x >> 6;
   uint64_t* tab = L.tab + (kW ? 0 : grp * SLOTS);
   uint32_t* keys = L.keys + (kW ? grp * SLOTS : 0);
   uint64_t* vals = L.vals + (kW ? grp * SLOTS : 0);
   uint32_t* s_excl = L.excl[grp];
   uint32_t* s_start = L.start[grp];
   uint64_t* s_w = kW ? L.w[grp] : nullptr;
+  uint8_t* mark = L.mark[wv];
+  mark[lane_id()] = 0;
+  wave_fence();
+  Stage SG{L.st_c[wv], L.st_h[wv], kW ? L.st_w2[wv] : nullptr, L.st_k[wv], L.st_d[wv],
+           (uint32_t)STAGE, L.so_s[wv], L.so_a[wv], L.so_c[wv], 64u};
+  Retry<kW> RT{L.rt_key[wv], L.rt_h[wv], kW ? L.rt_w[wv] : nullptr};
   FpAcc fa;
-  const bool want_dc = needs_dc(E.measure);
-  const uint32_t total = work_count(wl);
+  const uint32_t ts_bits = E.fp_mode ? 0u : E.tau[0];
+  const uint64_t wmin = kW ? min_wsum(E.measure, ts_bits, E.shift) : 1ull;
+  const uint32_t total = uniform(work_count(wl));
   for (uint32_t i = blockIdx.x * NG + grp; i < total; i += gridDim.x * NG) {
-    const Src s = load_src<kQuery>(g, cnt, wedges, qnew, work_item(wl, i));
-    // partitions: P = 2^lgP so that each partition's table is at most half full
-    uint32_t lgP = 0;
-    while (((uint64_t)s.U * 2 >> lgP) > (uint64_t)SLOTS) lgP++;
-    const uint32_t per = (uint32_t)(((uint64_t)s.U + (1u << lgP) - 1) >> lgP);
-    uint32_t lgS = 4;
-    while ((1u << lgS) < 2 * per && (1u << lgS) < (uint32_t)SLOTS) lgS++;
-    const uint32_t S = 1u << lgS, mask = S - 1;
-    const uint32_t da = s.e1 - s.e0;
-    for (uint32_t pass = 0; pass < (1u << lgP); pass++) {
+    const SrcRec s = uniform_rec(load_rec(wl, i));
+    // first batch of first-order neighbours, in flight during accumulation
+    const uint32_t xe = s.x0 + gl;
+    const uint32_t xb = g.adj[xe < s.x1 ? xe : s.x0];
+    uint32_t P, S;
+    table_geometry(s.U, SLOTS, &P, &S);
+    const uint32_t hmin = kW ? 1u : min_count(E.measure, ts_bits, s.da, !kQuery);
+    for (uint32_t pass = 0; pass < P; pass++) {
       for (uint32_t t = gl; t < S; t += G) {
         if (kW) {
           keys[t] = kEmpty32;
           vals[t] = 0;
         } else {
-          tab[t] = kEmpty64;
+          tab[t] = kSlotEmpty;
         }
       }
       if (gl == 0) L.ovf[grp] = 0;
       group_sync<G>();
-      // accumulate the wedges of this source (this partition's keys)
+      bool full = false;
       for (uint32_t cb = 0; cb < s.na; cb += G) {
         uint32_t lo, hi;
         load_chunk<G, kQuery, kW>(g, E, s, cb, s_excl, s_start, s_w, L.scan_tmp, &lo, &hi);
         group_sync<G>();
-        for (uint32_t f0 = lo + gl; f0 < hi; f0 += G * kUnrollGather) {
-          uint32_t cv[kUnrollGather];
-          uint64_t wv[kUnrollGather];
+        const uint32_t narcs = s.na - cb < (uint32_t)G ? s.na - cb : (uint32_t)G;
+        walk_chunk<G / 64, G>(g, s_excl, s_start, narcs, lo, hi, (int)uniform(gl >> 6), mark,
+                              [&](const uint32_t (&c)[kWin], const uint32_t (&arc)[kWin],
+                                  const bool (&v)[kWin]) {
 #pragma unroll
-          for (int u = 0; u < kUnrollGather; u++) {
-            const uint32_t f = f0 + (uint32_t)(u * G);
-            cv[u] = kEmpty32;
-            wv[u] = 0;
-            if (f < hi) {
-              const int jj = seg_search<G>(s_excl, f);
-              cv[u] = g.adj[s_start[jj] + (f - s_excl[jj])];
-              if (kW) wv[u] = s_w[jj];
-            }
+          for (int u = 0; u < kWin; u++) {
+            bool live = v[u];
+            if (kQuery) live = live & (c[u] != s.a);
+            if (P > 1) live = live & (key_part(c[u], P) == pass);
+            const uint64_t w = kW ? s_w[arc[u]] : 0ull;
+            const bool ok = tab_insert<kW>(tab, keys, vals, S, live ? c[u] : kEmpty32,
+                                           key_slot(c[u], S), w, RT);
+            full = full | !ok;
           }
-#pragma unroll
-          for (int u = 0; u < kUnrollGather; u++) {
-            const uint32_t c = cv[u];
-            if (c == kEmpty32 || (kQuery && c == s.a)) continue;
-            const uint32_t hc = c * kHashMul;
-            if (lgP && (hc >> (32 - lgP)) != pass) continue;
-            uint32_t h = (hc << lgP) >> (32 - lgS);
-            bool done = false;
-            if (kW) {
-              for (uint32_t probe = 0; probe < S; probe++) {
-                const uint32_t old = atomicCAS(&keys[h], kEmpty32, c);
-                if (old == kEmpty32 || old == c) {
-                  atomicAdd((unsigned long long*)&vals[h], (unsigned long long)wv[u]);
-                  done = true;
-                  break;
-                }
-                h = (h + 1) & mask;
-              }
-            } else {
-              const uint64_t want = ((uint64_t)c << 32) | 1ull;
-              for (uint32_t probe = 0; probe < S; probe++) {
-                const uint64_t old = atomicCAS((unsigned long long*)&tab[h], kEmpty64, want);
-                if (old == kEmpty64) {
-                  done = true;
-                  break;
-                }
-                if ((uint32_t)(old >> 32) == c) {
-                  atomicAdd((unsigned long long*)&tab[h], 1ull);
-                  done = true;
-                  break;
-                }
-                h = (h + 1) & mask;
-              }
-            }
-            if (!done) L.ovf[grp] = 1;
-          }
-        }
+        });
+        full = full | !retry_drain<kW>(tab, keys, vals, S, RT);
         group_sync<G>();
       }
-      // first-order neighbours are not candidates (predict: only ids > a can be keys)
-      const uint32_t x0 = kQuery ? s.e0 : s.e0 + g.below[s.a];
-      for (uint32_t e = x0 + gl; e < s.e1; e += G) {
-        const uint32_t b = g.adj[e];
-        const uint32_t hb = b * kHashMul;
-        if (lgP && (hb >> (32 - lgP)) != pass) continue;
-        uint32_t h = (hb << lgP) >> (32 - lgS);
-        for (uint32_t probe = 0; probe < S; probe++) {
-          if (kW) {
-            const uint32_t k = keys[h];
-            if (k == b) {
-              vals[h] = 0;
-              break;
-            }
-            if (k == kEmpty32) break;
-          } else {
-            const uint64_t v = tab[h];
-            const uint32_t k = (uint32_t)(v >> 32);
-            if (k == b) {
-              tab[h] = (uint64_t)b << 32;
-              break;
-            }
-            if (k == kEmpty32) break;
-          }
-          h = (h + 1) & mask;
-        }
+      if (full) L.ovf[grp] = 1;
+      // first-order neighbours are not candidates: flag their entries
+      for (uint32_t e0 = s.x0; e0 < s.x1; e0 += G) {
+        const uint32_t e = e0 + gl;
+        const bool in = e < s.x1;
+        const uint32_t b = e0 == s.x0 ? xb : g.adj[in ? e : s.x0];
+        bool act = in;
+        if (P > 1) act = act && key_part(b, P) == pass;
+        if (kW) tab_block_weight(keys, vals, S, b, key_slot(b, S), act);
+        else tab_block_count(tab, S, b, key_slot(b, S), act);
       }
       group_sync<G>();
       if (L.ovf[grp]) {
@@ -404,8 +488,8 @@ __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, const uin
         if (gl == 0) {
           const uint32_t slot = atomicAdd(E.ovf_count, 1u);
           if (slot < E.ovf_cap) {
-            E.ovf[2 * slot] = kQuery ? s.a_key : s.a;
-            E.ovf[2 * slot + 1] = pass | (lgP << 8);
+            static_cast<SrcRec*>(E.ovf_rec)[slot] = s;
+            E.ovf[slot] = pass | (P << 8);
           } else {
             atomicOr(E.err, kErrOvfList);
           }
@@ -413,42 +497,247 @@ __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, const uin
         group_sync<G>();
         break;
       }
-      // score every key of this partition
-      for (uint32_t t0 = gl; t0 < S; t0 += G * kUnrollScore) {
-        uint32_t cv[kUnrollScore], hv[kUnrollScore], dv[kUnrollScore];
-        uint64_t wv[kUnrollScore];
-        bool ok[kUnrollScore];
-#pragma unroll
-        for (int u = 0; u < kUnrollScore; u++) {
-          const uint32_t t = t0 + (uint32_t)(u * G);
-          ok[u] = false;
-          cv[u] = 0;
-          hv[u] = 0;
-          wv[u] = 0;
-          if (t < S) {
-            if (kW) {
-              cv[u] = keys[t];
-              wv[u] = vals[t];
-              ok[u] = cv[u] != kEmpty32 && wv[u] != 0;
-            } else {
-              const uint64_t v = tab[t];
-              cv[u] = (uint32_t)(v >> 32);
-              hv[u] = (uint32_t)v;
-              ok[u] = cv[u] != kEmpty32 && hv[u] != 0;
-            }
-          }
+      // stage every key of this partition that can still reach tau
+      for (uint32_t t0 = 0; t0 < S; t0 += G) {
+        const uint32_t t = t0 + gl;
+        const uint32_t tc = t < S ? t : 0u;
+        uint32_t c, h = 0;
+        uint64_t wsum = 0;
+        bool ok;
+        if (kW) {
+          c = keys[tc];
+          wsum = vals[tc];
+          ok = t < S && c != kEmpty32 && (wsum >> 63) == 0 && wsum >= wmin;
+        } else {
+          const uint64_t v = tab[tc];
+          c = (uint32_t)v;
+          h = (uint32_t)(v >> 32);
+          ok = t < S && c != kEmpty32 && (h & kBlocked) == 0 && h >= hmin;
         }
-#pragma unroll
-        for (int u = 0; u < kUnrollScore; u++) dv[u] = (ok[u] && want_dc) ? g.deg[cv[u]] : 0u;
-#pragma unroll
-        for (int u = 0; u < kUnrollScore; u++)
-          emit_one<kQuery>(E, g, SG, ok[u], s.a_orig, s.a_key, da, ok[u] ? cv[u] : 0u, dv[u],
-                           hv[u], wv[u], fa);
+        stage_add<kQuery, kW>(E, g, SG, ok, c, h, wsum, s.key, s.da, fa);
       }
       group_sync<G>();
     }
   }
-  if (!E.fp_mode) stage_flush(E, SG);
+  stage_drain<kQuery, kW>(E, g, SG, fa);
+  flush_fp(E, fa);
+}
+
+// ---------------------------------------------------------------------------
+// Batched LDS accumulation for small sources (prediction orientation): one
+// workgroup takes B consecutive sources of a bucket and accumulates all their
+// wedges into one table keyed by (position in the batch, c), so the batch pays
+// the dependent global round trips (records, arcs, wedges, first-order rows)
+// once instead of once per source.  Needs ids below 2^24 and B <= 64.
+// ---------------------------------------------------------------------------
+
+constexpr uint32_t kBatchIdBits = 24;
+constexpr uint32_t kBatchIdMask = (1u << kBatchIdBits) - 1;
+
+template <int WGS, int B, int SLOTS, bool kW, int STAGE>
+struct BatchTab {
+  static constexpr int NW = WGS / 64;
+  uint64_t tab[kW ? 1 : SLOTS];
+  uint32_t keys[kW ? SLOTS : 1];
+  uint64_t vals[kW ? SLOTS : 1];
+  uint32_t excl[WGS];
+  uint32_t start[WGS];
+  uint32_t srcof[WGS];
+  uint64_t w[kW ? WGS : 1];
+  SrcRec rec[B];
+  uint32_t arcoff[B + 1];  // prefix of explored arcs
+  uint32_t wedoff[B + 1];  // prefix of wedges
+  uint32_t xoff[B + 1];    // prefix of first-order neighbours to exclude
+  uint32_t hmin[B];
+  int ovf;
+  uint8_t mark[NW][64];
+  uint32_t rt_key[NW][64];
+  uint32_t rt_h[NW][64];
+  uint64_t rt_w[kW ? NW : 1][64];
+  uint32_t st_c[NW][STAGE];
+  uint32_t st_h[NW][STAGE];
+  uint32_t st_w2[kW ? NW : 1][kW ? STAGE : 1];
+  uint32_t st_k[NW][STAGE];
+  uint32_t st_d[NW][STAGE];
+  uint32_t so_s[NW][64];
+  uint32_t so_a[NW][64];
+  uint32_t so_c[NW][64];
+};
+
+// last index i in [0, B) with off[i] <= q (off non-decreasing, off[0] == 0 <= q)
+template <int B>
+__device__ inline int batch_search(const uint32_t* off, uint32_t q) {
+  int lo = 0;
+#pragma unroll
+  for (int step = 32; step >= 1; step >>= 1)
+    if (step < B && lo + step < B && off[lo + step] <= q) lo += step;
+  return lo;
+}
+
+template <int WGS, int B, int SLOTS, bool kW, int STAGE>
+__global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkList wl) {
+  static_assert(B <= 64 && B >= 1, "batch fits in one wave");
+  constexpr int NW = WGS / 64;
+  __shared__ BatchTab<WGS, B, SLOTS, kW, STAGE> L;
+  const int tid = threadIdx.x;
+  const int wv = tid >> 6;
+  uint8_t* mark = L.mark[wv];
+  mark[lane_id()] = 0;
+  wave_fence();
+  Stage SG{L.st_c[wv], L.st_h[wv], kW ? L.st_w2[wv] : nullptr, L.st_k[wv], L.st_d[wv],
+           (uint32_t)STAGE, L.so_s[wv], L.so_a[wv], L.so_c[wv], 64u};
+  Retry<kW> RT{L.rt_key[wv], L.rt_h[wv], kW ? L.rt_w[wv] : nullptr};
+  FpAcc fa;
+  const uint32_t ts_bits = E.fp_mode ? 0u : E.tau[0];
+  const uint64_t wmin = kW ? min_wsum(E.measure, ts_bits, E.shift) : 1ull;
+  const uint32_t total = uniform(work_count(wl));
+  const uint32_t nbatch = (total + B - 1) / B;
+  for (uint32_t bi = blockIdx.x; bi < nbatch; bi += gridDim.x) {
+    const uint32_t i0 = bi * B;
+    const uint32_t nb = total - i0 < (uint32_t)B ? total - i0 : (uint32_t)B;
+    // records and their prefix sums (first wave)
+    if (tid < 64) {
+      SrcRec r{};
+      uint32_t na = 0, U = 0, nx = 0;
+      if (tid < (int)nb) {
+        r = load_rec(wl, i0 + tid);
+        na = r.na;
+        U = r.U;
+        nx = r.x1 - r.x0;
+        L.rec[tid] = r;
+        L.hmin[tid] = kW ? 1u : min_count(E.measure, ts_bits, r.da, true);
+      }
+      uint32_t xa = na, xu = U, xx = nx;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t ya = __shfl_up(xa, o, 64), yu = __shfl_up(xu, o, 64), yx = __shfl_up(xx, o, 64);
+        if (tid >= o) {
+          xa += ya;
+          xu += yu;
+          xx += yx;
+        }
+      }
+      if (tid < B) {
+        L.arcoff[tid] = xa - na;
+        L.wedoff[tid] = xu - U;
+        L.xoff[tid] = xx - nx;
+      }
+      if (tid == B - 1) {
+        L.arcoff[B] = xa;
+        L.wedoff[B] = xu;
+        L.xoff[B] = xx;
+      }
+      if (tid == 0) L.ovf = 0;
+    }
+    __syncthreads();
+    const uint32_t NA = uniform(L.arcoff[B]), UT = uniform(L.wedoff[B]), NX = uniform(L.xoff[B]);
+    uint32_t S = (uint32_t)(((uint64_t)UT * 3 + 1) / 2);
+    if (S < 16) S = 16;
+    if (S > (uint32_t)SLOTS) S = SLOTS;  // cannot happen within the bucket's bounds
+    // first batch of first-order neighbours, in flight during accumulation
+    const uint32_t xq = (uint32_t)tid < NX ? (uint32_t)tid : 0u;
+    const uint32_t xbi = NX ? (uint32_t)batch_search<B>(L.xoff, xq) : 0u;
+    const uint32_t xb = NX ? g.adj[L.rec[xbi].x0 + (xq - L.xoff[xbi])] : 0u;
+    for (uint32_t t = tid; t < S; t += WGS) {
+      if (kW) {
+        L.keys[t] = kEmpty32;
+        L.vals[t] = 0;
+      } else {
+        L.tab[t] = kSlotEmpty;
+      }
+    }
+    __syncthreads();
+    bool full = false;
+    for (uint32_t cb = 0; cb < NA; cb += WGS) {
+      const uint32_t q = cb + tid;
+      const bool qin = q < NA;
+      const uint32_t qc = qin ? q : cb;
+      const uint32_t si = (uint32_t)batch_search<B>(L.arcoff, qc);
+      const uint32_t local = qc - L.arcoff[si];
+      const uint32_t e = L.rec[si].h0 + local;
+      const uint32_t start = g.hstart[e];
+      const uint32_t prev = local == 0 ? 0u : g.hpsum[e - 1];
+      uint64_t w = 0;
+      if (kW) w = weight_of(E.measure, g.deg[g.hb[e]], E.shift);
+      L.excl[tid] = qin ? L.wedoff[si] + prev : kEmpty32;
+      L.start[tid] = start;
+      L.srcof[tid] = si;
+      if (kW) L.w[tid] = w;
+      // flat wedge range of this chunk
+      const uint32_t qlast = (cb + WGS < NA ? cb + WGS : NA) - 1;
+      const uint32_t sl = (uint32_t)batch_search<B>(L.arcoff, qlast);
+      const uint32_t hi = uniform(L.wedoff[sl] + g.hpsum[L.rec[sl].h0 + (qlast - L.arcoff[sl])]);
+      __syncthreads();
+      const uint32_t lo = uniform(L.excl[0]);
+      const uint32_t narcs = NA - cb < (uint32_t)WGS ? NA - cb : (uint32_t)WGS;
+      walk_chunk<NW, WGS>(g, L.excl, L.start, narcs, lo, hi, (int)uniform(wv), mark,
+                          [&](const uint32_t (&c)[kWin], const uint32_t (&arc)[kWin],
+                              const bool (&v)[kWin]) {
+#pragma unroll
+        for (int u = 0; u < kWin; u++) {
+          const uint32_t k = (L.srcof[arc[u]] << kBatchIdBits) | (c[u] & kBatchIdMask);
+          const uint64_t w = kW ? L.w[arc[u]] : 0ull;
+          const bool ok = tab_insert<kW>(L.tab, L.keys, L.vals, S, v[u] ? k : kEmpty32, key_slot(k, S), w, RT);
+          full = full | !ok;
+        }
+      });
+      full = full | !retry_drain<kW>(L.tab, L.keys, L.vals, S, RT);
+      __syncthreads();
+    }
+    if (full) L.ovf = 1;
+    // first-order neighbours are not candidates: flag their entries
+    for (uint32_t x0 = 0; x0 < NX; x0 += WGS) {
+      const uint32_t x = x0 + tid;
+      const bool in = x < NX;
+      uint32_t b = xb, i = xbi;
+      if (x0 != 0) {
+        const uint32_t xc = in ? x : x0;
+        i = (uint32_t)batch_search<B>(L.xoff, xc);
+        b = g.adj[L.rec[i].x0 + (xc - L.xoff[i])];
+      }
+      const uint32_t key = (i << kBatchIdBits) | b;
+      if (kW) tab_block_weight(L.keys, L.vals, S, key, key_slot(key, S), in);
+      else tab_block_count(L.tab, S, key, key_slot(key, S), in);
+    }
+    __syncthreads();
+    if (L.ovf) {
+      // a full table: every source of the batch goes to the global path whole
+      if (tid < (int)nb) {
+        const uint32_t slot = atomicAdd(E.ovf_count, 1u);
+        if (slot < E.ovf_cap) {
+          static_cast<SrcRec*>(E.ovf_rec)[slot] = L.rec[tid];
+          E.ovf[slot] = 0u | (1u << 8);
+        } else {
+          atomicOr(E.err, kErrOvfList);
+        }
+      }
+      __syncthreads();
+      continue;
+    }
+    // stage every key that can still reach tau
+    for (uint32_t t0 = 0; t0 < S; t0 += WGS) {
+      const uint32_t t = t0 + tid;
+      const uint32_t tc = t < S ? t : 0u;
+      uint32_t key, h = 0;
+      uint64_t wsum = 0;
+      bool ok;
+      if (kW) {
+        key = L.keys[tc];
+        wsum = L.vals[tc];
+        ok = t < S && key != kEmpty32 && (wsum >> 63) == 0 && wsum >= wmin;
+      } else {
+        const uint64_t v = L.tab[tc];
+        key = (uint32_t)v;
+        h = (uint32_t)(v >> 32);
+        ok = t < S && key != kEmpty32 && (h & kBlocked) == 0;
+      }
+      const uint32_t i = ok ? key >> kBatchIdBits : 0u;
+      if (!kW) ok = ok && h >= L.hmin[i];
+      stage_add<false, kW>(E, g, SG, ok, key & kBatchIdMask, h, wsum, L.rec[i].key, L.rec[i].da, fa);
+    }
+    __syncthreads();
+  }
+  stage_drain<false, kW>(E, g, SG, fa);
   flush_fp(E, fa);
 }
 
@@ -460,27 +749,33 @@ __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, const uin
 // ---------------------------------------------------------------------------
 
 struct SpaItem {
-  const uint32_t* ovf;  // if non-null: (source, pass | lgP << 8) records
+  const uint32_t* ovf;  // if non-null: overflow entries (pass | P << 8) ...
+  const SrcRec* recs;   // ... and their source records
   uint32_t ovf_begin, ovf_end;
 };
 
 constexpr int kSpaThreads = 1024;
+constexpr int kSpaStage = 128;
 
 template <bool kW, bool kQuery>
-__global__ __launch_bounds__(kSpaThreads) void acc_spa_kernel(GView g, Emit E, const uint32_t* __restrict__ cnt,
-                                                      const uint32_t* __restrict__ wedges,
-                                                      const uint32_t* __restrict__ qnew,
-                                                      WorkList wl, SpaItem ov, char* spa_acc,
-                                                      uint32_t* spa_keys) {
+__global__ __launch_bounds__(kSpaThreads) void acc_spa_kernel(GView g, Emit E, WorkList wl,
+                                                              SpaItem ov, char* spa_acc,
+                                                              uint32_t* spa_keys) {
   constexpr int T = kSpaThreads;
-  constexpr int STAGE = 128;
-  __shared__ uint32_t s_excl[T], s_start[T], scan_tmp[T / 64];
+  constexpr int NW = T / 64;
+  __shared__ uint32_t s_excl[T], s_start[T], scan_tmp[NW];
   __shared__ uint64_t s_w[kW ? T : 1];
   __shared__ uint32_t nkeys;
-  __shared__ uint32_t st_s[T / 64][STAGE], st_a[T / 64][STAGE], st_c[T / 64][STAGE], st_n[T / 64];
-  const int wv_id = threadIdx.x >> 6;
-  const Stage SG{st_s[wv_id], st_a[wv_id], st_c[wv_id], &st_n[wv_id], (uint32_t)STAGE};
-  if (lane_id() == 0) stage_set_count(SG, 0u);
+  __shared__ uint8_t s_mark[NW][64];
+  __shared__ uint32_t st_c[NW][kSpaStage], st_h[NW][kSpaStage], st_k[NW][kSpaStage],
+      st_d[NW][kSpaStage], st_w2[kW ? NW : 1][kW ? kSpaStage : 1];
+  __shared__ uint32_t so_s[NW][64], so_a[NW][64], so_c[NW][64];
+  const int wv = threadIdx.x >> 6;
+  uint8_t* mark = s_mark[wv];
+  mark[lane_id()] = 0;
+  wave_fence();
+  Stage SG{st_c[wv], st_h[wv], kW ? st_w2[wv] : nullptr, st_k[wv], st_d[wv], (uint32_t)kSpaStage,
+           so_s[wv], so_a[wv], so_c[wv], 64u};
   // one 8-byte-per-vertex accumulator slab per workgroup, whatever the measure:
   // counts use its first half, so every slab stays zero between calls
   char* slab = spa_acc + (uint64_t)blockIdx.x * g.n * 8;
@@ -488,56 +783,46 @@ __global__ __launch_bounds__(kSpaThreads) void acc_spa_kernel(GView g, Emit E, c
   unsigned long long* HW = reinterpret_cast<unsigned long long*>(slab);
   uint32_t* K = spa_keys + (uint64_t)blockIdx.x * g.n;
   FpAcc fa;
-  const bool want_dc = needs_dc(E.measure);
+  const uint32_t ts_bits = E.fp_mode ? 0u : E.tau[0];
+  const uint64_t wmin = kW ? min_wsum(E.measure, ts_bits, E.shift) : 1ull;
   const uint32_t total = ov.ovf ? (ov.ovf_end - ov.ovf_begin) : work_count(wl);
   for (uint32_t i = blockIdx.x; i < total; i += gridDim.x) {
-    uint32_t item, p0 = 0, lgP = 0;
+    SrcRec s;
+    uint32_t p0 = 0, P = 1;
     if (ov.ovf) {
-      item = ov.ovf[2 * (ov.ovf_begin + i)];
-      const uint32_t pl = ov.ovf[2 * (ov.ovf_begin + i) + 1];
+      s = uniform_rec(ov.recs[ov.ovf_begin + i]);
+      const uint32_t pl = uniform(ov.ovf[ov.ovf_begin + i]);
       p0 = pl & 0xFFu;
-      lgP = pl >> 8;
+      P = pl >> 8;
     } else {
-      item = work_item(wl, i);
+      s = uniform_rec(load_rec(wl, i));
     }
-    const Src s = load_src<kQuery>(g, cnt, wedges, qnew, item);
-    const uint32_t da = s.e1 - s.e0;
+    const uint32_t hmin = kW ? 1u : min_count(E.measure, ts_bits, s.da, !kQuery);
     if (threadIdx.x == 0) nkeys = 0;
     __syncthreads();
     for (uint32_t cb = 0; cb < s.na; cb += T) {
       uint32_t lo, hi;
       load_chunk<T, kQuery, kW>(g, E, s, cb, s_excl, s_start, s_w, scan_tmp, &lo, &hi);
       __syncthreads();
-      for (uint32_t f0 = lo + threadIdx.x; f0 < hi; f0 += T * kUnrollGather) {
-        uint32_t cv[kUnrollGather];
-        uint64_t wv[kUnrollGather];
+      const uint32_t narcs = s.na - cb < (uint32_t)T ? s.na - cb : (uint32_t)T;
+      walk_chunk<NW, T>(g, s_excl, s_start, narcs, lo, hi, (int)uniform(wv), mark,
+                        [&](const uint32_t (&c)[kWin], const uint32_t (&arc)[kWin],
+                            const bool (&v)[kWin]) {
 #pragma unroll
-        for (int u = 0; u < kUnrollGather; u++) {
-          const uint32_t f = f0 + (uint32_t)(u * T);
-          cv[u] = kEmpty32;
-          wv[u] = 0;
-          if (f < hi) {
-            const int jj = seg_search<T>(s_excl, f);
-            cv[u] = g.adj[s_start[jj] + (f - s_excl[jj])];
-            if (kW) wv[u] = s_w[jj];
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < kUnrollGather; u++) {
-          const uint32_t c = cv[u];
-          if (c == kEmpty32 || (kQuery && c == s.a)) continue;
-          if (lgP && ((c * kHashMul) >> (32 - lgP)) < p0) continue;
+        for (int u = 0; u < kWin; u++) {
+          if (!v[u] || (kQuery && c[u] == s.a)) continue;
+          if (P > 1 && key_part(c[u], P) < p0) continue;
           bool first;
-          if (kW) first = atomicAdd(&HW[c], (unsigned long long)wv[u]) == 0ull;
-          else first = atomicAdd(&H[c], 1u) == 0u;
+          if (kW) first = atomicAdd(&HW[c[u]], (unsigned long long)s_w[arc[u]]) == 0ull;
+          else first = atomicAdd(&H[c[u]], 1u) == 0u;
           if (first)
-            __hip_atomic_store(&K[atomicAdd(&nkeys, 1u)], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&K[atomicAdd(&nkeys, 1u)], c[u], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
         }
-      }
+      });
       __syncthreads();
     }
-    const uint32_t x0 = kQuery ? s.e0 : s.e0 + g.below[s.a];
-    for (uint32_t e = x0 + threadIdx.x; e < s.e1; e += T) {
+    for (uint32_t e = s.x0 + threadIdx.x; e < s.x1; e += T) {
       const uint32_t b = g.adj[e];
       if (kW) __hip_atomic_store(&HW[b], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       else __hip_atomic_store(&H[b], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -545,28 +830,27 @@ __global__ __launch_bounds__(kSpaThreads) void acc_spa_kernel(GView g, Emit E, c
     __threadfence();
     __syncthreads();
     const uint32_t nk = nkeys;
-    for (uint32_t t = threadIdx.x; t < ((nk + 63) & ~63u); t += T) {
-      const bool in = t < nk;
-      uint32_t c = 0, h = 0, dc = 0;
+    for (uint32_t t0 = 0; t0 < nk; t0 += T) {
+      const uint32_t t = t0 + threadIdx.x;
+      uint32_t c = 0, h = 0;
       uint64_t wsum = 0;
-      bool valid = false;
-      if (in) {
+      bool ok = false;
+      if (t < nk) {
         c = __hip_atomic_load(&K[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (kW) {
           wsum = __hip_atomic_exchange(&HW[c], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          valid = wsum != 0;
+          ok = wsum != 0 && wsum >= wmin;
         } else {
           h = __hip_atomic_exchange(&H[c], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          valid = h != 0;
+          ok = h != 0 && h >= hmin;
         }
-        if (valid && want_dc) dc = g.deg[c];
       }
-      emit_one<kQuery>(E, g, SG, valid, s.a_orig, s.a_key, da, c, dc, h, wsum, fa);
+      stage_add<kQuery, kW>(E, g, SG, ok, c, h, wsum, s.key, s.da, fa);
     }
     __threadfence();
     __syncthreads();
   }
-  if (!E.fp_mode) stage_flush(E, SG);
+  stage_drain<kQuery, kW>(E, g, SG, fa);
   flush_fp(E, fa);
 }
 
@@ -621,19 +905,35 @@ __global__ __launch_bounds__(256) void sel_hist_kernel(const uint32_t* __restric
     if (lh[i]) atomicAdd(&hist[i], lh[i]);
 }
 
+// Find the digit whose bin holds the k_rem-th largest key: 64 threads each
+// sum 32 bins (from the top), a wave scan locates the thread, which then
+// walks its own 32 bins.
 __global__ __launch_bounds__(64) void sel_pick_kernel(SelState* st, int step, uint32_t* hist) {
   if (st->done) return;
   int word, shift, bits;
   step_geom(step, &word, &shift, &bits);
-  if (threadIdx.x == 0) {
-    const unsigned long long k = st->k_rem;
-    unsigned long long above = 0;
-    int d = (1 << bits) - 1;
-    for (; d >= 0; d--) {
+  const int nbins = 1 << bits;
+  const int per = nbins / 64;
+  const int t = threadIdx.x;
+  const int top = nbins - 1 - t * per;  // this thread's bins: top, top - 1, ..., top - per + 1
+  unsigned long long sum = 0;
+  for (int j = 0; j < per; j++) sum += hist[top - j];
+  unsigned long long incl = sum;
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned long long y = __shfl_up(incl, o, 64);
+    if (t >= o) incl += y;
+  }
+  const unsigned long long k = st->k_rem;
+  const uint64_t hit = __ballot(incl >= k);
+  const int owner = hit ? __ffsll((unsigned long long)hit) - 1 : 63;
+  if (t == owner) {
+    unsigned long long above = incl - sum;
+    int d = top;
+    for (int j = 0; j < per; j++, d--) {
       if (above + hist[d] >= k) break;
       above += hist[d];
     }
-    if (d < 0) d = 0;  // cannot happen when n_cur >= k
+    if (d < top - per + 1) d = top - per + 1;
     st->digit = (uint32_t)d;
     st->take_all = (above + hist[d] == k) ? 1u : 0u;
     st->k_rem = k - above;
@@ -641,7 +941,7 @@ __global__ __launch_bounds__(64) void sel_pick_kernel(SelState* st, int step, ui
     st->n_next = 0;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < 2048; i += 64) hist[i] = 0;
+  for (int i = t; i < 2048; i += 64) hist[i] = 0;
 }
 
 constexpr int kSelItems = 16;  // elements per thread per tile of the partition
@@ -857,27 +1157,48 @@ static AccConfig acc_config(const lp_graph* g) {
 // Launch the accumulation of one work list in the given bucket.
 template <bool kW, bool kQuery>
 static lp_status launch_bucket(lp_graph* g, int bucket, const GView& gv, const Emit& E,
-                               const uint32_t* cnt, const uint32_t* wedges, const uint32_t* qnew,
                                WorkList wl, uint64_t nitems, hipStream_t st) {
   if (nitems == 0) return LP_OK;
   const unsigned cus = (unsigned)num_cus();
+  if (!kQuery && g->n <= (int64_t)kBatchIdMask + 1 && bucket <= kBucketMid1) {
+    // batches: Tiny 48 sources (<= 1536 wedges), Small 8 (<= 2048), Mid1 2 (<= 2048)
+    switch (bucket) {
+      case kBucketTiny:
+        hipLaunchKernelGGL((acc_batch_kernel<256, 48, 3072, kW, 128>),
+                           dim3(grid_for((nitems + 47) / 48, 1, cus * 8)), dim3(256), 0, st, gv, E, wl);
+        break;
+      case kBucketSmall:
+        hipLaunchKernelGGL((acc_batch_kernel<256, 8, 3072, kW, 128>),
+                           dim3(grid_for((nitems + 7) / 8, 1, cus * 8)), dim3(256), 0, st, gv, E, wl);
+        break;
+      default:
+        hipLaunchKernelGGL((acc_batch_kernel<256, 2, 3072, kW, 128>),
+                           dim3(grid_for((nitems + 1) / 2, 1, cus * 8)), dim3(256), 0, st, gv, E, wl);
+        break;
+    }
+    LP_HIP(hipGetLastError());
+    return LP_OK;
+  }
   switch (bucket) {
     case kBucketTiny:
-      hipLaunchKernelGGL((acc_lds_kernel<256, 16, 64, kW, kQuery, 256>), dim3(grid_for(nitems, 16, cus * 16)),
-                         dim3(256), 0, st, gv, E, cnt, wedges, qnew, wl);
+      hipLaunchKernelGGL((acc_lds_kernel<256, 64, 48, kW, kQuery, 128>),
+                         dim3(grid_for(nitems, 4, cus * 16)), dim3(256), 0, st, gv, E, wl);
       break;
     case kBucketSmall:
-      hipLaunchKernelGGL((acc_lds_kernel<256, 64, 512, kW, kQuery, 256>), dim3(grid_for(nitems, 4, cus * 16)),
-                         dim3(256), 0, st, gv, E, cnt, wedges, qnew, wl);
+      hipLaunchKernelGGL((acc_lds_kernel<256, 64, 384, kW, kQuery, 128>),
+                         dim3(grid_for(nitems, 4, cus * 16)), dim3(256), 0, st, gv, E, wl);
       break;
-    case kBucketMid:
-      hipLaunchKernelGGL((acc_lds_kernel<256, 256, 4096, kW, kQuery, kW ? 256 : 112>), dim3(grid_for(nitems, 1, cus * 8)),
-                         dim3(256), 0, st, gv, E, cnt, wedges, qnew, wl);
+    case kBucketMid1:
+      hipLaunchKernelGGL((acc_lds_kernel<128, 128, 1536, kW, kQuery, 128>),
+                         dim3(grid_for(nitems, 1, cus * 16)), dim3(128), 0, st, gv, E, wl);
+      break;
+    case kBucketMid2:
+      hipLaunchKernelGGL((acc_lds_kernel<512, 512, kW ? 4608 : 6144, kW, kQuery, 64>),
+                         dim3(grid_for(nitems, 1, cus * 4)), dim3(512), 0, st, gv, E, wl);
       break;
     case kBucketLarge:
-      hipLaunchKernelGGL((acc_lds_kernel<1024, 1024, kW ? 8192 : 16384, kW, kQuery, 64>),
-                         dim3(grid_for(nitems, 1, cus * 2)), dim3(1024), 0, st, gv, E, cnt, wedges,
-                         qnew, wl);
+      hipLaunchKernelGGL((acc_lds_kernel<1024, 1024, kW ? 7680 : 14336, kW, kQuery, 64>),
+                         dim3(grid_for(nitems, 1, cus * 2)), dim3(1024), 0, st, gv, E, wl);
       break;
     default:
       return set_error(LP_ERR_INVALID_ARGUMENT, "bad bucket");
@@ -887,9 +1208,8 @@ static lp_status launch_bucket(lp_graph* g, int bucket, const GView& gv, const E
 }
 
 template <bool kW, bool kQuery>
-static lp_status launch_spa(lp_graph* g, const GView& gv, const Emit& E, const uint32_t* cnt,
-                            const uint32_t* wedges, const uint32_t* qnew, WorkList wl,
-                            SpaItem ov, uint64_t nitems, hipStream_t st) {
+static lp_status launch_spa(lp_graph* g, const GView& gv, const Emit& E, WorkList wl, SpaItem ov,
+                            uint64_t nitems, hipStream_t st) {
   if (nitems == 0) return LP_OK;
   AccConfig cfg = acc_config(g);
   const size_t n = (size_t)g->n;
@@ -906,19 +1226,19 @@ static lp_status launch_spa(lp_graph* g, const GView& gv, const Emit& E, const u
   char* base = w.global_tab.as<char>();
   uint32_t* spa_keys = reinterpret_cast<uint32_t*>(base + (size_t)cfg.spa_wgs * n * 8);
   const unsigned wgs = (unsigned)std::min<uint64_t>(cfg.spa_wgs, nitems);
-  hipLaunchKernelGGL((acc_spa_kernel<kW, kQuery>), dim3(wgs), dim3(kSpaThreads), 0, st, gv, E, cnt,
-                     wedges, qnew, wl, ov, base, spa_keys);
+  hipLaunchKernelGGL((acc_spa_kernel<kW, kQuery>), dim3(wgs), dim3(kSpaThreads), 0, st, gv, E, wl,
+                     ov, base, spa_keys);
   LP_HIP(hipGetLastError());
   return LP_OK;
 }
 
 // The whole accumulation for one phase (all buckets, then overflow records).
 template <bool kW, bool kQuery>
-static lp_status run_phase(lp_graph* g, const GView& gv, const Emit& E, const uint32_t* cnt,
-                           const uint32_t* wedges, const uint32_t* qnew, const uint32_t* lists,
+static lp_status run_phase(lp_graph* g, const GView& gv, const Emit& E, const SrcRec* lists,
                            uint64_t list_stride, const uint32_t* counts_host, uint32_t stride,
                            int phase, uint32_t* ovf_host_count, hipStream_t st) {
-  for (int b = 0; b < kBuckets; b++) {
+  // largest buckets first: their long-running workgroups start early
+  for (int b = kBuckets - 1; b >= 0; b--) {
     WorkList wl{lists + (uint64_t)b * list_stride, counts_host[b], stride, phase};
     uint64_t items;
     if (phase == 0 || stride <= 1) items = phase == 2 ? 0 : counts_host[b];
@@ -927,9 +1247,9 @@ static lp_status run_phase(lp_graph* g, const GView& gv, const Emit& E, const ui
       items = phase == 1 ? ns : counts_host[b] - ns;
     }
     if (b == kBucketHuge) {
-      LP_TRY((launch_spa<kW, kQuery>(g, gv, E, cnt, wedges, qnew, wl, SpaItem{nullptr, 0, 0}, items, st)));
+      LP_TRY((launch_spa<kW, kQuery>(g, gv, E, wl, SpaItem{nullptr, nullptr, 0, 0}, items, st)));
     } else {
-      LP_TRY((launch_bucket<kW, kQuery>(g, b, gv, E, cnt, wedges, qnew, wl, items, st)));
+      LP_TRY((launch_bucket<kW, kQuery>(g, b, gv, E, wl, items, st)));
     }
   }
   // overflow records written by this phase's LDS kernels
@@ -939,23 +1259,22 @@ static lp_status run_phase(lp_graph* g, const GView& gv, const Emit& E, const ui
   if (ovf_total > E.ovf_cap) return set_error(LP_ERR_OUT_OF_MEMORY, "overflow list exhausted");
   if (ovf_total > *ovf_host_count) {
     WorkList none{nullptr, 0, 1, 0};
-    SpaItem ov{E.ovf, *ovf_host_count, ovf_total};
-    LP_TRY((launch_spa<kW, kQuery>(g, gv, E, cnt, wedges, qnew, none, ov, ovf_total - *ovf_host_count, st)));
+    SpaItem ov{E.ovf, static_cast<const SrcRec*>(E.ovf_rec), *ovf_host_count, ovf_total};
+    LP_TRY((launch_spa<kW, kQuery>(g, gv, E, none, ov, ovf_total - *ovf_host_count, st)));
     *ovf_host_count = ovf_total;
   }
   return LP_OK;
 }
 
 template <bool kQuery>
-static lp_status run_phase_any(lp_graph* g, const GView& gv, const Emit& E, const uint32_t* cnt,
-                               const uint32_t* wedges, const uint32_t* qnew, const uint32_t* lists,
+static lp_status run_phase_any(lp_graph* g, const GView& gv, const Emit& E, const SrcRec* lists,
                                uint64_t list_stride, const uint32_t* counts_host, uint32_t stride,
                                int phase, uint32_t* ovf_host_count, hipStream_t st) {
   if (E.measure == LP_AA || E.measure == LP_RA)
-    return run_phase<true, kQuery>(g, gv, E, cnt, wedges, qnew, lists, list_stride, counts_host,
-                                   stride, phase, ovf_host_count, st);
-  return run_phase<false, kQuery>(g, gv, E, cnt, wedges, qnew, lists, list_stride, counts_host,
-                                  stride, phase, ovf_host_count, st);
+    return run_phase<true, kQuery>(g, gv, E, lists, list_stride, counts_host, stride, phase,
+                                   ovf_host_count, st);
+  return run_phase<false, kQuery>(g, gv, E, lists, list_stride, counts_host, stride, phase,
+                                  ovf_host_count, st);
 }
 
 // Radix select of the k largest keys among entries [base, count) of the
@@ -1047,9 +1366,7 @@ struct PlanResult {
 static lp_status run_plan(lp_graph* g, int64_t L, PlanResult* pr, hipStream_t st) {
   Workspace& w = g->ws;
   const uint64_t n = (uint64_t)g->n;
-  LP_TRY(w.cnt.ensure(std::max<uint64_t>(n, 1) * 4));
-  LP_TRY(w.wedges.ensure(std::max<uint64_t>(n, 1) * 4));
-  LP_TRY(w.lists.ensure(std::max<uint64_t>(n, 1) * 4 * kBuckets));
+  LP_TRY(w.lists.ensure(std::max<uint64_t>(n, 1) * sizeof(SrcRec) * kBuckets));
   LP_TRY(w.stats.ensure(sizeof(PlanOut) + 64));
   LP_TRY(w.host_stats.ensure(4096));
   pr->hub = hub_start(g, L);
@@ -1057,9 +1374,8 @@ static lp_status run_plan(lp_graph* g, int64_t L, PlanResult* pr, hipStream_t st
   LP_HIP(hipMemsetAsync(d_out, 0, sizeof(PlanOut), st));
   const AccConfig cfg = acc_config(g);
   if (n > 0) {
-    hipLaunchKernelGGL(plan_kernel, dim3(grid_for(n, 256, 0x7FFFFFFF)), dim3(256), 0, st, view_of(g),
-                       pr->hub, cfg.lds_cap, w.cnt.as<uint32_t>(), w.wedges.as<uint32_t>(),
-                       w.lists.as<uint32_t>(), d_out);
+    hipLaunchKernelGGL(plan_kernel, dim3(grid_for(n, 256 * kPlanItems, 0x7FFFFFFF)), dim3(256), 0, st,
+                       view_of(g), pr->hub, cfg.lds_cap, w.lists.as<SrcRec>(), d_out);
     LP_HIP(hipGetLastError());
   }
   PlanOut* h = w.host_stats.as<PlanOut>();
@@ -1088,11 +1404,11 @@ struct Timer {
   }
 };
 
-static lp_status ensure_ovf(Workspace& w, uint32_t** ovf, uint32_t** ovf_count, uint32_t* cap,
-                            uint32_t** err, unsigned long long** count, unsigned long long** fp,
-                            uint32_t** tau, hipStream_t st) {
+static lp_status ensure_ovf(Workspace& w, uint32_t** ovf, void** ovf_rec, uint32_t** ovf_count,
+                            uint32_t* cap, uint32_t** err, unsigned long long** count,
+                            unsigned long long** fp, uint32_t** tau, hipStream_t st) {
   const uint32_t ocap = 1u << 16;
-  LP_TRY(w.counters.ensure(4096 + (size_t)ocap * 8));
+  LP_TRY(w.counters.ensure(4096 + (size_t)ocap * (4 + sizeof(SrcRec))));
   char* base = w.counters.as<char>();
   *count = reinterpret_cast<unsigned long long*>(base);   // [0]
   *fp = reinterpret_cast<unsigned long long*>(base + 64);  // [3]
@@ -1100,6 +1416,7 @@ static lp_status ensure_ovf(Workspace& w, uint32_t** ovf, uint32_t** ovf_count, 
   *err = reinterpret_cast<uint32_t*>(base + 192);
   *tau = reinterpret_cast<uint32_t*>(base + 256);          // [3]
   *ovf = reinterpret_cast<uint32_t*>(base + 4096);
+  *ovf_rec = base + 4096 + (size_t)ocap * 4;
   *cap = ocap;
   LP_HIP(hipMemsetAsync(base, 0, 4096, st));
   return LP_OK;
@@ -1138,9 +1455,10 @@ lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int3
   for (int b = 0; b < kBuckets; b++) S.bucket_sources[b] = pr.out.count[b];
   const GView gv = view_of(g);
   uint32_t *ovf, *ovf_count, *err, *tau;
+  void* ovf_rec;
   unsigned long long *count, *fp;
   uint32_t ovf_cap;
-  LP_TRY(ensure_ovf(w, &ovf, &ovf_count, &ovf_cap, &err, &count, &fp, &tau, st));
+  LP_TRY(ensure_ovf(w, &ovf, &ovf_rec, &ovf_count, &ovf_cap, &err, &count, &fp, &tau, st));
   if (k == 0 || pr.out.wedges == 0 || g->n == 0) {
     LP_HIP(hipEventRecord(tm.ev[2], st));
     LP_HIP(hipEventRecord(tm.ev[3], st));
@@ -1151,7 +1469,7 @@ lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int3
   }
   const uint64_t total_w = pr.out.wedges;
   const uint64_t budget = g->tuning.sample_budget > 0 ? (uint64_t)g->tuning.sample_budget
-                                                      : (g->tuning.sample_budget < 0 ? 0 : (1ull << 24));
+                                                      : (g->tuning.sample_budget < 0 ? 0 : (1ull << 22));
   // Sampling pays off only when candidates far outnumber k: a sampled subset
   // of sources (every stride-th of each bucket) is scored first, without a
   // threshold; tau is then a lower bound of its r-th best key with
@@ -1190,16 +1508,15 @@ lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int3
   E.cap = cap;
   E.fp = fp;
   E.ovf = ovf;
+  E.ovf_rec = ovf_rec;
   E.ovf_count = ovf_count;
   E.ovf_cap = ovf_cap;
   E.err = err;
-  const uint32_t* lists = w.lists.as<uint32_t>();
-  const uint32_t* cnt = w.cnt.as<uint32_t>();
-  const uint32_t* wed = w.wedges.as<uint32_t>();
+  const SrcRec* lists = w.lists.as<SrcRec>();
   uint32_t ovf_host = 0;
   unsigned long long n_sample = 0;
   if (sample) {
-    LP_TRY(run_phase_any<false>(g, gv, E, cnt, wed, nullptr, lists, (uint64_t)g->n, pr.out.count,
+    LP_TRY(run_phase_any<false>(g, gv, E, lists, (uint64_t)g->n, pr.out.count,
                                 stride, 1, &ovf_host, st));
     LP_HIP(hipMemcpyAsync(&n_sample, count, 8, hipMemcpyDeviceToHost, st));
     LP_HIP(hipStreamSynchronize(st));
@@ -1217,10 +1534,10 @@ lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int3
         else
           LP_TRY(run_select(g, E.out_s, E.out_a, E.out_c, count, cap, 0, r_target, ts, ta, tc, tau, st));
       }
-      LP_TRY(run_phase_any<false>(g, gv, E, cnt, wed, nullptr, lists, (uint64_t)g->n, pr.out.count,
+      LP_TRY(run_phase_any<false>(g, gv, E, lists, (uint64_t)g->n, pr.out.count,
                                   stride, 2, &ovf_host, st));
     } else {
-      LP_TRY(run_phase_any<false>(g, gv, E, cnt, wed, nullptr, lists, (uint64_t)g->n, pr.out.count,
+      LP_TRY(run_phase_any<false>(g, gv, E, lists, (uint64_t)g->n, pr.out.count,
                                   1, 0, &ovf_host, st));
     }
     if (retries == 0) LP_HIP(hipEventRecord(tm.ev[2], st));
@@ -1316,9 +1633,10 @@ lp_status run_fingerprint(lp_graph* g, int64_t L, uint64_t* out, hipStream_t st)
   S.sources = pr.out.sources;
   for (int b = 0; b < kBuckets; b++) S.bucket_sources[b] = pr.out.count[b];
   uint32_t *ovf, *ovf_count, *err, *tau;
+  void* ovf_rec;
   unsigned long long *count, *fp;
   uint32_t ovf_cap;
-  LP_TRY(ensure_ovf(w, &ovf, &ovf_count, &ovf_cap, &err, &count, &fp, &tau, st));
+  LP_TRY(ensure_ovf(w, &ovf, &ovf_rec, &ovf_count, &ovf_cap, &err, &count, &fp, &tau, st));
   Emit E{};
   E.measure = LP_CN;
   E.shift = g->fixed_shift;
@@ -1328,13 +1646,14 @@ lp_status run_fingerprint(lp_graph* g, int64_t L, uint64_t* out, hipStream_t st)
   E.fp_mode = 1;
   E.fp = fp;
   E.ovf = ovf;
+  E.ovf_rec = ovf_rec;
   E.ovf_count = ovf_count;
   E.ovf_cap = ovf_cap;
   E.err = err;
   uint32_t ovf_host = 0;
   if (pr.out.wedges)
-    LP_TRY(run_phase_any<false>(g, view_of(g), E, w.cnt.as<uint32_t>(), w.wedges.as<uint32_t>(),
-                                nullptr, w.lists.as<uint32_t>(), (uint64_t)g->n, pr.out.count, 1, 0,
+    LP_TRY(run_phase_any<false>(g, view_of(g), E, w.lists.as<SrcRec>(), (uint64_t)g->n,
+                                pr.out.count, 1, 0,
                                 &ovf_host, st));
   unsigned long long h[3];
   uint32_t herr = 0;
@@ -1358,12 +1677,9 @@ lp_status run_query(lp_graph* g, const int32_t* sources, int64_t nq, int m, int6
   // sources to device (validated on the host side by the caller)
   LP_TRY(w.q_src.ensure(Q * 4));
   LP_HIP(hipMemcpyAsync(w.q_src.p, sources, Q * 4, hipMemcpyDefault, st));
-  // per query: new id, explored arcs, wedge bound; bucket lists over query indices
-  LP_TRY(w.q_rows.ensure(Q * 4 * (3 + kBuckets) + 256));
-  uint32_t* qnew = w.q_rows.as<uint32_t>();
-  uint32_t* qcnt = qnew + Q;
-  uint32_t* qwed = qcnt + Q;
-  uint32_t* qlists = qwed + Q;
+  // per query: a source record in the list of its bucket
+  LP_TRY(w.q_rows.ensure(Q * sizeof(SrcRec) * kBuckets + 256));
+  SrcRec* qlists = w.q_rows.as<SrcRec>();
   LP_TRY(w.stats.ensure(sizeof(PlanOut) + 64));
   LP_TRY(w.host_stats.ensure(4096));
   PlanOut* d_out = w.stats.as<PlanOut>();
@@ -1372,8 +1688,7 @@ lp_status run_query(lp_graph* g, const int32_t* sources, int64_t nq, int m, int6
   const AccConfig cfg = acc_config(g);
   const GView gv = view_of(g);
   hipLaunchKernelGGL(query_plan_kernel, dim3(grid_for(Q, 1, 65536)), dim3(256), 0, st, gv, hub,
-                     cfg.lds_cap, w.q_src.as<int32_t>(), g->rank, (uint32_t)Q, qnew, qcnt, qwed,
-                     qlists, d_out);
+                     cfg.lds_cap, w.q_src.as<int32_t>(), g->rank, (uint32_t)Q, qlists, d_out);
   LP_HIP(hipGetLastError());
   PlanOut* hp = w.host_stats.as<PlanOut>();
   LP_HIP(hipMemcpyAsync(hp, d_out, sizeof(PlanOut), hipMemcpyDeviceToHost, st));
@@ -1390,9 +1705,10 @@ lp_status run_query(lp_graph* g, const int32_t* sources, int64_t nq, int m, int6
   uint32_t* seg_start = seg_count + Q;
   LP_HIP(hipMemsetAsync(seg_count, 0, Q * 4, st));
   uint32_t *ovf, *ovf_count, *err, *tau;
+  void* ovf_rec;
   unsigned long long *count, *fp;
   uint32_t ovf_cap;
-  LP_TRY(ensure_ovf(w, &ovf, &ovf_count, &ovf_cap, &err, &count, &fp, &tau, st));
+  LP_TRY(ensure_ovf(w, &ovf, &ovf_rec, &ovf_count, &ovf_cap, &err, &count, &fp, &tau, st));
   Emit E{};
   E.measure = m;
   E.shift = g->fixed_shift;
@@ -1406,12 +1722,13 @@ lp_status run_query(lp_graph* g, const int32_t* sources, int64_t nq, int m, int6
   E.q_count = seg_count;
   E.fp = fp;
   E.ovf = ovf;
+  E.ovf_rec = ovf_rec;
   E.ovf_count = ovf_count;
   E.ovf_cap = ovf_cap;
   E.err = err;
   uint32_t ovf_host = 0;
   if (po.wedges)
-    LP_TRY(run_phase_any<true>(g, gv, E, qcnt, qwed, qnew, qlists, Q, po.count, 1, 0, &ovf_host, st));
+    LP_TRY(run_phase_any<true>(g, gv, E, qlists, Q, po.count, 1, 0, &ovf_host, st));
   unsigned long long n_total = 0;
   LP_HIP(hipMemcpyAsync(&n_total, count, 8, hipMemcpyDeviceToHost, st));
   LP_HIP(hipStreamSynchronize(st));

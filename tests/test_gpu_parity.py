@@ -153,7 +153,7 @@ def test_global_path_and_partitions(lp, config1):
                 assert_same_list(got, ref, m, f"cap={cap}/{m}")
             assert lp.fingerprint(g, None) == oracle.fingerprint(gr, None)
             st = lp.last_stats(g)
-            assert st["bucket_sources"][4] > 0
+            assert st["buckets"]["global"] > 0
     say("[gpu] hash partitions K_{5,4000}")
     kb = synth.from_edges(4005, [(h, 5 + i) for h in range(5) for i in range(4000)])
     with lp.Graph(kb.offsets, kb.indices) as g:
@@ -163,7 +163,7 @@ def test_global_path_and_partitions(lp, config1):
             assert_same_list(got, ref, m, f"K5,4000/{m}")
         assert lp.fingerprint(g, None) == oracle.fingerprint(kb, None)
         st = lp.last_stats(g)
-        assert st["bucket_sources"][3] > 0
+        assert st["buckets"]["large"] > 0
 
 
 def test_sampled_threshold_path(lp, config1):
