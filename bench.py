@@ -10,6 +10,7 @@ hand-off, with the graph resident in HBM.
 Prints one JSON line (metric, value, roofline, cpu_baseline, ...).
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -22,6 +23,64 @@ import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 PAPER_DLH_EDGES_PER_S = 38.1e6  # sk-2005, 2x Xeon Gold 6226R (context only)
+
+# Accumulation kernel of each scheduling bucket (count tables: CN, JC, ...,
+# LHN; weighted tables: AA, RA), as rocprofv3 names them, for graphs with
+# fewer than 2^24 vertices (the batched small-source kernels).
+BUCKET_KERNELS = {
+    False: {"tiny": "acc_batch_kernel<256, 48, 3072, false, 64>",
+            "small": "acc_batch_kernel<256, 8, 3072, false, 64>",
+            "mid1": "acc_batch_kernel<256, 2, 3072, false, 64>",
+            "mid2": "acc_lds_kernel<512, 512, 6144, false, false, 64>",
+            "large": "acc_lds_kernel<1024, 1024, 14336, false, false, 64>",
+            "global": "acc_spa_kernel<false, false>"},
+    True: {"tiny": "acc_batch_kernel<256, 48, 3072, true, 64>",
+           "small": "acc_batch_kernel<256, 8, 3072, true, 64>",
+           "mid1": "acc_batch_kernel<256, 2, 3072, true, 64>",
+           "mid2": "acc_lds_kernel<512, 512, 4608, true, false, 64>",
+           "large": "acc_lds_kernel<1024, 1024, 7680, true, false, 64>",
+           "global": "acc_spa_kernel<true, false>"},
+}
+KERNEL_SOURCES = ["paper_2401_11415_amd/csrc/predict.hip", "paper_2401_11415_amd/csrc/kernels.h",
+                  "paper_2401_11415_amd/csrc/lp_common.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "acc_kernels_rmat22_dlh_jc_traffic.txt")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def launch_bytes(b, normalised):
+    """Algorithmic bytes of the accumulation launches of one bucket: per source
+    its two row offsets (8 B), its row and the degree of every neighbour for
+    the hub test (8 B per first-order neighbour), the row start of every
+    explored intermediate (4 B per arc), one id per wedge (4 B), and deg[c]
+    per distinct candidate for the normalised measures (4 B)."""
+    return (8 * b["sources"] + 8 * b["first_order"] + 4 * b["arcs"] + 4 * b["wedges"]
+            + (4 * b["candidates"] if normalised else 0))
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
+    WRITE_SIZE summary, or None when it is missing or was taken on other
+    kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec, rows = {}, {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if line.startswith("source_sha256:"):
+                rec["hash"] = line.split(":", 1)[1].strip()
+            elif line.startswith("traffic_bytes_per_launch "):
+                name, val = line[len("traffic_bytes_per_launch "):].rsplit("=", 1)
+                rows[name.strip()] = float(val)
+    if rec.get("hash") != kernel_source_hash():
+        return None
+    return rows.get(kernel)
 
 
 def log(*a):
@@ -53,6 +112,8 @@ def main():
     ap.add_argument("--scale", type=int, default=22)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device 5 times (scales HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -60,6 +121,16 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.calibrate_copy:
+        n = args.calibrate_copy << 18
+        src = torch.ones(n, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 5}))
+        return
 
     import paper_2401_11415_amd as lp
     import synth
@@ -84,6 +155,7 @@ def main():
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     acc_ms, tot_ms, per_step = [], [], []
+    per_bucket = {}
     t_start = time.perf_counter()
     ev0.record(stream)
     for i in range(args.steps):
@@ -93,6 +165,10 @@ def main():
         per_step.append((time.perf_counter() - ts) * 1e3)
         acc_ms.append(st["ms_accumulate"])
         tot_ms.append(st["ms_total"])
+        for name, b in st["launches"].items():
+            acc = per_bucket.setdefault(name, dict.fromkeys(b, 0))
+            for f, v in b.items():
+                acc[f] += v
     ev1.record(stream)
     torch.cuda.synchronize()
     wall_ms = (time.perf_counter() - t_start) * 1e3
@@ -106,9 +182,23 @@ def main():
                           normalised=args.measure.upper() not in ("CN", "AA", "RA"))
     acc_med = float(np.median(acc_ms))
     tot_med = float(np.median(tot_ms))
-    # dominant phase: the accumulation kernels (two-hop gather + hash + scoring)
-    B_acc = B - 12 * k_out
-    achieved = B_acc / (acc_med * 1e-3) / 1e9
+    normalised = args.measure.upper() not in ("CN", "AA", "RA")
+    weighted = args.measure.upper() in ("AA", "RA")
+    kernels = {}
+    for name, b in per_bucket.items():
+        if b["launches"] == 0:
+            continue
+        nb = launch_bytes(b, normalised)
+        kernels[name] = {
+            "kernel": BUCKET_KERNELS[weighted][name], "launches": b["launches"],
+            "avg_launch_ms": b["ms"] / b["launches"],
+            "algorithmic_bytes_per_launch": nb / b["launches"],
+            "wedges_per_launch": b["wedges"] / b["launches"],
+            "gbs": nb / (b["ms"] * 1e-3) / 1e9, "share_of_step": b["ms"] / args.steps / ms_per_step}
+    dom = max(kernels, key=lambda n: kernels[n]["avg_launch_ms"] * kernels[n]["launches"])
+    dk = kernels[dom]
+    achieved = dk["gbs"]
+    traffic = measured_traffic(dk["kernel"])
     value = k_out / (ms_per_step * 1e-3)
     res = {
         "metric": "predicted edges/s (DLH, Jaccard)",
@@ -135,12 +225,16 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "kernel": "accumulation phase (acc_lds_kernel buckets + acc_spa_kernel)",
-            "algorithmic_bytes": B_acc,
-            "ms": acc_med,
+            "traffic": traffic,
+            "kernel": dk["kernel"],
+            "bucket": dom,
+            "algorithmic_bytes_per_launch": dk["algorithmic_bytes_per_launch"],
+            "avg_launch_ms": dk["avg_launch_ms"],
+            "kernel_source_sha256": kernel_source_hash(),
         },
+        "kernels": kernels,
         "whole_call": {"algorithmic_bytes": B, "ms_device_median": tot_med,
+                       "ms_accumulate_median": acc_med,
                        "frac_hbm": B / (tot_med * 1e-3) / 1e9 / HBM_PEAK_GBS,
                        "wedges": stats["wedges"], "candidates": fp[0],
                        "appended": stats["appended"], "retries": stats["retries"],

@@ -45,12 +45,19 @@ class _Tuning(ctypes.Structure):
                 ("sample_budget", ctypes.c_int64), ("reserved", ctypes.c_int64 * 5)]
 
 
+class _BucketStats(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_uint64), ("sources", ctypes.c_uint64),
+                ("first_order", ctypes.c_uint64), ("arcs", ctypes.c_uint64),
+                ("wedges", ctypes.c_uint64), ("candidates", ctypes.c_uint64),
+                ("ms", ctypes.c_double)]
+
+
 class _Stats(ctypes.Structure):
     _fields_ = [("wedges", ctypes.c_uint64), ("sources", ctypes.c_uint64),
                 ("bucket_sources", ctypes.c_uint64 * 8), ("appended", ctypes.c_uint64),
                 ("retries", ctypes.c_uint64), ("ms_plan", ctypes.c_double),
                 ("ms_accumulate", ctypes.c_double), ("ms_select", ctypes.c_double),
-                ("ms_total", ctypes.c_double)]
+                ("ms_total", ctypes.c_double), ("bucket", _BucketStats * 8)]
 
 
 def library_path() -> str:
@@ -227,7 +234,10 @@ def set_tuning(g: Graph, lds_wedge_cap: int = 0, global_slots: int = 0, sample_b
 def last_stats(g: Graph) -> dict:
     s = _Stats()
     _check(load().lp_last_stats(g.handle, ctypes.byref(s)))
+    launches = {}
+    for name, b in zip(BUCKETS, s.bucket):
+        launches[name] = {f: getattr(b, f) for f, _ in _BucketStats._fields_}
     return {"wedges": s.wedges, "sources": s.sources,
             "buckets": dict(zip(BUCKETS, list(s.bucket_sources))), "appended": s.appended,
             "retries": s.retries, "ms_plan": s.ms_plan, "ms_accumulate": s.ms_accumulate,
-            "ms_select": s.ms_select, "ms_total": s.ms_total}
+            "ms_select": s.ms_select, "ms_total": s.ms_total, "launches": launches}

@@ -42,7 +42,29 @@ struct Emit {
   uint32_t* ovf_count;
   uint32_t ovf_cap;
   uint32_t* err;           // error flags
+  unsigned long long* work;  // [5] this launch's work counters (lp_bucket_stats order)
 };
+
+// Work counters of one lane (sources, sum d_a, arcs, wedges, candidates),
+// added to the launch's totals once per wave at the end of a kernel.
+struct WorkAcc {
+  unsigned long long v[5] = {0, 0, 0, 0, 0};
+  __device__ void source(uint32_t da, uint32_t na, uint32_t U) {
+    v[0] += 1;
+    v[1] += da;
+    v[2] += na;
+    v[3] += U;
+  }
+};
+
+__device__ inline void flush_work(const Emit& E, WorkAcc& wa) {
+#pragma unroll
+  for (int i = 0; i < 5; i++) {
+    unsigned long long x = wa.v[i];
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
+    if ((threadIdx.x & 63) == 0 && x) atomicAdd(&E.work[i], x);
+  }
+}
 
 enum : uint32_t { kErrProbe = 1, kErrOvfList = 2 };
 
@@ -339,19 +361,25 @@ __device__ inline uint32_t rank_lt(uint64_t M) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(M >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)M, 0u));
 }
 
+// Table updates carry a 64-bit increment: for count tables kSlotOne (a wedge)
+// or kBlocked64 (the key is a first-order neighbour of the source), for
+// weighted tables the fixed-point weight of the wedge's intermediate or
+// kBlocked64W.  A key is blocked at most once and sums stay below 2^62, so
+// adding the flag sets it.  The sweep drops flagged entries.
+
 // Probe from slot h on until key lands (key == kEmpty32: nothing to do);
 // the loop runs until every lane of the wave is done.  False if the table is
 // full for some lane.
-__device__ inline bool probe_count(uint64_t* tab, uint32_t S, uint32_t key, uint32_t h) {
+__device__ inline bool probe_count(uint64_t* tab, uint32_t S, uint32_t key, uint32_t h, uint64_t inc) {
   for (uint32_t probe = 0; probe < S; probe++) {
     if (!__any(key != kEmpty32)) return true;
     uint64_t old = kSlotEmpty;
     if (key != kEmpty32)
       old = atomicCAS((unsigned long long*)&tab[h], (unsigned long long)kSlotEmpty,
-                      (unsigned long long)(kSlotOne | key));
+                      (unsigned long long)(inc | key));
     // lanes without a live key saw old == kSlotEmpty and stay dead
     const bool same = (key != kEmpty32) & ((uint32_t)old == key);
-    if (same) atomicAdd((unsigned long long*)&tab[h], (unsigned long long)kSlotOne);
+    if (same) atomicAdd((unsigned long long*)&tab[h], (unsigned long long)inc);
     key = (same | (old == kSlotEmpty)) ? kEmpty32 : key;
     h = next_slot(h, S);
   }
@@ -359,13 +387,13 @@ __device__ inline bool probe_count(uint64_t* tab, uint32_t S, uint32_t key, uint
 }
 
 __device__ inline bool probe_weight(uint32_t* keys, uint64_t* vals, uint32_t S, uint32_t key, uint32_t h,
-                                    uint64_t w) {
+                                    uint64_t inc) {
   for (uint32_t probe = 0; probe < S; probe++) {
     if (!__any(key != kEmpty32)) return true;
     uint32_t old = 0;
     if (key != kEmpty32) old = atomicCAS(&keys[h], kEmpty32, key);
     const bool hit = (key != kEmpty32) & ((old == kEmpty32) | (old == key));
-    if (hit) atomicAdd((unsigned long long*)&vals[h], (unsigned long long)w);
+    if (hit) atomicAdd((unsigned long long*)&vals[h], (unsigned long long)inc);
     key = hit ? kEmpty32 : key;
     h = next_slot(h, S);
   }
@@ -376,12 +404,13 @@ __device__ inline bool probe_weight(uint32_t* keys, uint64_t* vals, uint32_t S, 
 // gets one probe where it falls; the few that need more wait here and are
 // probed on in batches of up to 64, so that one long probe sequence does not
 // hold up the 63 other lanes of its window.  Used by all lanes of a wave
-// together; the fill count is wave-uniform.
+// together; the fill count is wave-uniform.  Count tables keep the kind of
+// increment in bit 31 of the slot index (set: blocked).
 template <bool kW>
 struct Retry {
   uint32_t* key;  // [64]
   uint32_t* h;    // [64] next slot to probe
-  uint64_t* w;    // [64] weight (weighted tables only)
+  uint64_t* w;    // [64] increment (weighted tables only)
   uint32_t n = 0;
 };
 
@@ -393,32 +422,33 @@ __device__ inline bool retry_drain(uint64_t* tab, uint32_t* keys, uint64_t* vals
   const uint32_t l = (uint32_t)lane_id();
   const bool in = l < R.n;
   const uint32_t key = in ? R.key[l] : kEmpty32;
-  const uint32_t h = in ? R.h[l] : 0u;
+  const uint32_t hv = in ? R.h[l] : 0u;
   const uint64_t w = (kW && in) ? R.w[l] : 0ull;
   wave_fence();
   R.n = 0;
-  return kW ? probe_weight(keys, vals, S, key, h, w) : probe_count(tab, S, key, h);
+  if (kW) return probe_weight(keys, vals, S, key, hv, w);
+  return probe_count(tab, S, key, hv & ~kBlocked, (hv & kBlocked) ? kBlocked64 : kSlotOne);
 }
 
-// Insert one key per lane (kEmpty32: none): count tables add one, weighted
-// tables add w.  False if the table is full for some key.
+// Add inc to key's entry, inserting the key if absent (key == kEmpty32: no
+// update on this lane).  False if the table is full for some key.
 template <bool kW>
 __device__ inline bool tab_insert(uint64_t* tab, uint32_t* keys, uint64_t* vals, uint32_t S, uint32_t key,
-                                  uint32_t h, uint64_t w, Retry<kW>& R) {
+                                  uint32_t h, uint64_t inc, Retry<kW>& R) {
   const bool live = key != kEmpty32;
   bool done;
   if (kW) {
     uint32_t old = 0;
     if (live) old = atomicCAS(&keys[h], kEmpty32, key);
     done = (old == kEmpty32) | (old == key);
-    if (live & done) atomicAdd((unsigned long long*)&vals[h], (unsigned long long)w);
+    if (live & done) atomicAdd((unsigned long long*)&vals[h], (unsigned long long)inc);
   } else {
     uint64_t old = kSlotEmpty;
     if (live)
       old = atomicCAS((unsigned long long*)&tab[h], (unsigned long long)kSlotEmpty,
-                      (unsigned long long)(kSlotOne | key));
+                      (unsigned long long)(inc | key));
     const bool same = (uint32_t)old == key;
-    if (live & same) atomicAdd((unsigned long long*)&tab[h], (unsigned long long)kSlotOne);
+    if (live & same) atomicAdd((unsigned long long*)&tab[h], (unsigned long long)inc);
     done = same | (old == kSlotEmpty);
   }
   const bool fail = live & !done;
@@ -430,37 +460,75 @@ __device__ inline bool tab_insert(uint64_t* tab, uint32_t* keys, uint64_t* vals,
   if (fail) {
     const uint32_t p = R.n + rank_lt(M);
     R.key[p] = key;
-    R.h[p] = next_slot(h, S);
-    if (kW) R.w[p] = w;
+    const uint32_t hn = next_slot(h, S);
+    if (kW) {
+      R.h[p] = hn;
+      R.w[p] = inc;
+    } else {
+      R.h[p] = inc == kSlotOne ? hn : (hn | kBlocked);
+    }
   }
   R.n += nf;
   return ok;
 }
 
-// Flag a key's entry as a first-order neighbour if the key is present.  Runs
-// after every insertion of the table has completed; no two lanes look for the
-// same key, so plain read-modify-write suffices.
-__device__ inline void tab_block_count(uint64_t* tab, uint32_t S, uint32_t key, uint32_t h, bool act) {
+// Flag the entry of key (kEmpty32: none on this lane) as a first-order
+// neighbour if the key is present.  Runs after every insertion into the table
+// has completed; no two lanes look for the same key, so a plain
+// read-modify-write suffices.  Lookups that meet another key at their home
+// slot continue through the retry list, which must be empty on entry and is
+// emptied by mark_drain.
+template <bool kW>
+__device__ inline void mark_probe(uint64_t* tab, uint32_t* keys, uint64_t* vals, uint32_t S,
+                                  uint32_t key, uint32_t h) {
   for (uint32_t probe = 0; probe < S; probe++) {
-    if (!__any(act)) return;
-    const uint64_t v = tab[h];
-    const bool found = act && (uint32_t)v == key;
-    if (found) tab[h] = v | kBlocked64;
-    act = act && !found && (uint32_t)v != kEmpty32;
+    if (!__any(key != kEmpty32)) return;
+    uint32_t k = kEmpty32;
+    if (key != kEmpty32) k = kW ? keys[h] : (uint32_t)tab[h];
+    const bool found = (key != kEmpty32) & (k == key);
+    if (found) {
+      if (kW) vals[h] |= kBlocked64W;
+      else tab[h] |= kBlocked64;
+    }
+    key = (found | (k == kEmpty32)) ? kEmpty32 : key;
     h = next_slot(h, S);
   }
 }
 
-__device__ inline void tab_block_weight(const uint32_t* keys, uint64_t* vals, uint32_t S, uint32_t key,
-                                        uint32_t h, bool act) {
-  for (uint32_t probe = 0; probe < S; probe++) {
-    if (!__any(act)) return;
-    const uint32_t k = keys[h];
-    const bool found = act && k == key;
-    if (found) vals[h] |= kBlocked64W;
-    act = act && !found && k != kEmpty32;
-    h = next_slot(h, S);
+template <bool kW>
+__device__ inline void mark_drain(uint64_t* tab, uint32_t* keys, uint64_t* vals, uint32_t S, Retry<kW>& R) {
+  if (R.n == 0) return;
+  wave_fence();
+  const uint32_t l = (uint32_t)lane_id();
+  const uint32_t key = l < R.n ? R.key[l] : kEmpty32;
+  const uint32_t h = l < R.n ? R.h[l] : 0u;
+  wave_fence();
+  R.n = 0;
+  mark_probe<kW>(tab, keys, vals, S, key, h);
+}
+
+template <bool kW>
+__device__ inline void tab_mark(uint64_t* tab, uint32_t* keys, uint64_t* vals, uint32_t S, uint32_t key,
+                                uint32_t h, Retry<kW>& R) {
+  const bool live = key != kEmpty32;
+  uint32_t k = kEmpty32;
+  if (live) k = kW ? keys[h] : (uint32_t)tab[h];
+  const bool found = live & (k == key);
+  if (found) {
+    if (kW) vals[h] |= kBlocked64W;
+    else tab[h] |= kBlocked64;
   }
+  const bool cont = live & !found & (k != kEmpty32);
+  const uint64_t M = __ballot(cont);
+  if (M == 0) return;
+  const uint32_t nf = (uint32_t)__popcll(M);
+  if (R.n + nf > 64) mark_drain<kW>(tab, keys, vals, S, R);
+  if (cont) {
+    const uint32_t p = R.n + rank_lt(M);
+    R.key[p] = key;
+    R.h[p] = next_slot(h, S);
+  }
+  R.n += nf;
 }
 
 // ---------------------------------------------------------------------------

@@ -426,25 +426,30 @@ __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, WorkList 
            (uint32_t)STAGE, L.so_s[wv], L.so_a[wv], L.so_c[wv], 64u};
   Retry<kW> RT{L.rt_key[wv], L.rt_h[wv], kW ? L.rt_w[wv] : nullptr};
   FpAcc fa;
+  WorkAcc wk;
   const uint32_t ts_bits = E.fp_mode ? 0u : E.tau[0];
   const uint64_t wmin = kW ? min_wsum(E.measure, ts_bits, E.shift) : 1ull;
   const uint32_t total = uniform(work_count(wl));
+  // slots [0, clean) of the group's table are empty: every sweep empties the
+  // slots it reads, so only growth beyond the largest table so far is cleared
+  uint32_t clean = 0;
   for (uint32_t i = blockIdx.x * NG + grp; i < total; i += gridDim.x * NG) {
     const SrcRec s = uniform_rec(load_rec(wl, i));
-    // first batch of first-order neighbours, in flight during accumulation
-    const uint32_t xe = s.x0 + gl;
-    const uint32_t xb = g.adj[xe < s.x1 ? xe : s.x0];
     uint32_t P, S;
     table_geometry(s.U, SLOTS, &P, &S);
     const uint32_t hmin = kW ? 1u : min_count(E.measure, ts_bits, s.da, !kQuery);
+    bool handed = false;
     for (uint32_t pass = 0; pass < P; pass++) {
-      for (uint32_t t = gl; t < S; t += G) {
-        if (kW) {
-          keys[t] = kEmpty32;
-          vals[t] = 0;
-        } else {
-          tab[t] = kSlotEmpty;
+      if (S > clean) {
+        for (uint32_t t = clean + gl; t < S; t += G) {
+          if (kW) {
+            keys[t] = kEmpty32;
+            vals[t] = 0;
+          } else {
+            tab[t] = kSlotEmpty;
+          }
         }
+        clean = S;
       }
       if (gl == 0) L.ovf[grp] = 0;
       group_sync<G>();
@@ -462,9 +467,9 @@ __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, WorkList 
             bool live = v[u];
             if (kQuery) live = live & (c[u] != s.a);
             if (P > 1) live = live & (key_part(c[u], P) == pass);
-            const uint64_t w = kW ? s_w[arc[u]] : 0ull;
+            const uint64_t inc = kW ? s_w[arc[u]] : kSlotOne;
             const bool ok = tab_insert<kW>(tab, keys, vals, S, live ? c[u] : kEmpty32,
-                                           key_slot(c[u], S), w, RT);
+                                           key_slot(c[u], S), inc, RT);
             full = full | !ok;
           }
         });
@@ -475,16 +480,15 @@ __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, WorkList 
       // first-order neighbours are not candidates: flag their entries
       for (uint32_t e0 = s.x0; e0 < s.x1; e0 += G) {
         const uint32_t e = e0 + gl;
-        const bool in = e < s.x1;
-        const uint32_t b = e0 == s.x0 ? xb : g.adj[in ? e : s.x0];
-        bool act = in;
-        if (P > 1) act = act && key_part(b, P) == pass;
-        if (kW) tab_block_weight(keys, vals, S, b, key_slot(b, S), act);
-        else tab_block_count(tab, S, b, key_slot(b, S), act);
+        uint32_t b = e < s.x1 ? g.adj[e] : kEmpty32;
+        if (P > 1 && b != kEmpty32 && key_part(b, P) != pass) b = kEmpty32;
+        tab_mark<kW>(tab, keys, vals, S, b, key_slot(b, S), RT);
       }
+      mark_drain<kW>(tab, keys, vals, S, RT);
       group_sync<G>();
       if (L.ovf[grp]) {
         // the table filled up: hand the rest of this source to the global path
+        clean = 0;
         if (gl == 0) {
           const uint32_t slot = atomicAdd(E.ovf_count, 1u);
           if (slot < E.ovf_cap) {
@@ -495,32 +499,44 @@ __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, WorkList 
           }
         }
         group_sync<G>();
+        handed = true;
         break;
       }
-      // stage every key of this partition that can still reach tau
+      // stage every key of this partition that can still reach tau, and
+      // leave the table empty for the next source
       for (uint32_t t0 = 0; t0 < S; t0 += G) {
         const uint32_t t = t0 + gl;
         const uint32_t tc = t < S ? t : 0u;
         uint32_t c, h = 0;
         uint64_t wsum = 0;
-        bool ok;
+        bool cand, ok;
         if (kW) {
           c = keys[tc];
           wsum = vals[tc];
-          ok = t < S && c != kEmpty32 && (wsum >> 63) == 0 && wsum >= wmin;
+          if (t < S) {
+            keys[t] = kEmpty32;
+            vals[t] = 0;
+          }
+          cand = t < S && c != kEmpty32 && (wsum >> 63) == 0;
+          ok = cand && wsum >= wmin;
         } else {
           const uint64_t v = tab[tc];
+          if (t < S) tab[t] = kSlotEmpty;
           c = (uint32_t)v;
           h = (uint32_t)(v >> 32);
-          ok = t < S && c != kEmpty32 && (h & kBlocked) == 0 && h >= hmin;
+          cand = t < S && c != kEmpty32 && (h & kBlocked) == 0;
+          ok = cand && h >= hmin;
         }
+        wk.v[4] += cand ? 1u : 0u;
         stage_add<kQuery, kW>(E, g, SG, ok, c, h, wsum, s.key, s.da, fa);
       }
       group_sync<G>();
     }
+    if (!handed && gl == 0) wk.source(s.da, s.na, s.U);
   }
   stage_drain<kQuery, kW>(E, g, SG, fa);
   flush_fp(E, fa);
+  flush_work(E, wk);
 }
 
 // ---------------------------------------------------------------------------
@@ -588,10 +604,12 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
            (uint32_t)STAGE, L.so_s[wv], L.so_a[wv], L.so_c[wv], 64u};
   Retry<kW> RT{L.rt_key[wv], L.rt_h[wv], kW ? L.rt_w[wv] : nullptr};
   FpAcc fa;
+  WorkAcc wk;
   const uint32_t ts_bits = E.fp_mode ? 0u : E.tau[0];
   const uint64_t wmin = kW ? min_wsum(E.measure, ts_bits, E.shift) : 1ull;
   const uint32_t total = uniform(work_count(wl));
   const uint32_t nbatch = (total + B - 1) / B;
+  uint32_t clean = 0;  // slots [0, clean) of the table are empty
   for (uint32_t bi = blockIdx.x; bi < nbatch; bi += gridDim.x) {
     const uint32_t i0 = bi * B;
     const uint32_t nb = total - i0 < (uint32_t)B ? total - i0 : (uint32_t)B;
@@ -634,19 +652,18 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
     uint32_t S = (uint32_t)(((uint64_t)UT * 3 + 1) / 2);
     if (S < 16) S = 16;
     if (S > (uint32_t)SLOTS) S = SLOTS;  // cannot happen within the bucket's bounds
-    // first batch of first-order neighbours, in flight during accumulation
-    const uint32_t xq = (uint32_t)tid < NX ? (uint32_t)tid : 0u;
-    const uint32_t xbi = NX ? (uint32_t)batch_search<B>(L.xoff, xq) : 0u;
-    const uint32_t xb = NX ? g.adj[L.rec[xbi].x0 + (xq - L.xoff[xbi])] : 0u;
-    for (uint32_t t = tid; t < S; t += WGS) {
-      if (kW) {
-        L.keys[t] = kEmpty32;
-        L.vals[t] = 0;
-      } else {
-        L.tab[t] = kSlotEmpty;
+    if (S > clean) {
+      for (uint32_t t = clean + tid; t < S; t += WGS) {
+        if (kW) {
+          L.keys[t] = kEmpty32;
+          L.vals[t] = 0;
+        } else {
+          L.tab[t] = kSlotEmpty;
+        }
       }
+      clean = S;
+      __syncthreads();
     }
-    __syncthreads();
     bool full = false;
     for (uint32_t cb = 0; cb < NA; cb += WGS) {
       const uint32_t q = cb + tid;
@@ -676,7 +693,7 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
 #pragma unroll
         for (int u = 0; u < kWin; u++) {
           const uint32_t k = (L.srcof[arc[u]] << kBatchIdBits) | (c[u] & kBatchIdMask);
-          const uint64_t w = kW ? L.w[arc[u]] : 0ull;
+          const uint64_t w = kW ? L.w[arc[u]] : kSlotOne;
           const bool ok = tab_insert<kW>(L.tab, L.keys, L.vals, S, v[u] ? k : kEmpty32, key_slot(k, S), w, RT);
           full = full | !ok;
         }
@@ -688,20 +705,18 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
     // first-order neighbours are not candidates: flag their entries
     for (uint32_t x0 = 0; x0 < NX; x0 += WGS) {
       const uint32_t x = x0 + tid;
-      const bool in = x < NX;
-      uint32_t b = xb, i = xbi;
-      if (x0 != 0) {
-        const uint32_t xc = in ? x : x0;
-        i = (uint32_t)batch_search<B>(L.xoff, xc);
-        b = g.adj[L.rec[i].x0 + (xc - L.xoff[i])];
+      uint32_t key = kEmpty32;
+      if (x < NX) {
+        const uint32_t i = (uint32_t)batch_search<B>(L.xoff, x);
+        key = (i << kBatchIdBits) | g.adj[L.rec[i].x0 + (x - L.xoff[i])];
       }
-      const uint32_t key = (i << kBatchIdBits) | b;
-      if (kW) tab_block_weight(L.keys, L.vals, S, key, key_slot(key, S), in);
-      else tab_block_count(L.tab, S, key, key_slot(key, S), in);
+      tab_mark<kW>(L.tab, L.keys, L.vals, S, key, key_slot(key, S), RT);
     }
+    mark_drain<kW>(L.tab, L.keys, L.vals, S, RT);
     __syncthreads();
     if (L.ovf) {
       // a full table: every source of the batch goes to the global path whole
+      clean = 0;
       if (tid < (int)nb) {
         const uint32_t slot = atomicAdd(E.ovf_count, 1u);
         if (slot < E.ovf_cap) {
@@ -714,6 +729,7 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
       __syncthreads();
       continue;
     }
+    if (tid < (int)nb) wk.source(L.rec[tid].da, L.rec[tid].na, L.rec[tid].U);
     // stage every key that can still reach tau
     for (uint32_t t0 = 0; t0 < S; t0 += WGS) {
       const uint32_t t = t0 + tid;
@@ -724,12 +740,20 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
       if (kW) {
         key = L.keys[tc];
         wsum = L.vals[tc];
-        ok = t < S && key != kEmpty32 && (wsum >> 63) == 0 && wsum >= wmin;
+        if (t < S) {
+          L.keys[t] = kEmpty32;
+          L.vals[t] = 0;
+        }
+        ok = t < S && key != kEmpty32 && (wsum >> 63) == 0;
+        wk.v[4] += ok ? 1u : 0u;
+        ok = ok && wsum >= wmin;
       } else {
         const uint64_t v = L.tab[tc];
+        if (t < S) L.tab[t] = kSlotEmpty;
         key = (uint32_t)v;
         h = (uint32_t)(v >> 32);
         ok = t < S && key != kEmpty32 && (h & kBlocked) == 0;
+        wk.v[4] += ok ? 1u : 0u;
       }
       const uint32_t i = ok ? key >> kBatchIdBits : 0u;
       if (!kW) ok = ok && h >= L.hmin[i];
@@ -739,6 +763,7 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
   }
   stage_drain<false, kW>(E, g, SG, fa);
   flush_fp(E, fa);
+  flush_work(E, wk);
 }
 
 // ---------------------------------------------------------------------------
@@ -783,9 +808,10 @@ __global__ __launch_bounds__(kSpaThreads) void acc_spa_kernel(GView g, Emit E, W
   unsigned long long* HW = reinterpret_cast<unsigned long long*>(slab);
   uint32_t* K = spa_keys + (uint64_t)blockIdx.x * g.n;
   FpAcc fa;
+  WorkAcc wk;
   const uint32_t ts_bits = E.fp_mode ? 0u : E.tau[0];
   const uint64_t wmin = kW ? min_wsum(E.measure, ts_bits, E.shift) : 1ull;
-  const uint32_t total = ov.ovf ? (ov.ovf_end - ov.ovf_begin) : work_count(wl);
+  const uint32_t total = ov.ovf ? (ov.ovf_end - ov.ovf_begin) : uniform(work_count(wl));
   for (uint32_t i = blockIdx.x; i < total; i += gridDim.x) {
     SrcRec s;
     uint32_t p0 = 0, P = 1;
@@ -839,19 +865,23 @@ __global__ __launch_bounds__(kSpaThreads) void acc_spa_kernel(GView g, Emit E, W
         c = __hip_atomic_load(&K[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (kW) {
           wsum = __hip_atomic_exchange(&HW[c], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          wk.v[4] += wsum != 0 ? 1u : 0u;
           ok = wsum != 0 && wsum >= wmin;
         } else {
           h = __hip_atomic_exchange(&H[c], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          wk.v[4] += h != 0 ? 1u : 0u;
           ok = h != 0 && h >= hmin;
         }
       }
       stage_add<kQuery, kW>(E, g, SG, ok, c, h, wsum, s.key, s.da, fa);
     }
+    if (threadIdx.x == 0) wk.source(s.da, s.na, s.U);
     __threadfence();
     __syncthreads();
   }
   stage_drain<kQuery, kW>(E, g, SG, fa);
   flush_fp(E, fa);
+  flush_work(E, wk);
 }
 
 // ---------------------------------------------------------------------------
@@ -1164,15 +1194,15 @@ static lp_status launch_bucket(lp_graph* g, int bucket, const GView& gv, const E
     // batches: Tiny 48 sources (<= 1536 wedges), Small 8 (<= 2048), Mid1 2 (<= 2048)
     switch (bucket) {
       case kBucketTiny:
-        hipLaunchKernelGGL((acc_batch_kernel<256, 48, 3072, kW, 128>),
+        hipLaunchKernelGGL((acc_batch_kernel<256, 48, 3072, kW, 64>),
                            dim3(grid_for((nitems + 47) / 48, 1, cus * 8)), dim3(256), 0, st, gv, E, wl);
         break;
       case kBucketSmall:
-        hipLaunchKernelGGL((acc_batch_kernel<256, 8, 3072, kW, 128>),
+        hipLaunchKernelGGL((acc_batch_kernel<256, 8, 3072, kW, 64>),
                            dim3(grid_for((nitems + 7) / 8, 1, cus * 8)), dim3(256), 0, st, gv, E, wl);
         break;
       default:
-        hipLaunchKernelGGL((acc_batch_kernel<256, 2, 3072, kW, 128>),
+        hipLaunchKernelGGL((acc_batch_kernel<256, 2, 3072, kW, 64>),
                            dim3(grid_for((nitems + 1) / 2, 1, cus * 8)), dim3(256), 0, st, gv, E, wl);
         break;
     }
@@ -1232,11 +1262,68 @@ static lp_status launch_spa(lp_graph* g, const GView& gv, const Emit& E, WorkLis
   return LP_OK;
 }
 
+// HIP events around every accumulation launch of a call, on the call's
+// stream; per-bucket device time and launch counts go to the call's stats.
+struct LaunchClock {
+  hipEvent_t ev[2 * (kBuckets + 1)] = {};
+  bool used[kBuckets + 1] = {};
+  lp_stats* stats = nullptr;
+  explicit LaunchClock(lp_stats* s) : stats(s) {
+    for (auto& e : ev) (void)hipEventCreate(&e);
+  }
+  ~LaunchClock() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+  // slot kBuckets: the global-path launch for overflowing LDS tables
+  lp_status start(int slot, hipStream_t st) {
+    used[slot] = true;
+    LP_HIP(hipEventRecord(ev[2 * slot], st));
+    return LP_OK;
+  }
+  lp_status stop(int slot, hipStream_t st) {
+    LP_HIP(hipEventRecord(ev[2 * slot + 1], st));
+    return LP_OK;
+  }
+  // after the stream has passed every stop event
+  void collect() {
+    for (int s = 0; s <= kBuckets; s++) {
+      if (!used[s]) continue;
+      float t = 0;
+      if (hipEventElapsedTime(&t, ev[2 * s], ev[2 * s + 1]) != hipSuccess) (void)hipGetLastError();
+      lp_bucket_stats& b = stats->bucket[s < kBuckets ? s : kBucketHuge];
+      b.ms += t;
+      b.launches += 1;
+      used[s] = false;
+    }
+  }
+};
+
+// Work counters of the launches of one call: 8 uint64 per bucket.
+static unsigned long long* work_counters(Workspace& w) {
+  return reinterpret_cast<unsigned long long*>(w.counters.as<char>() + 1024);
+}
+
+static lp_status collect_work(Workspace& w, lp_stats* S, hipStream_t st) {
+  unsigned long long h[kBuckets * 8];
+  LP_HIP(hipMemcpyAsync(h, work_counters(w), sizeof(h), hipMemcpyDeviceToHost, st));
+  LP_HIP(hipStreamSynchronize(st));
+  for (int b = 0; b < kBuckets; b++) {
+    S->bucket[b].sources = h[b * 8 + 0];
+    S->bucket[b].first_order = h[b * 8 + 1];
+    S->bucket[b].arcs = h[b * 8 + 2];
+    S->bucket[b].wedges = h[b * 8 + 3];
+    S->bucket[b].candidates = h[b * 8 + 4];
+  }
+  return LP_OK;
+}
+
 // The whole accumulation for one phase (all buckets, then overflow records).
 template <bool kW, bool kQuery>
-static lp_status run_phase(lp_graph* g, const GView& gv, const Emit& E, const SrcRec* lists,
+static lp_status run_phase(lp_graph* g, const GView& gv, const Emit& E0, const SrcRec* lists,
                            uint64_t list_stride, const uint32_t* counts_host, uint32_t stride,
-                           int phase, uint32_t* ovf_host_count, hipStream_t st) {
+                           int phase, uint32_t* ovf_host_count, LaunchClock* clk, hipStream_t st) {
+  unsigned long long* work = work_counters(g->ws);
   // largest buckets first: their long-running workgroups start early
   for (int b = kBuckets - 1; b >= 0; b--) {
     WorkList wl{lists + (uint64_t)b * list_stride, counts_host[b], stride, phase};
@@ -1246,35 +1333,47 @@ static lp_status run_phase(lp_graph* g, const GView& gv, const Emit& E, const Sr
       uint64_t ns = (counts_host[b] + stride - 1) / stride;
       items = phase == 1 ? ns : counts_host[b] - ns;
     }
+    if (items == 0) continue;
+    Emit E = E0;
+    E.work = work + b * 8;
+    if (clk) LP_TRY(clk->start(b, st));
     if (b == kBucketHuge) {
       LP_TRY((launch_spa<kW, kQuery>(g, gv, E, wl, SpaItem{nullptr, nullptr, 0, 0}, items, st)));
     } else {
       LP_TRY((launch_bucket<kW, kQuery>(g, b, gv, E, wl, items, st)));
     }
+    if (clk) LP_TRY(clk->stop(b, st));
   }
   // overflow records written by this phase's LDS kernels
   uint32_t ovf_total = 0;
-  LP_HIP(hipMemcpyAsync(&ovf_total, E.ovf_count, 4, hipMemcpyDeviceToHost, st));
+  LP_HIP(hipMemcpyAsync(&ovf_total, E0.ovf_count, 4, hipMemcpyDeviceToHost, st));
   LP_HIP(hipStreamSynchronize(st));
-  if (ovf_total > E.ovf_cap) return set_error(LP_ERR_OUT_OF_MEMORY, "overflow list exhausted");
+  if (ovf_total > E0.ovf_cap) return set_error(LP_ERR_OUT_OF_MEMORY, "overflow list exhausted");
   if (ovf_total > *ovf_host_count) {
     WorkList none{nullptr, 0, 1, 0};
-    SpaItem ov{E.ovf, static_cast<const SrcRec*>(E.ovf_rec), *ovf_host_count, ovf_total};
+    SpaItem ov{E0.ovf, static_cast<const SrcRec*>(E0.ovf_rec), *ovf_host_count, ovf_total};
+    Emit E = E0;
+    E.work = work + kBucketHuge * 8;
+    if (clk) LP_TRY(clk->start(kBuckets, st));
     LP_TRY((launch_spa<kW, kQuery>(g, gv, E, none, ov, ovf_total - *ovf_host_count, st)));
+    if (clk) LP_TRY(clk->stop(kBuckets, st));
     *ovf_host_count = ovf_total;
+    LP_HIP(hipStreamSynchronize(st));
   }
+  if (clk) clk->collect();
   return LP_OK;
 }
 
 template <bool kQuery>
 static lp_status run_phase_any(lp_graph* g, const GView& gv, const Emit& E, const SrcRec* lists,
                                uint64_t list_stride, const uint32_t* counts_host, uint32_t stride,
-                               int phase, uint32_t* ovf_host_count, hipStream_t st) {
+                               int phase, uint32_t* ovf_host_count, LaunchClock* clk,
+                               hipStream_t st) {
   if (E.measure == LP_AA || E.measure == LP_RA)
     return run_phase<true, kQuery>(g, gv, E, lists, list_stride, counts_host, stride, phase,
-                                   ovf_host_count, st);
+                                   ovf_host_count, clk, st);
   return run_phase<false, kQuery>(g, gv, E, lists, list_stride, counts_host, stride, phase,
-                                  ovf_host_count, st);
+                                  ovf_host_count, clk, st);
 }
 
 // Radix select of the k largest keys among entries [base, count) of the
@@ -1515,9 +1614,10 @@ lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int3
   const SrcRec* lists = w.lists.as<SrcRec>();
   uint32_t ovf_host = 0;
   unsigned long long n_sample = 0;
+  LaunchClock clk(&S);
   if (sample) {
     LP_TRY(run_phase_any<false>(g, gv, E, lists, (uint64_t)g->n, pr.out.count,
-                                stride, 1, &ovf_host, st));
+                                stride, 1, &ovf_host, &clk, st));
     LP_HIP(hipMemcpyAsync(&n_sample, count, 8, hipMemcpyDeviceToHost, st));
     LP_HIP(hipStreamSynchronize(st));
     if (n_sample > cap) return set_error(LP_ERR_OUT_OF_MEMORY, "sample exceeded its buffer");
@@ -1535,10 +1635,10 @@ lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int3
           LP_TRY(run_select(g, E.out_s, E.out_a, E.out_c, count, cap, 0, r_target, ts, ta, tc, tau, st));
       }
       LP_TRY(run_phase_any<false>(g, gv, E, lists, (uint64_t)g->n, pr.out.count,
-                                  stride, 2, &ovf_host, st));
+                                  stride, 2, &ovf_host, &clk, st));
     } else {
       LP_TRY(run_phase_any<false>(g, gv, E, lists, (uint64_t)g->n, pr.out.count,
-                                  1, 0, &ovf_host, st));
+                                  1, 0, &ovf_host, &clk, st));
     }
     if (retries == 0) LP_HIP(hipEventRecord(tm.ev[2], st));
     unsigned long long n_total = 0;
@@ -1615,6 +1715,7 @@ lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int3
     LP_HIP(hipStreamSynchronize(st));
     if (herr) return set_error(LP_ERR_DEVICE, "device error flags 0x%x", herr);
     *out_count = (int64_t)kout;
+    LP_TRY(collect_work(w, &S, st));
     S.ms_plan = tm.ms(0, 1);
     S.ms_accumulate = tm.ms(1, 2);
     S.ms_select = tm.ms(2, 3);
@@ -1651,10 +1752,12 @@ lp_status run_fingerprint(lp_graph* g, int64_t L, uint64_t* out, hipStream_t st)
   E.ovf_cap = ovf_cap;
   E.err = err;
   uint32_t ovf_host = 0;
-  if (pr.out.wedges)
+  if (pr.out.wedges) {
+    LaunchClock clk(&S);
     LP_TRY(run_phase_any<false>(g, view_of(g), E, w.lists.as<SrcRec>(), (uint64_t)g->n,
-                                pr.out.count, 1, 0,
-                                &ovf_host, st));
+                                pr.out.count, 1, 0, &ovf_host, &clk, st));
+    LP_TRY(collect_work(w, &S, st));
+  }
   unsigned long long h[3];
   uint32_t herr = 0;
   LP_HIP(hipMemcpyAsync(h, fp, 24, hipMemcpyDeviceToHost, st));
@@ -1728,7 +1831,7 @@ lp_status run_query(lp_graph* g, const int32_t* sources, int64_t nq, int m, int6
   E.err = err;
   uint32_t ovf_host = 0;
   if (po.wedges)
-    LP_TRY(run_phase_any<true>(g, gv, E, qlists, Q, po.count, 1, 0, &ovf_host, st));
+    LP_TRY(run_phase_any<true>(g, gv, E, qlists, Q, po.count, 1, 0, &ovf_host, nullptr, st));
   unsigned long long n_total = 0;
   LP_HIP(hipMemcpyAsync(&n_total, count, 8, hipMemcpyDeviceToHost, st));
   LP_HIP(hipStreamSynchronize(st));

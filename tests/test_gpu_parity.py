@@ -166,6 +166,43 @@ def test_global_path_and_partitions(lp, config1):
         assert st["buckets"]["large"] > 0
 
 
+def _launch_sums(st):
+    tot = {f: 0 for f in ("launches", "sources", "wedges", "candidates")}
+    for b in st["launches"].values():
+        for f in tot:
+            tot[f] += b[f]
+        assert (b["ms"] > 0) == (b["launches"] > 0)
+    return tot
+
+
+@pytest.mark.parametrize("L", [2, 256, None])
+def test_launch_work_counters(lp, config1, L):
+    """Per-launch work counters: over a call, the wedges and the distinct
+    candidates the accumulation kernels report add up to W_L and |C_L|."""
+    gr, k = config1
+    say(f"[gpu] launch work counters L={L}")
+    ref = oracle.fingerprint(gr, L)
+    with lp.Graph(gr.offsets, gr.indices) as g:
+        for cap in (0, 40):
+            lp.set_tuning(g, lds_wedge_cap=cap)
+            assert lp.fingerprint(g, L) == ref
+            st = lp.last_stats(g)
+            tot = _launch_sums(st)
+            assert tot["wedges"] == ref[3] == st["wedges"]
+            assert tot["candidates"] == ref[0]
+            assert tot["sources"] == st["sources"]
+            assert st["launches"]["global"]["sources"] >= st["buckets"]["global"]
+            if cap == 40 and L is None:
+                assert st["buckets"]["global"] > 0
+        lp.set_tuning(g, sample_budget=20000)
+        run_predict(lp, g, "JC", L, 50)
+        st = lp.last_stats(g)
+        tot = _launch_sums(st)
+        if st["retries"] == 0:
+            assert tot["wedges"] == ref[3]
+            assert tot["candidates"] == ref[0]
+
+
 def test_sampled_threshold_path(lp, config1):
     """The top-k threshold estimated from a sample, including its retries."""
     gr, k = config1
