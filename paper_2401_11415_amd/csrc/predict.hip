@@ -74,13 +74,15 @@ __device__ inline uint32_t lower_bound_dev(const uint32_t* __restrict__ a, uint3
   return lo;
 }
 
-__device__ inline int bucket_of(uint32_t U, uint32_t lds_cap) {
+// Bucket of a source with U wedges and T = U + (first-order neighbours to
+// exclude) table entries at most; sources without wedges have no candidates.
+__device__ inline int bucket_of(uint32_t U, uint32_t T, uint32_t lds_cap) {
   if (U == 0) return -1;
-  if (U > lds_cap) return kBucketHuge;
-  if (U <= 32) return kBucketTiny;
-  if (U <= 256) return kBucketSmall;
-  if (U <= 1024) return kBucketMid1;
-  if (U <= 4096) return kBucketMid2;
+  if (T > lds_cap) return kBucketHuge;
+  if (T <= 32) return kBucketTiny;
+  if (T <= 256) return kBucketSmall;
+  if (T <= 1024) return kBucketMid1;
+  if (T <= 4096) return kBucketMid2;
   return kBucketLarge;
 }
 
@@ -105,12 +107,14 @@ __global__ __launch_bounds__(256) void plan_kernel(GView g, uint32_t hub_start, 
     bk[j] = 0xFF;
     if (a < g.n) {
       const uint32_t h0 = g.hoff[a], h1 = g.hoff[a + 1];
-      uint32_t U = 0;
+      uint32_t U = 0, T = 0;
       if (h1 > h0) {
         const uint32_t k = lower_bound_dev(g.hb, h0, h1, hub_start) - h0;
         U = k ? g.hpsum[h0 + k - 1] : 0u;
+        const uint64_t t = (uint64_t)U + (g.off[a + 1] - g.off[a] - g.below[a]);
+        T = t > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)t;
       }
-      const int b = bucket_of(U, lds_cap);
+      const int b = bucket_of(U, T, lds_cap);
       if (b >= 0) {
         bk[j] = (uint8_t)b;
         nb[b]++;
@@ -207,7 +211,8 @@ __global__ __launch_bounds__(256) void query_plan_kernel(GView g, uint32_t hub_s
     if (threadIdx.x == 0) {
       const unsigned long long tot = part[0] + part[1] + part[2] + part[3];
       const uint32_t U = tot > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)tot;
-      const int b = bucket_of(U, lds_cap);
+      const uint64_t t = (uint64_t)U + (e1 - e0);
+      const int b = bucket_of(U, t > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)t, lds_cap);
       if (b >= 0) {
         SrcRec r;
         r.a = s;
@@ -389,7 +394,7 @@ struct LdsTab {
   uint32_t start[NG][G];
   uint64_t w[kW ? NG : 1][kW ? G : 1];
   uint32_t scan_tmp[G > 64 ? G / 64 : 1];
-  int ovf[NG];
+  int ovf[NG][2];
   uint8_t mark[NW][64];
   uint32_t rt_key[NW][64];
   uint32_t rt_h[NW][64];
@@ -433,10 +438,25 @@ __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, WorkList 
   // slots [0, clean) of the group's table are empty: every sweep empties the
   // slots it reads, so only growth beyond the largest table so far is cleared
   uint32_t clean = 0;
-  for (uint32_t i = blockIdx.x * NG + grp; i < total; i += gridDim.x * NG) {
-    const SrcRec s = uniform_rec(load_rec(wl, i));
+  // The group meets at two barriers per source (and chunk of arcs): after the
+  // chunk scratch is loaded and after the last table update.  The sweep of
+  // one source runs into the next source's first barrier, which is safe: the
+  // next source clears only slots beyond the swept ones, and its first table
+  // update follows that barrier.  The overflow flag alternates between two
+  // words so that resetting one cannot race a late reader.
+  uint32_t par = 0;
+  const uint32_t step = gridDim.x * NG;
+  uint32_t i = blockIdx.x * NG + grp;
+  SrcRec nxt{};
+  if (i < total) nxt = load_rec(wl, i);
+  for (; i < total; i += step) {
+    const SrcRec s = uniform_rec(nxt);
+    if (i + step < total) nxt = load_rec(wl, i + step);  // in flight during this source
+    // first batch of first-order ids, in flight during the accumulation
+    const uint32_t xe = s.x0 + gl;
+    const uint32_t xb = xe < s.x1 ? g.adj[xe] : kEmpty32;
     uint32_t P, S;
-    table_geometry(s.U, SLOTS, &P, &S);
+    table_geometry(s.U + (s.x1 - s.x0), SLOTS, &P, &S);
     const uint32_t hmin = kW ? 1u : min_count(E.measure, ts_bits, s.da, !kQuery);
     bool handed = false;
     for (uint32_t pass = 0; pass < P; pass++) {
@@ -451,11 +471,12 @@ __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, WorkList 
         }
         clean = S;
       }
-      if (gl == 0) L.ovf[grp] = 0;
-      group_sync<G>();
+      par ^= 1u;
+      if (gl == 0) L.ovf[grp][par] = 0;
       bool full = false;
       for (uint32_t cb = 0; cb < s.na; cb += G) {
         uint32_t lo, hi;
+        if (cb > 0) group_sync<G>();  // every wave is done with the previous chunk
         load_chunk<G, kQuery, kW>(g, E, s, cb, s_excl, s_start, s_w, L.scan_tmp, &lo, &hi);
         group_sync<G>();
         const uint32_t narcs = s.na - cb < (uint32_t)G ? s.na - cb : (uint32_t)G;
@@ -473,20 +494,20 @@ __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, WorkList 
             full = full | !ok;
           }
         });
-        full = full | !retry_drain<kW>(tab, keys, vals, S, RT);
-        group_sync<G>();
       }
-      if (full) L.ovf[grp] = 1;
-      // first-order neighbours are not candidates: flag their entries
+      // first-order neighbours are not candidates: they enter flagged
       for (uint32_t e0 = s.x0; e0 < s.x1; e0 += G) {
         const uint32_t e = e0 + gl;
-        uint32_t b = e < s.x1 ? g.adj[e] : kEmpty32;
+        uint32_t b = e0 == s.x0 ? xb : (e < s.x1 ? g.adj[e] : kEmpty32);
         if (P > 1 && b != kEmpty32 && key_part(b, P) != pass) b = kEmpty32;
-        tab_mark<kW>(tab, keys, vals, S, b, key_slot(b, S), RT);
+        const bool ok = tab_insert<kW>(tab, keys, vals, S, b, key_slot(b, S),
+                                       kW ? kBlocked64W : kBlocked64, RT);
+        full = full | !ok;
       }
-      mark_drain<kW>(tab, keys, vals, S, RT);
+      full = full | !retry_drain<kW>(tab, keys, vals, S, RT);
+      if (full) L.ovf[grp][par] = 1;
       group_sync<G>();
-      if (L.ovf[grp]) {
+      if (L.ovf[grp][par]) {
         // the table filled up: hand the rest of this source to the global path
         clean = 0;
         if (gl == 0) {
@@ -530,7 +551,6 @@ __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, WorkList 
         wk.v[4] += cand ? 1u : 0u;
         stage_add<kQuery, kW>(E, g, SG, ok, c, h, wsum, s.key, s.da, fa);
       }
-      group_sync<G>();
     }
     if (!handed && gl == 0) wk.source(s.da, s.na, s.U);
   }
@@ -649,9 +669,15 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
     }
     __syncthreads();
     const uint32_t NA = uniform(L.arcoff[B]), UT = uniform(L.wedoff[B]), NX = uniform(L.xoff[B]);
-    uint32_t S = (uint32_t)(((uint64_t)UT * 3 + 1) / 2);
+    uint32_t S = (uint32_t)(((uint64_t)(UT + NX) * 3 + 1) / 2);
     if (S < 16) S = 16;
     if (S > (uint32_t)SLOTS) S = SLOTS;  // cannot happen within the bucket's bounds
+    // first batch of first-order keys, in flight during the accumulation
+    uint32_t xkey = kEmpty32;
+    if ((uint32_t)tid < NX) {
+      const uint32_t xi = (uint32_t)batch_search<B>(L.xoff, (uint32_t)tid);
+      xkey = (xi << kBatchIdBits) | g.adj[L.rec[xi].x0 + ((uint32_t)tid - L.xoff[xi])];
+    }
     if (S > clean) {
       for (uint32_t t = clean + tid; t < S; t += WGS) {
         if (kW) {
@@ -662,10 +688,10 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
         }
       }
       clean = S;
-      __syncthreads();
     }
     bool full = false;
     for (uint32_t cb = 0; cb < NA; cb += WGS) {
+      if (cb > 0) __syncthreads();  // every wave is done with the previous chunk
       const uint32_t q = cb + tid;
       const bool qin = q < NA;
       const uint32_t qc = qin ? q : cb;
@@ -698,21 +724,21 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
           full = full | !ok;
         }
       });
-      full = full | !retry_drain<kW>(L.tab, L.keys, L.vals, S, RT);
-      __syncthreads();
     }
-    if (full) L.ovf = 1;
-    // first-order neighbours are not candidates: flag their entries
+    // first-order neighbours are not candidates: they enter flagged
     for (uint32_t x0 = 0; x0 < NX; x0 += WGS) {
       const uint32_t x = x0 + tid;
-      uint32_t key = kEmpty32;
-      if (x < NX) {
+      uint32_t key = x0 == 0 ? xkey : kEmpty32;
+      if (x0 != 0 && x < NX) {
         const uint32_t i = (uint32_t)batch_search<B>(L.xoff, x);
         key = (i << kBatchIdBits) | g.adj[L.rec[i].x0 + (x - L.xoff[i])];
       }
-      tab_mark<kW>(L.tab, L.keys, L.vals, S, key, key_slot(key, S), RT);
+      const bool ok = tab_insert<kW>(L.tab, L.keys, L.vals, S, key, key_slot(key, S),
+                                     kW ? kBlocked64W : kBlocked64, RT);
+      full = full | !ok;
     }
-    mark_drain<kW>(L.tab, L.keys, L.vals, S, RT);
+    full = full | !retry_drain<kW>(L.tab, L.keys, L.vals, S, RT);
+    if (full) L.ovf = 1;
     __syncthreads();
     if (L.ovf) {
       // a full table: every source of the batch goes to the global path whole
