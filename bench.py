@@ -31,13 +31,15 @@ BUCKET_KERNELS = {
     False: {"tiny": "acc_batch_kernel<256, 48, 3072, false, 64>",
             "small": "acc_batch_kernel<256, 8, 3072, false, 64>",
             "mid1": "acc_batch_kernel<256, 2, 3072, false, 64>",
-            "mid2": "acc_lds_kernel<512, 512, 6144, false, false, 64>",
+            "mid2": "acc_lds_kernel<256, 256, 3072, false, false, 64>",
+            "mid3": "acc_lds_kernel<512, 512, 6144, false, false, 64>",
             "large": "acc_lds_kernel<1024, 1024, 14336, false, false, 64>",
             "global": "acc_spa_kernel<false, false>"},
     True: {"tiny": "acc_batch_kernel<256, 48, 3072, true, 64>",
            "small": "acc_batch_kernel<256, 8, 3072, true, 64>",
            "mid1": "acc_batch_kernel<256, 2, 3072, true, 64>",
-           "mid2": "acc_lds_kernel<512, 512, 4608, true, false, 64>",
+           "mid2": "acc_lds_kernel<256, 256, 3072, true, false, 64>",
+           "mid3": "acc_lds_kernel<512, 512, 4608, true, false, 64>",
            "large": "acc_lds_kernel<1024, 1024, 7680, true, false, 64>",
            "global": "acc_spa_kernel<true, false>"},
 }

@@ -173,7 +173,7 @@ typedef struct {
   uint64_t appended;          /* candidates written to the selection buffer */
   uint64_t retries;           /* extra passes after a threshold estimate missed */
   double ms_plan, ms_accumulate, ms_select, ms_total; /* device time per phase */
-  lp_bucket_stats bucket[8];  /* per bucket: tiny, small, mid1, mid2, large, global */
+  lp_bucket_stats bucket[8];  /* per bucket: tiny, small, mid1, mid2, mid3, large, global */
 } lp_stats;
 lp_status lp_last_stats(const lp_graph *g, lp_stats *out);
 

@@ -24,7 +24,7 @@ __all__ = ["MEASURES", "HUB_NONE", "LpError", "Graph", "predict", "query", "fing
 MEASURES = ("CN", "JC", "SI", "SC", "HP", "HD", "LHN", "AA", "RA")
 HUB_NONE = (1 << 63) - 1  # L_H = infinity: IBase
 # scheduling buckets of the accumulation, by wedges per source (lp_stats order)
-BUCKETS = ("tiny", "small", "mid1", "mid2", "large", "global")
+BUCKETS = ("tiny", "small", "mid1", "mid2", "mid3", "large", "global")
 LP_VALIDATE = 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))

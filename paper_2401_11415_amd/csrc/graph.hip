@@ -212,7 +212,7 @@ uint32_t hub_start(const lp_graph* g, int64_t L) {
 
 static void free_graph_arrays(lp_graph* g) {
   uint32_t** arrs[] = {&g->off, &g->adj, &g->hoff, &g->hb, &g->hstart, &g->hpsum,
-                       &g->deg, &g->below, &g->perm, &g->rank};
+                       &g->deg, &g->below, &g->perm, &g->rank, &g->deg_first};
   for (auto p : arrs) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
@@ -401,6 +401,18 @@ lp_status build_graph(int64_t n, const int64_t* offsets, const int32_t* indices,
   g->n = n;
   g->arcs = arcs;
   g->max_deg = n > 0 ? g->host_deg[(size_t)n - 1] : 0;
+  // degree -> first new id of at least that degree (ids are in degree order),
+  // for degrees up to deg_cap; scoring uses it to bound d_c from an id alone
+  {
+    const uint32_t cap = (uint32_t)std::min<int64_t>(g->max_deg + 1, 65536);
+    std::vector<uint32_t> first((size_t)cap + 1);
+    for (uint32_t d = 0; d <= cap; d++)
+      first[d] = (uint32_t)(std::lower_bound(g->host_deg.begin(), g->host_deg.end(), d) - g->host_deg.begin());
+    LP_HIP(hipMalloc((void**)&g->deg_first, first.size() * 4));
+    LP_HIP(hipMemcpy(g->deg_first, first.data(), first.size() * 4, hipMemcpyHostToDevice));
+    g->deg_cap = cap;
+    g->device_bytes += (int64_t)(first.size() * 4);
+  }
   // AA / RA fixed point: a sum of at most max_deg terms, each <= 1/ln 2 < 1.45,
   // must stay below 2^63.
   int shift = 44;

@@ -20,6 +20,8 @@ struct GView {
   const uint32_t* deg;
   const uint32_t* below;
   const uint32_t* perm;
+  const uint32_t* deg_first;  // [deg_cap + 1] first id whose degree is >= d
+  uint32_t deg_cap;
   uint32_t n;
 };
 
@@ -163,6 +165,36 @@ __device__ inline uint32_t min_count(int m, uint32_t ts_bits, uint32_t da, bool 
   while (h < hmax && bound_score(m, h, da, ordered) < ts) h++;
   while (h > 1 && bound_score(m, h - 1, da, ordered) >= ts) h--;
   return h;
+}
+
+// Candidates with count h of a source of degree da can reach the score lo
+// only if d_c stays below a bound that follows from the measure:
+//   JC: d_c <= h / lo + h - d_a   SI: d_c <= h / lo - d_a
+//   SC: d_c <= h^2 / (lo^2 d_a)   LHN: d_c <= h / (lo d_a)
+//   HD: d_c <= h / lo (ordered: d_c >= d_a)
+// Ids are in degree order, so that is an id cutoff: candidates with an id
+// at or above the returned value cannot pass (0xFFFFFFFF: no cutoff).  The
+// bound is rounded up, so no passing candidate is ever cut.
+__device__ inline uint32_t id_cutoff(int m, uint32_t h, uint32_t da, double lo, const GView& g,
+                                     bool ordered) {
+  if (!(lo > 0.0) || da == 0) return 0xFFFFFFFFu;
+  const double H = (double)h, A = (double)da;
+  double X;
+  switch (m) {
+    case LP_JC: X = H / lo + H - A; break;
+    case LP_SI: X = H / lo - A; break;
+    case LP_SC: X = H * H / (lo * lo * A); break;
+    case LP_HD:
+      if (!ordered) return 0xFFFFFFFFu;
+      X = H / lo;
+      break;
+    case LP_LHN: X = H / (lo * A); break;
+    default: return 0xFFFFFFFFu;
+  }
+  X = X * (1.0 + 0x1p-40) + 1e-6;
+  if (!(X < (double)g.deg_cap)) return 0xFFFFFFFFu;
+  if (X < 0.0) return 0u;
+  return g.deg_first[(uint32_t)X + 1];
 }
 
 // Lower edge of the exact scores whose FP32 value can pass the threshold key

@@ -66,7 +66,7 @@ struct HostBuf {
 // the one that does little work.
 // ---------------------------------------------------------------------------
 
-constexpr int kNumBuckets = 6;  // scheduling buckets of the accumulation
+constexpr int kNumBuckets = 7;  // scheduling buckets of the accumulation
 
 struct Workspace {
   // plan
@@ -102,6 +102,8 @@ struct lp_graph {
   int64_t harcs = 0;
   uint32_t* deg = nullptr;       // n, non-decreasing
   uint32_t* below = nullptr;     // n, number of neighbours with a smaller id
+  uint32_t* deg_first = nullptr; // deg_cap + 1 entries: first new id whose degree is >= d
+  uint32_t deg_cap = 0;
   uint32_t* perm = nullptr;      // n, new id -> original id
   uint32_t* rank = nullptr;      // n, original id -> new id
   std::vector<uint32_t> host_deg;  // copy of deg (sorted), for hub boundaries

@@ -37,13 +37,14 @@ namespace lp {
 // ---------------------------------------------------------------------------
 
 enum : int {
-  kBucketTiny = 0,   // U <= 32:      16 lanes
-  kBucketSmall = 1,  // U <= 256:     64 lanes
-  kBucketMid1 = 2,   // U <= 1024:    128 lanes
-  kBucketMid2 = 3,   // U <= 4096:    256 lanes
-  kBucketLarge = 4,  // U <= cap:     1024 lanes, hash partitions
-  kBucketHuge = 5,   // U >  cap:     dense accumulator in global memory
-  kBuckets = 6
+  kBucketTiny = 0,   // T <= 32:      48 sources per 256-lane workgroup
+  kBucketSmall = 1,  // T <= 256:     8 sources per workgroup
+  kBucketMid1 = 2,   // T <= 1024:    2 sources per workgroup
+  kBucketMid2 = 3,   // T <= 2048:    256 lanes per source
+  kBucketMid3 = 4,   // T <= 4096:    512 lanes per source
+  kBucketLarge = 5,  // T <= cap:     1024 lanes, hash partitions
+  kBucketHuge = 6,   // T >  cap:     dense accumulator in global memory
+  kBuckets = 7
 };
 
 // One source as the accumulation kernels see it (32 bytes, one load).
@@ -82,7 +83,8 @@ __device__ inline int bucket_of(uint32_t U, uint32_t T, uint32_t lds_cap) {
   if (T <= 32) return kBucketTiny;
   if (T <= 256) return kBucketSmall;
   if (T <= 1024) return kBucketMid1;
-  if (T <= 4096) return kBucketMid2;
+  if (T <= 2048) return kBucketMid2;
+  if (T <= 4096) return kBucketMid3;
   return kBucketLarge;
 }
 
@@ -99,7 +101,7 @@ __global__ __launch_bounds__(256) void plan_kernel(GView g, uint32_t hub_start, 
   const int lane = lane_id(), wid = threadIdx.x >> 6;
   const uint64_t tile = (uint64_t)blockIdx.x * 256 * kPlanItems;
   uint8_t bk[kPlanItems];
-  uint32_t nb[kBuckets] = {0, 0, 0, 0, 0, 0};
+  uint32_t nb[kBuckets] = {};
   unsigned long long w_sum = 0, s_sum = 0;
 #pragma unroll
   for (int j = 0; j < kPlanItems; j++) {
@@ -434,6 +436,7 @@ __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, WorkList 
   WorkAcc wk;
   const uint32_t ts_bits = E.fp_mode ? 0u : E.tau[0];
   const uint64_t wmin = kW ? min_wsum(E.measure, ts_bits, E.shift) : 1ull;
+  const double lo = E.fp_mode ? 0.0 : pass_edge(ts_bits, E.s_th);
   const uint32_t total = uniform(work_count(wl));
   // slots [0, clean) of the group's table are empty: every sweep empties the
   // slots it reads, so only growth beyond the largest table so far is cleared
@@ -452,12 +455,15 @@ __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, WorkList 
   for (; i < total; i += step) {
     const SrcRec s = uniform_rec(nxt);
     if (i + step < total) nxt = load_rec(wl, i + step);  // in flight during this source
-    // first batch of first-order ids, in flight during the accumulation
-    const uint32_t xe = s.x0 + gl;
+    // first batch of first-order ids, in flight during the accumulation (from
+    // the group's last wave on, which has the lightest share of the wedges)
+    const uint32_t xe = s.x0 + (G - 1 - gl);
     const uint32_t xb = xe < s.x1 ? g.adj[xe] : kEmpty32;
     uint32_t P, S;
     table_geometry(s.U + (s.x1 - s.x0), SLOTS, &P, &S);
     const uint32_t hmin = kW ? 1u : min_count(E.measure, ts_bits, s.da, !kQuery);
+    const uint32_t cut1 = kW ? 0xFFFFFFFFu : uniform(id_cutoff(E.measure, 1, s.da, lo, g, !kQuery));
+    const uint32_t cut2 = kW ? 0xFFFFFFFFu : uniform(id_cutoff(E.measure, 2, s.da, lo, g, !kQuery));
     bool handed = false;
     for (uint32_t pass = 0; pass < P; pass++) {
       if (S > clean) {
@@ -497,7 +503,7 @@ __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, WorkList 
       }
       // first-order neighbours are not candidates: they enter flagged
       for (uint32_t e0 = s.x0; e0 < s.x1; e0 += G) {
-        const uint32_t e = e0 + gl;
+        const uint32_t e = e0 + (G - 1 - gl);
         uint32_t b = e0 == s.x0 ? xb : (e < s.x1 ? g.adj[e] : kEmpty32);
         if (P > 1 && b != kEmpty32 && key_part(b, P) != pass) b = kEmpty32;
         const bool ok = tab_insert<kW>(tab, keys, vals, S, b, key_slot(b, S),
@@ -546,7 +552,7 @@ __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, WorkList 
           c = (uint32_t)v;
           h = (uint32_t)(v >> 32);
           cand = t < S && c != kEmpty32 && (h & kBlocked) == 0;
-          ok = cand && h >= hmin;
+          ok = cand && h >= hmin && !(h == 1 && c >= cut1) && !(h == 2 && c >= cut2);
         }
         wk.v[4] += cand ? 1u : 0u;
         stage_add<kQuery, kW>(E, g, SG, ok, c, h, wsum, s.key, s.da, fa);
@@ -585,6 +591,7 @@ struct BatchTab {
   uint32_t wedoff[B + 1];  // prefix of wedges
   uint32_t xoff[B + 1];    // prefix of first-order neighbours to exclude
   uint32_t hmin[B];
+  uint32_t cut[B][2];
   int ovf;
   uint8_t mark[NW][64];
   uint32_t rt_key[NW][64];
@@ -627,24 +634,36 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
   WorkAcc wk;
   const uint32_t ts_bits = E.fp_mode ? 0u : E.tau[0];
   const uint64_t wmin = kW ? min_wsum(E.measure, ts_bits, E.shift) : 1ull;
+  const double lo = E.fp_mode ? 0.0 : pass_edge(ts_bits, E.s_th);
   const uint32_t total = uniform(work_count(wl));
   const uint32_t nbatch = (total + B - 1) / B;
   uint32_t clean = 0;  // slots [0, clean) of the table are empty
+  // the first wave keeps the next batch's records in flight
+  SrcRec nrec{};
+  if (tid < B && blockIdx.x * B + tid < total) nrec = load_rec(wl, blockIdx.x * B + tid);
   for (uint32_t bi = blockIdx.x; bi < nbatch; bi += gridDim.x) {
     const uint32_t i0 = bi * B;
     const uint32_t nb = total - i0 < (uint32_t)B ? total - i0 : (uint32_t)B;
-    // records and their prefix sums (first wave)
+    // records and their prefix sums (first wave); the id cutoffs are loaded
+    // here and published after the accumulation, off the critical path
+    uint32_t cut0 = 0xFFFFFFFFu, cut1 = 0xFFFFFFFFu;
     if (tid < 64) {
       SrcRec r{};
       uint32_t na = 0, U = 0, nx = 0;
       if (tid < (int)nb) {
-        r = load_rec(wl, i0 + tid);
+        r = nrec;
         na = r.na;
         U = r.U;
         nx = r.x1 - r.x0;
         L.rec[tid] = r;
         L.hmin[tid] = kW ? 1u : min_count(E.measure, ts_bits, r.da, true);
+        if (!kW) {
+          cut0 = id_cutoff(E.measure, 1, r.da, lo, g, true);
+          cut1 = id_cutoff(E.measure, 2, r.da, lo, g, true);
+        }
       }
+      const uint32_t inext = i0 + gridDim.x * B + tid;
+      if (tid < B && inext < total) nrec = load_rec(wl, inext);
       uint32_t xa = na, xu = U, xx = nx;
 #pragma unroll
       for (int o = 1; o < 64; o <<= 1) {
@@ -674,9 +693,10 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
     if (S > (uint32_t)SLOTS) S = SLOTS;  // cannot happen within the bucket's bounds
     // first batch of first-order keys, in flight during the accumulation
     uint32_t xkey = kEmpty32;
-    if ((uint32_t)tid < NX) {
-      const uint32_t xi = (uint32_t)batch_search<B>(L.xoff, (uint32_t)tid);
-      xkey = (xi << kBatchIdBits) | g.adj[L.rec[xi].x0 + ((uint32_t)tid - L.xoff[xi])];
+    if ((uint32_t)(WGS - 1 - tid) < NX) {
+      const uint32_t xq = (uint32_t)(WGS - 1 - tid);
+      const uint32_t xi = (uint32_t)batch_search<B>(L.xoff, xq);
+      xkey = (xi << kBatchIdBits) | g.adj[L.rec[xi].x0 + (xq - L.xoff[xi])];
     }
     if (S > clean) {
       for (uint32_t t = clean + tid; t < S; t += WGS) {
@@ -725,9 +745,14 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
         }
       });
     }
-    // first-order neighbours are not candidates: they enter flagged
+    if (tid < (int)nb) {
+      L.cut[tid][0] = cut0;
+      L.cut[tid][1] = cut1;
+    }
+    // first-order neighbours are not candidates: they enter flagged (from the
+    // last wave on, which has the lightest share of the wedges)
     for (uint32_t x0 = 0; x0 < NX; x0 += WGS) {
-      const uint32_t x = x0 + tid;
+      const uint32_t x = x0 + (WGS - 1 - tid);
       uint32_t key = x0 == 0 ? xkey : kEmpty32;
       if (x0 != 0 && x < NX) {
         const uint32_t i = (uint32_t)batch_search<B>(L.xoff, x);
@@ -782,7 +807,10 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
         wk.v[4] += ok ? 1u : 0u;
       }
       const uint32_t i = ok ? key >> kBatchIdBits : 0u;
-      if (!kW) ok = ok && h >= L.hmin[i];
+      if (!kW) {
+        const uint32_t c = key & kBatchIdMask;
+        ok = ok && h >= L.hmin[i] && !(h == 1 && c >= L.cut[i][0]) && !(h == 2 && c >= L.cut[i][1]);
+      }
       stage_add<false, kW>(E, g, SG, ok, key & kBatchIdMask, h, wsum, L.rec[i].key, L.rec[i].da, fa);
     }
     __syncthreads();
@@ -1186,6 +1214,8 @@ static GView view_of(const lp_graph* g) {
   v.deg = g->deg;
   v.below = g->below;
   v.perm = g->perm;
+  v.deg_first = g->deg_first;
+  v.deg_cap = g->deg_cap;
   v.n = (uint32_t)g->n;
   return v;
 }
@@ -1249,6 +1279,10 @@ static lp_status launch_bucket(lp_graph* g, int bucket, const GView& gv, const E
                          dim3(grid_for(nitems, 1, cus * 16)), dim3(128), 0, st, gv, E, wl);
       break;
     case kBucketMid2:
+      hipLaunchKernelGGL((acc_lds_kernel<256, 256, 3072, kW, kQuery, 64>),
+                         dim3(grid_for(nitems, 1, cus * 8)), dim3(256), 0, st, gv, E, wl);
+      break;
+    case kBucketMid3:
       hipLaunchKernelGGL((acc_lds_kernel<512, 512, kW ? 4608 : 6144, kW, kQuery, 64>),
                          dim3(grid_for(nitems, 1, cus * 4)), dim3(512), 0, st, gv, E, wl);
       break;
