@@ -323,3 +323,49 @@ def test_invalid_inputs(lp):
         # the graph stays usable after errors
         a, c, s = lp.predict(g, "CN", None, 10)
         assert to_np(a).tolist() == [0, 1] and to_np(c).tolist() == [2, 3]
+
+
+@pytest.fixture(scope="module")
+def rmat22():
+    """The benchmark workload: R-MAT scale 22, edge factor 16, seed 1, 10% holdout."""
+    full = synth.rmat22(seed=1)
+    obs, held = synth.holdout(full, 0.1, seed=1)
+    return obs, int(held.shape[0])
+
+
+def test_full_size_rmat22_digest(lp, rmat22):
+    """Parity at the benchmark's full size (R-MAT-22, L = 256): the
+    candidate-set digest (|C_L|, sum h, sum mix64, W_L) is exact."""
+    gr, k = rmat22
+    say(f"[gpu] R-MAT-22 fingerprint n={gr.n}")
+    with lp.Graph(gr.offsets, gr.indices) as g:
+        assert lp.fingerprint(g, 256) == oracle.fingerprint(gr, 256)
+
+
+def test_full_size_rmat22_topk(lp, rmat22):
+    """The benchmark's own call (DLH JC, L = 256, k = |held out|, sampled
+    threshold): identical FP32 top-k list to the oracle's."""
+    gr, k = rmat22
+    say(f"[gpu] R-MAT-22 predict JC k={k}")
+    with lp.Graph(gr.offsets, gr.indices) as g:
+        got = run_predict(lp, g, "JC", 256, k)
+        st = lp.last_stats(g)
+        assert st["launches"]["mid3"]["launches"] > 0 and st["launches"]["large"]["launches"] > 0
+    ref = oracle.predict(gr, 256, "JC", k)
+    assert_same_list(got, ref, "JC", "R-MAT-22/JC/L=256")
+
+
+@pytest.mark.parametrize("m", ["JC", "RA"])
+def test_full_size_rmat22_query(lp, rmat22, m):
+    """Per-source ranked lists on R-MAT-22 for a seeded sample of sources,
+    including the 16 of highest degree."""
+    gr, _ = rmat22
+    src = synth.sample_sources(gr, 512, seed=7, top=16)
+    say(f"[gpu] R-MAT-22 query {m} ns={src.shape[0]}")
+    with lp.Graph(gr.offsets, gr.indices) as g:
+        c, s, cnt = lp.query(g, src, m, 256, 10)
+        c, s, cnt = to_np(c), to_np(s), to_np(cnt)
+    refq = oracle.query(gr, 256, m, src, 10)
+    for i in range(src.shape[0]):
+        assert_same_query((c[i][: cnt[i]], s[i][: cnt[i]]), refq[i], m,
+                          f"R-MAT-22 query {m} src={src[i]}")
