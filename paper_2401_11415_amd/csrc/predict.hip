@@ -345,7 +345,36 @@ constexpr int kWin = 4;  // windows of 64 wedges a wave decodes per round
 // Walk one wave's slice of a chunk's flat wedge range [lo, hi): the range is
 // cut into NWG slices of whole windows, one per wave of the group (wig =
 // wave's index in the group).  Per round of kWin windows, fn(c, arc, v) gets
-// each lane's wedges c (kEmpty32 where v is false) and their arcs.
+// each lane's wedges c (kEmpty32 where v is false) and their arcs.  Rounds
+// are software-pipelined: the next round is decoded and its wedge loads are
+// in flight while fn works on the current one.
+template <int NWG, int GA>
+struct WalkRound {
+  uint32_t arc[kWin], c[kWin];
+  bool v[kWin];
+  // decode the round starting at base (j: arc holding base, advanced) and
+  // issue its wedge loads
+  __device__ void start(const GView& g, const uint32_t* excl, const uint32_t* start_of, uint32_t narcs,
+                        uint8_t* mark, uint32_t base, uint32_t f1, uint32_t& j) {
+    const uint32_t lane = (uint32_t)lane_id();
+    uint32_t idx[kWin];
+#pragma unroll
+    for (int u = 0; u < kWin; u++) {
+      const uint32_t b = base + 64u * u;
+      arc[u] = 0;
+      v[u] = false;
+      idx[u] = 0;
+      if (b < f1) {
+        arc[u] = decode_window(excl, narcs, mark, b, j);
+        v[u] = b + lane < f1;
+        if (v[u]) idx[u] = start_of[arc[u]] + (b + lane - excl[arc[u]]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kWin; u++) c[u] = v[u] ? g.adj[idx[u]] : kEmpty32;
+  }
+};
+
 template <int NWG, int GA, typename Fn>
 __device__ inline void walk_chunk(const GView& g, const uint32_t* excl, const uint32_t* start,
                                   uint32_t narcs, uint32_t lo, uint32_t hi, int wig, uint8_t* mark,
@@ -356,27 +385,15 @@ __device__ inline void walk_chunk(const GView& g, const uint32_t* excl, const ui
   if (f0l >= hi) return;
   const uint32_t f0 = (uint32_t)f0l;
   const uint32_t f1 = (uint32_t)(f0l + q < (uint64_t)hi ? f0l + q : (uint64_t)hi);
-  const uint32_t lane = (uint32_t)lane_id();
   uint32_t j = uniform((uint32_t)seg_search<GA>(excl, f0));
+  WalkRound<NWG, GA> cur;
+  cur.start(g, excl, start, narcs, mark, f0, f1, j);
   for (uint32_t base = f0; base < f1; base += 64 * kWin) {
-    uint32_t arc[kWin], c[kWin];
-    bool v[kWin];
-#pragma unroll
-    for (int u = 0; u < kWin; u++) {
-      const uint32_t b = base + 64u * u;
-      arc[u] = 0;
-      v[u] = false;
-      uint32_t idx = 0;
-      if (b < f1) {
-        arc[u] = decode_window(excl, narcs, mark, b, j);
-        v[u] = b + lane < f1;
-        if (v[u]) idx = start[arc[u]] + (b + lane - excl[arc[u]]);
-      }
-      c[u] = idx;
-    }
-#pragma unroll
-    for (int u = 0; u < kWin; u++) c[u] = v[u] ? g.adj[c[u]] : kEmpty32;
-    fn(c, arc, v);
+    const uint32_t nbase = base + 64 * kWin;
+    WalkRound<NWG, GA> nxt;
+    if (nbase < f1) nxt.start(g, excl, start, narcs, mark, nbase, f1, j);
+    fn(cur.c, cur.arc, cur.v);
+    cur = nxt;
   }
 }
 
