@@ -177,6 +177,57 @@ typedef struct {
 } lp_stats;
 lp_status lp_last_stats(const lp_graph *g, lp_stats *out);
 
+/* ---------------------------------------------------------------------------
+ * Serving: a request loop over the per-source query (lp_query), for the
+ * recommendation use the paper describes in Section 1.  A server keeps the
+ * graph resident and runs up to `slots` batches at once, each on its own HIP
+ * stream with its own device scratch (candidate buffers, tables, sort space).
+ * Requests queue until a slot is free; a free slot takes the oldest request
+ * and every other queued request with the same measure, hub limit, k_q and
+ * threshold, up to max_batch_sources sources and max_batch_paths two-hop
+ * paths, and runs them as one query.  The path count of a source s is
+ * sum over b in Gamma(s) of d_b, an upper bound of its wedges under any hub
+ * limit; it bounds the batch's candidate buffer.  A request above either cap
+ * runs alone.  Each request's result equals lp_query on that request alone.
+ * Requests that arrive while batches run join the next batch of the slot that
+ * frees first, so work of several requests overlaps on the device.
+ * ------------------------------------------------------------------------- */
+typedef struct lp_server lp_server;
+
+typedef struct {
+  int32_t slots;             /* concurrent batches, 1..8 (0: 2) */
+  int64_t max_batch_sources; /* sources per batch (0: 16384) */
+  int64_t max_batch_paths;   /* two-hop paths per batch (0: 2^27) */
+} lp_server_config;
+
+typedef struct {
+  lp_status status;        /* of the batch that served the request */
+  uint64_t batch;          /* batch id (in launch order, from 1) */
+  uint32_t batch_requests; /* requests served by that batch */
+  uint64_t batch_sources;  /* sources in that batch */
+  double queue_ms;         /* submit -> batch start (host clock) */
+  double run_ms;           /* batch start -> results written */
+  double total_ms;         /* submit -> results written */
+} lp_request_info;
+
+/* g must outlive the server; while a server exists, lp_query / lp_predict on g
+ * from other threads stay allowed (they use the graph's own scratch). */
+lp_status lp_server_create(lp_graph *g, const lp_server_config *cfg, lp_server **out);
+/* Finishes every submitted request, then frees the server (not the graph). */
+lp_status lp_server_destroy(lp_server *s);
+/* Queue a request.  sources (original ids, host memory) is copied.  out_c and
+ * out_score (n_sources * k_q entries, row i = i-th source, best first) and
+ * out_count (n_sources) are host buffers that the server writes before the
+ * request completes; they must stay valid until lp_server_wait returns for the
+ * ticket.  Invalid arguments or a source outside [0, n) fail here. */
+lp_status lp_server_submit(lp_server *s, const int32_t *sources, int64_t n_sources, lp_measure m,
+                           int64_t hub_limit, int32_t k_q, float score_threshold, int32_t *out_c,
+                           float *out_score, int32_t *out_count, uint64_t *ticket);
+/* Wait for a request (timeout_ms < 0: no limit).  Returns the request's
+ * status; LP_ERR_BUSY if it is still running at the timeout.  Each ticket can
+ * be waited for successfully once (LP_ERR_INVALID_ARGUMENT afterwards). */
+lp_status lp_server_wait(lp_server *s, uint64_t ticket, int64_t timeout_ms, lp_request_info *info);
+
 /* Human-readable name of a status, and the detail of the last failure on the
  * calling thread ("" if none).  Both return static / thread-local storage. */
 const char *lp_status_string(lp_status s);

@@ -19,7 +19,7 @@ import os
 import numpy as np
 
 __all__ = ["MEASURES", "HUB_NONE", "LpError", "Graph", "predict", "query", "fingerprint",
-           "set_tuning", "last_stats", "library_path", "load"]
+           "set_tuning", "last_stats", "Server", "library_path", "load"]
 
 MEASURES = ("CN", "JC", "SI", "SC", "HP", "HD", "LHN", "AA", "RA")
 HUB_NONE = (1 << 63) - 1  # L_H = infinity: IBase
@@ -60,6 +60,18 @@ class _Stats(ctypes.Structure):
                 ("ms_total", ctypes.c_double), ("bucket", _BucketStats * 8)]
 
 
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("max_batch_sources", ctypes.c_int64),
+                ("max_batch_paths", ctypes.c_int64)]
+
+
+class _RequestInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("batch", ctypes.c_uint64),
+                ("batch_requests", ctypes.c_uint32), ("batch_sources", ctypes.c_uint64),
+                ("queue_ms", ctypes.c_double), ("run_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double)]
+
+
 def library_path() -> str:
     return _LIB
 
@@ -90,6 +102,15 @@ def load():
     lib.lp_set_tuning.argtypes = [vp, ctypes.POINTER(_Tuning)]
     lib.lp_last_stats.restype = st
     lib.lp_last_stats.argtypes = [vp, ctypes.POINTER(_Stats)]
+    lib.lp_server_create.restype = st
+    lib.lp_server_create.argtypes = [vp, ctypes.POINTER(_ServerConfig), ctypes.POINTER(vp)]
+    lib.lp_server_destroy.restype = st
+    lib.lp_server_destroy.argtypes = [vp]
+    lib.lp_server_submit.restype = st
+    lib.lp_server_submit.argtypes = [vp, vp, i64, ctypes.c_int, i64, i32, f32, vp, vp, vp,
+                                     ctypes.POINTER(ctypes.c_uint64)]
+    lib.lp_server_wait.restype = st
+    lib.lp_server_wait.argtypes = [vp, ctypes.c_uint64, i64, ctypes.POINTER(_RequestInfo)]
     lib.lp_status_string.restype = ctypes.c_char_p
     lib.lp_status_string.argtypes = [ctypes.c_int]
     lib.lp_last_error.restype = ctypes.c_char_p
@@ -241,3 +262,55 @@ def last_stats(g: Graph) -> dict:
             "buckets": dict(zip(BUCKETS, list(s.bucket_sources))), "appended": s.appended,
             "retries": s.retries, "ms_plan": s.ms_plan, "ms_accumulate": s.ms_accumulate,
             "ms_select": s.ms_select, "ms_total": s.ms_total, "launches": launches}
+
+
+class Server:
+    """Request loop over the per-source query (lp_server_*): submit() queues a
+    request and returns a ticket; wait() returns (c [n, k_q], score [n, k_q],
+    count [n]) numpy arrays and the request's timing / batch record."""
+
+    def __init__(self, g: Graph, slots: int = 0, max_batch_sources: int = 0,
+                 max_batch_paths: int = 0):
+        lib = load()
+        cfg = _ServerConfig(slots, max_batch_sources, max_batch_paths)
+        h = ctypes.c_void_p()
+        _check(lib.lp_server_create(g.handle, ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._g = g  # the graph must outlive the server
+        self._pending = {}
+
+    def submit(self, sources, measure, hub_limit, k_q: int, score_threshold: float = 0.0) -> int:
+        src = np.ascontiguousarray(np.asarray(sources, dtype=np.int32))
+        ns, k_q = int(src.shape[0]), int(k_q)
+        out = (np.zeros((ns, k_q), np.int32), np.zeros((ns, k_q), np.float32),
+               np.zeros(ns, np.int32))
+        t = ctypes.c_uint64(0)
+        _check(load().lp_server_submit(self._h, _ptr(src), ns, _measure(measure), _hub(hub_limit),
+                                       k_q, float(score_threshold), _ptr(out[0]), _ptr(out[1]),
+                                       _ptr(out[2]), ctypes.byref(t)))
+        self._pending[t.value] = (src, out)  # keep the buffers alive until wait()
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        info = _RequestInfo()
+        _check(load().lp_server_wait(self._h, int(ticket), int(timeout_ms), ctypes.byref(info)))
+        _, out = self._pending.pop(int(ticket))
+        rec = {f: getattr(info, f) for f, _ in _RequestInfo._fields_}
+        return out, rec
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            load().lp_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

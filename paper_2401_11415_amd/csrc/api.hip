@@ -12,7 +12,8 @@ void destroy_graph(lp_graph* g);
 lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int32_t* out_a,
                       int32_t* out_c, float* out_score, int64_t* out_count, hipStream_t st);
 lp_status run_fingerprint(lp_graph* g, int64_t L, uint64_t* out, hipStream_t st);
-lp_status run_query(lp_graph* g, const int32_t* sources, int64_t nq, int m, int64_t L, int32_t kq,
+lp_status run_query(lp_graph* g, Workspace& w, const int32_t* sources, int64_t nq, int m, int64_t L,
+                    int32_t kq,
                     float s_th, int32_t* out_c, float* out_score, int32_t* out_count,
                     hipStream_t st);
 const char* last_error_text();
@@ -151,7 +152,7 @@ lp_status lp_query(lp_graph* g, const int32_t* sources, int64_t n_sources, lp_me
     BusyGuard busy(g);
     if (!busy.ok) return set_error(LP_ERR_BUSY, "graph is in use by another thread");
     LP_TRY(select_device(g));
-    return run_query(g, sources, n_sources, (int)m, hub_limit, k_q, score_threshold, out_c,
+    return run_query(g, g->ws, sources, n_sources, (int)m, hub_limit, k_q, score_threshold, out_c,
                      out_score, out_count, (hipStream_t)hip_stream);
   });
 }

@@ -422,9 +422,7 @@ lp_status build_graph(int64_t n, const int64_t* offsets, const int32_t* indices,
   return LP_OK;
 }
 
-void destroy_graph(lp_graph* g) {
-  free_graph_arrays(g);
-  Workspace& w = g->ws;
+void release_workspace(Workspace& w) {
   DevBuf* all[] = {&w.cnt, &w.wedges, &w.lists, &w.counters, &w.stats, &w.cand_s, &w.cand_a,
                    &w.cand_c, &w.tmp_s[0], &w.tmp_s[1], &w.tmp_a[0], &w.tmp_a[1], &w.tmp_c[0],
                    &w.tmp_c[1], &w.hist, &w.sel_state, &w.sort_tmp[0], &w.sort_tmp[1],
@@ -432,6 +430,11 @@ void destroy_graph(lp_graph* g) {
                    &w.q_cnt, &w.q_wedges, &w.q_rows, &w.q_out};
   for (auto b : all) b->release();
   w.host_stats.release();
+}
+
+void destroy_graph(lp_graph* g) {
+  free_graph_arrays(g);
+  release_workspace(g->ws);
 }
 
 }  // namespace lp

@@ -1315,12 +1315,11 @@ static lp_status launch_bucket(lp_graph* g, int bucket, const GView& gv, const E
 }
 
 template <bool kW, bool kQuery>
-static lp_status launch_spa(lp_graph* g, const GView& gv, const Emit& E, WorkList wl, SpaItem ov,
-                            uint64_t nitems, hipStream_t st) {
+static lp_status launch_spa(lp_graph* g, Workspace& w, const GView& gv, const Emit& E, WorkList wl,
+                            SpaItem ov, uint64_t nitems, hipStream_t st) {
   if (nitems == 0) return LP_OK;
   AccConfig cfg = acc_config(g);
   const size_t n = (size_t)g->n;
-  Workspace& w = g->ws;
   // pool: cfg.spa_wgs slabs of 8n accumulator bytes, then as many key lists of 4n
   const size_t need = (size_t)cfg.spa_wgs * n * 12;
   if (w.global_tab.cap < need || w.global_slabs != cfg.spa_wgs) {
@@ -1397,10 +1396,11 @@ static lp_status collect_work(Workspace& w, lp_stats* S, hipStream_t st) {
 
 // The whole accumulation for one phase (all buckets, then overflow records).
 template <bool kW, bool kQuery>
-static lp_status run_phase(lp_graph* g, const GView& gv, const Emit& E0, const SrcRec* lists,
-                           uint64_t list_stride, const uint32_t* counts_host, uint32_t stride,
-                           int phase, uint32_t* ovf_host_count, LaunchClock* clk, hipStream_t st) {
-  unsigned long long* work = work_counters(g->ws);
+static lp_status run_phase(lp_graph* g, Workspace& w, const GView& gv, const Emit& E0,
+                           const SrcRec* lists, uint64_t list_stride, const uint32_t* counts_host,
+                           uint32_t stride, int phase, uint32_t* ovf_host_count, LaunchClock* clk,
+                           hipStream_t st) {
+  unsigned long long* work = work_counters(w);
   // largest buckets first: their long-running workgroups start early
   for (int b = kBuckets - 1; b >= 0; b--) {
     WorkList wl{lists + (uint64_t)b * list_stride, counts_host[b], stride, phase};
@@ -1415,7 +1415,7 @@ static lp_status run_phase(lp_graph* g, const GView& gv, const Emit& E0, const S
     E.work = work + b * 8;
     if (clk) LP_TRY(clk->start(b, st));
     if (b == kBucketHuge) {
-      LP_TRY((launch_spa<kW, kQuery>(g, gv, E, wl, SpaItem{nullptr, nullptr, 0, 0}, items, st)));
+      LP_TRY((launch_spa<kW, kQuery>(g, w, gv, E, wl, SpaItem{nullptr, nullptr, 0, 0}, items, st)));
     } else {
       LP_TRY((launch_bucket<kW, kQuery>(g, b, gv, E, wl, items, st)));
     }
@@ -1432,7 +1432,7 @@ static lp_status run_phase(lp_graph* g, const GView& gv, const Emit& E0, const S
     Emit E = E0;
     E.work = work + kBucketHuge * 8;
     if (clk) LP_TRY(clk->start(kBuckets, st));
-    LP_TRY((launch_spa<kW, kQuery>(g, gv, E, none, ov, ovf_total - *ovf_host_count, st)));
+    LP_TRY((launch_spa<kW, kQuery>(g, w, gv, E, none, ov, ovf_total - *ovf_host_count, st)));
     if (clk) LP_TRY(clk->stop(kBuckets, st));
     *ovf_host_count = ovf_total;
     LP_HIP(hipStreamSynchronize(st));
@@ -1442,14 +1442,14 @@ static lp_status run_phase(lp_graph* g, const GView& gv, const Emit& E0, const S
 }
 
 template <bool kQuery>
-static lp_status run_phase_any(lp_graph* g, const GView& gv, const Emit& E, const SrcRec* lists,
-                               uint64_t list_stride, const uint32_t* counts_host, uint32_t stride,
-                               int phase, uint32_t* ovf_host_count, LaunchClock* clk,
-                               hipStream_t st) {
+static lp_status run_phase_any(lp_graph* g, Workspace& w, const GView& gv, const Emit& E,
+                               const SrcRec* lists, uint64_t list_stride,
+                               const uint32_t* counts_host, uint32_t stride, int phase,
+                               uint32_t* ovf_host_count, LaunchClock* clk, hipStream_t st) {
   if (E.measure == LP_AA || E.measure == LP_RA)
-    return run_phase<true, kQuery>(g, gv, E, lists, list_stride, counts_host, stride, phase,
+    return run_phase<true, kQuery>(g, w, gv, E, lists, list_stride, counts_host, stride, phase,
                                    ovf_host_count, clk, st);
-  return run_phase<false, kQuery>(g, gv, E, lists, list_stride, counts_host, stride, phase,
+  return run_phase<false, kQuery>(g, w, gv, E, lists, list_stride, counts_host, stride, phase,
                                   ovf_host_count, clk, st);
 }
 
@@ -1693,7 +1693,7 @@ lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int3
   unsigned long long n_sample = 0;
   LaunchClock clk(&S);
   if (sample) {
-    LP_TRY(run_phase_any<false>(g, gv, E, lists, (uint64_t)g->n, pr.out.count,
+    LP_TRY(run_phase_any<false>(g, w, gv, E, lists, (uint64_t)g->n, pr.out.count,
                                 stride, 1, &ovf_host, &clk, st));
     LP_HIP(hipMemcpyAsync(&n_sample, count, 8, hipMemcpyDeviceToHost, st));
     LP_HIP(hipStreamSynchronize(st));
@@ -1711,10 +1711,10 @@ lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int3
         else
           LP_TRY(run_select(g, E.out_s, E.out_a, E.out_c, count, cap, 0, r_target, ts, ta, tc, tau, st));
       }
-      LP_TRY(run_phase_any<false>(g, gv, E, lists, (uint64_t)g->n, pr.out.count,
+      LP_TRY(run_phase_any<false>(g, w, gv, E, lists, (uint64_t)g->n, pr.out.count,
                                   stride, 2, &ovf_host, &clk, st));
     } else {
-      LP_TRY(run_phase_any<false>(g, gv, E, lists, (uint64_t)g->n, pr.out.count,
+      LP_TRY(run_phase_any<false>(g, w, gv, E, lists, (uint64_t)g->n, pr.out.count,
                                   1, 0, &ovf_host, &clk, st));
     }
     if (retries == 0) LP_HIP(hipEventRecord(tm.ev[2], st));
@@ -1831,7 +1831,7 @@ lp_status run_fingerprint(lp_graph* g, int64_t L, uint64_t* out, hipStream_t st)
   uint32_t ovf_host = 0;
   if (pr.out.wedges) {
     LaunchClock clk(&S);
-    LP_TRY(run_phase_any<false>(g, view_of(g), E, w.lists.as<SrcRec>(), (uint64_t)g->n,
+    LP_TRY(run_phase_any<false>(g, w, view_of(g), E, w.lists.as<SrcRec>(), (uint64_t)g->n,
                                 pr.out.count, 1, 0, &ovf_host, &clk, st));
     LP_TRY(collect_work(w, &S, st));
   }
@@ -1848,10 +1848,9 @@ lp_status run_fingerprint(lp_graph* g, int64_t L, uint64_t* out, hipStream_t st)
   return LP_OK;
 }
 
-lp_status run_query(lp_graph* g, const int32_t* sources, int64_t nq, int m, int64_t L, int32_t kq,
-                    float s_th, int32_t* out_c, float* out_score, int32_t* out_count,
+lp_status run_query(lp_graph* g, Workspace& w, const int32_t* sources, int64_t nq, int m, int64_t L,
+                    int32_t kq, float s_th, int32_t* out_c, float* out_score, int32_t* out_count,
                     hipStream_t st) {
-  Workspace& w = g->ws;
   if (nq == 0) return LP_OK;
   const uint64_t Q = (uint64_t)nq;
   // sources to device (validated on the host side by the caller)
@@ -1908,7 +1907,7 @@ lp_status run_query(lp_graph* g, const int32_t* sources, int64_t nq, int m, int6
   E.err = err;
   uint32_t ovf_host = 0;
   if (po.wedges)
-    LP_TRY(run_phase_any<true>(g, gv, E, qlists, Q, po.count, 1, 0, &ovf_host, nullptr, st));
+    LP_TRY(run_phase_any<true>(g, w, gv, E, qlists, Q, po.count, 1, 0, &ovf_host, nullptr, st));
   unsigned long long n_total = 0;
   LP_HIP(hipMemcpyAsync(&n_total, count, 8, hipMemcpyDeviceToHost, st));
   LP_HIP(hipStreamSynchronize(st));

@@ -1,0 +1,315 @@
+// serve.hip - request loop over the per-source query with continuous
+// batching: a queue of requests, `slots` workers, each with its own HIP
+// stream and device scratch, forming batches from whatever is queued when
+// they become free (host code plus one setup kernel).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "lp_common.h"
+
+namespace lp {
+lp_status run_query(lp_graph* g, Workspace& w, const int32_t* sources, int64_t nq, int m, int64_t L,
+                    int32_t kq, float s_th, int32_t* out_c, float* out_score, int32_t* out_count,
+                    hipStream_t st);
+void release_workspace(Workspace& w);
+void clear_error();
+
+// Two-hop paths from each vertex (original id order): sum of the degrees of
+// its neighbours, an upper bound of its wedges under any hub limit.
+__global__ void path_bound_kernel(const uint32_t* __restrict__ off, const uint32_t* __restrict__ adj,
+                                  const uint32_t* __restrict__ deg, const uint32_t* __restrict__ rank,
+                                  int64_t n, unsigned long long* __restrict__ out) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= n) return;
+  const uint32_t v = rank[o];
+  unsigned long long s = 0;
+  for (uint32_t e = off[v]; e < off[v + 1]; e++) s += deg[adj[e]];
+  out[o] = s;
+}
+}  // namespace lp
+
+using namespace lp;
+using Clock = std::chrono::steady_clock;
+
+namespace {
+
+struct Request {
+  uint64_t id = 0;
+  std::vector<int32_t> sources;
+  int m = 0;
+  int64_t L = 0;
+  int32_t kq = 0;
+  float s_th = 0;
+  int32_t* out_c = nullptr;
+  float* out_s = nullptr;
+  int32_t* out_n = nullptr;
+  uint64_t paths = 0;
+  Clock::time_point t_submit, t_start, t_done;
+  lp_request_info info{};
+  bool done = false;
+};
+
+bool same_kind(const Request& a, const Request& b) {
+  return a.m == b.m && a.L == b.L && a.kq == b.kq && a.s_th == b.s_th;
+}
+
+double ms_between(Clock::time_point a, Clock::time_point b) {
+  return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+}  // namespace
+
+struct lp_server {
+  lp_graph* g = nullptr;
+  lp_server_config cfg{};
+  std::vector<unsigned long long> paths;  // per original id
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Request*> queue;
+  std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
+  uint64_t next_id = 1, next_batch = 1;
+  int running = 0;
+  bool stop = false;
+  struct Slot {
+    Workspace ws;
+    hipStream_t st = nullptr;
+    std::vector<int32_t> src, c, n;
+    std::vector<float> s;
+    std::thread th;
+  };
+  std::vector<std::unique_ptr<Slot>> slots;
+
+  void worker(Slot* sl);
+};
+
+void lp_server::worker(Slot* sl) {
+  (void)hipSetDevice(g->device);
+  for (;;) {
+    std::vector<Request*> batch;
+    uint64_t bid = 0;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv_work.wait(lk, [&] { return stop || !queue.empty(); });
+      if (queue.empty()) return;  // stop requested and nothing left
+      // the oldest request, then every queued one of the same kind that fits
+      Request* r0 = queue.front();
+      queue.pop_front();
+      batch.push_back(r0);
+      uint64_t ns = r0->sources.size(), np = r0->paths;
+      for (auto it = queue.begin(); it != queue.end();) {
+        Request* r = *it;
+        if (same_kind(*r, *r0) && ns + r->sources.size() <= (uint64_t)cfg.max_batch_sources &&
+            np + r->paths <= (uint64_t)cfg.max_batch_paths) {
+          ns += r->sources.size();
+          np += r->paths;
+          batch.push_back(r);
+          it = queue.erase(it);
+        } else {
+          ++it;
+        }
+      }
+      bid = next_batch++;
+      running++;
+    }
+    const Clock::time_point t0 = Clock::now();
+    const Request& k = *batch[0];
+    size_t total = 0;
+    for (auto* r : batch) total += r->sources.size();
+    sl->src.resize(total);
+    size_t pos = 0;
+    for (auto* r : batch) {
+      std::copy(r->sources.begin(), r->sources.end(), sl->src.begin() + pos);
+      pos += r->sources.size();
+    }
+    sl->c.resize(total * (size_t)k.kq);
+    sl->s.resize(total * (size_t)k.kq);
+    sl->n.resize(total);
+    clear_error();
+    lp_status status = LP_OK;
+    try {
+      status = run_query(g, sl->ws, sl->src.data(), (int64_t)total, k.m, k.L, k.kq, k.s_th,
+                         sl->c.data(), sl->s.data(), sl->n.data(), sl->st);
+    } catch (const std::bad_alloc&) {
+      status = LP_ERR_OUT_OF_MEMORY;
+    } catch (...) {
+      status = LP_ERR_DEVICE;
+    }
+    // results to each request's buffers
+    pos = 0;
+    for (auto* r : batch) {
+      const size_t m = r->sources.size();
+      if (status == LP_OK) {
+        std::copy(sl->c.begin() + pos * k.kq, sl->c.begin() + (pos + m) * k.kq, r->out_c);
+        std::copy(sl->s.begin() + pos * k.kq, sl->s.begin() + (pos + m) * k.kq, r->out_s);
+        std::copy(sl->n.begin() + pos, sl->n.begin() + pos + m, r->out_n);
+      }
+      pos += m;
+    }
+    const Clock::time_point t1 = Clock::now();
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      for (auto* r : batch) {
+        r->t_start = t0;
+        r->t_done = t1;
+        r->info.status = status;
+        r->info.batch = bid;
+        r->info.batch_requests = (uint32_t)batch.size();
+        r->info.batch_sources = total;
+        r->info.queue_ms = ms_between(r->t_submit, t0);
+        r->info.run_ms = ms_between(t0, t1);
+        r->info.total_ms = ms_between(r->t_submit, t1);
+        r->done = true;
+      }
+      running--;
+    }
+    cv_done.notify_all();
+  }
+}
+
+extern "C" {
+
+lp_status lp_server_create(lp_graph* g, const lp_server_config* cfg, lp_server** out) {
+  clear_error();
+  if (!g || !out) return set_error(LP_ERR_INVALID_ARGUMENT, "graph or out is NULL");
+  *out = nullptr;
+  try {
+    std::unique_ptr<lp_server> s(new lp_server());
+    s->g = g;
+    if (cfg) s->cfg = *cfg;
+    if (s->cfg.slots == 0) s->cfg.slots = 2;
+    if (s->cfg.max_batch_sources == 0) s->cfg.max_batch_sources = 16384;
+    if (s->cfg.max_batch_paths == 0) s->cfg.max_batch_paths = 1ll << 27;
+    if (s->cfg.slots < 1 || s->cfg.slots > 8 || s->cfg.max_batch_sources < 1 ||
+        s->cfg.max_batch_paths < 1)
+      return set_error(LP_ERR_INVALID_ARGUMENT, "server config out of range");
+    LP_HIP(hipSetDevice(g->device));
+    // path bounds, once, in original id order
+    const int64_t n = g->n;
+    s->paths.assign((size_t)n, 0);
+    if (n > 0) {
+      DevBuf tmp;
+      LP_TRY(tmp.ensure((size_t)n * 8));
+      hipLaunchKernelGGL(path_bound_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, nullptr,
+                         g->off, g->adj, g->deg, g->rank, n, tmp.as<unsigned long long>());
+      LP_HIP(hipGetLastError());
+      LP_HIP(hipMemcpy(s->paths.data(), tmp.p, (size_t)n * 8, hipMemcpyDeviceToHost));
+      tmp.release();
+    }
+    for (int i = 0; i < s->cfg.slots; i++) {
+      auto sl = std::make_unique<lp_server::Slot>();
+      LP_HIP(hipStreamCreateWithFlags(&sl->st, hipStreamNonBlocking));
+      s->slots.push_back(std::move(sl));
+    }
+    for (auto& sl : s->slots) {
+      lp_server::Slot* p = sl.get();
+      lp_server* sp = s.get();
+      sl->th = std::thread([sp, p] { sp->worker(p); });
+    }
+    *out = s.release();
+    return LP_OK;
+  } catch (const std::bad_alloc&) {
+    return set_error(LP_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (...) {
+    return set_error(LP_ERR_DEVICE, "server start failed");
+  }
+}
+
+lp_status lp_server_destroy(lp_server* s) {
+  clear_error();
+  if (!s) return set_error(LP_ERR_INVALID_ARGUMENT, "server is NULL");
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  for (auto& sl : s->slots)
+    if (sl->th.joinable()) sl->th.join();
+  (void)hipSetDevice(s->g->device);
+  for (auto& sl : s->slots) {
+    release_workspace(sl->ws);
+    if (sl->st) (void)hipStreamDestroy(sl->st);
+  }
+  delete s;
+  return LP_OK;
+}
+
+lp_status lp_server_submit(lp_server* s, const int32_t* sources, int64_t n_sources, lp_measure m,
+                           int64_t hub_limit, int32_t k_q, float score_threshold, int32_t* out_c,
+                           float* out_score, int32_t* out_count, uint64_t* ticket) {
+  clear_error();
+  if (!s || !ticket) return set_error(LP_ERR_INVALID_ARGUMENT, "server or ticket is NULL");
+  if ((int)m < LP_CN || (int)m > LP_RA) return set_error(LP_ERR_INVALID_ARGUMENT, "measure out of range");
+  if (hub_limit < 0) return set_error(LP_ERR_INVALID_ARGUMENT, "hub_limit must be >= 0");
+  if (!std::isfinite(score_threshold) || score_threshold < 0.0f)
+    return set_error(LP_ERR_INVALID_ARGUMENT, "score_threshold must be finite and >= 0");
+  if (k_q <= 0) return set_error(LP_ERR_INVALID_ARGUMENT, "k_q must be > 0");
+  if (n_sources <= 0 || n_sources > INT32_MAX)
+    return set_error(LP_ERR_INVALID_ARGUMENT, "n_sources must be in [1, 2^31 - 1]");
+  if ((uint64_t)n_sources * (uint64_t)k_q >= (1ull << 32))
+    return set_error(LP_ERR_INVALID_ARGUMENT, "n_sources * k_q too large");
+  if (!sources || !out_c || !out_score || !out_count)
+    return set_error(LP_ERR_INVALID_ARGUMENT, "array pointer is NULL");
+  try {
+    auto r = std::make_unique<Request>();
+    r->sources.assign(sources, sources + n_sources);
+    uint64_t paths = 0;
+    for (int32_t v : r->sources) {
+      if (v < 0 || (int64_t)v >= s->g->n)
+        return set_error(LP_ERR_INVALID_ARGUMENT, "source %d outside [0, n)", (int)v);
+      paths += s->paths[(size_t)v];
+    }
+    r->paths = paths;
+    r->m = (int)m;
+    r->L = hub_limit;
+    r->kq = k_q;
+    r->s_th = score_threshold;
+    r->out_c = out_c;
+    r->out_s = out_score;
+    r->out_n = out_count;
+    r->t_submit = Clock::now();
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      if (s->stop) return set_error(LP_ERR_INVALID_ARGUMENT, "server is stopping");
+      r->id = s->next_id++;
+      *ticket = r->id;
+      s->queue.push_back(r.get());
+      s->reqs.emplace(r->id, std::move(r));
+    }
+    s->cv_work.notify_one();
+    return LP_OK;
+  } catch (const std::bad_alloc&) {
+    return set_error(LP_ERR_OUT_OF_MEMORY, "host allocation failed");
+  }
+}
+
+lp_status lp_server_wait(lp_server* s, uint64_t ticket, int64_t timeout_ms, lp_request_info* info) {
+  clear_error();
+  if (!s) return set_error(LP_ERR_INVALID_ARGUMENT, "server is NULL");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return set_error(LP_ERR_INVALID_ARGUMENT, "unknown ticket %llu",
+                                            (unsigned long long)ticket);
+  Request* r = it->second.get();
+  auto ready = [&] { return r->done; };
+  if (timeout_ms < 0) {
+    s->cv_done.wait(lk, ready);
+  } else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready)) {
+    return set_error(LP_ERR_BUSY, "request %llu still running", (unsigned long long)ticket);
+  }
+  const lp_request_info ri = r->info;
+  s->reqs.erase(it);
+  if (info) *info = ri;
+  if (ri.status != LP_OK) return set_error(ri.status, "the batch serving request %llu failed",
+                                           (unsigned long long)ticket);
+  return LP_OK;
+}
+
+}  // extern "C"

@@ -369,3 +369,62 @@ def test_full_size_rmat22_query(lp, rmat22, m):
     for i in range(src.shape[0]):
         assert_same_query((c[i][: cnt[i]], s[i][: cnt[i]]), refq[i], m,
                           f"R-MAT-22 query {m} src={src[i]}")
+
+
+def test_server_mix_equals_alone(lp, config1):
+    """Serving loop: requests of uneven size and two kinds, submitted together
+    and batched by the server across three slots, each get exactly what
+    lp_query returns for that request alone (and what the oracle returns)."""
+    gr, _ = config1
+    rng = np.random.default_rng(11)
+    deg = gr.degrees()
+    nz = np.nonzero(deg > 0)[0]
+    kinds = [("JC", 256, 10), ("AA", None, 5)]
+    reqs = []
+    for i in range(40):
+        size = int(np.exp(rng.uniform(0, np.log(400))))
+        p = deg[nz] / deg[nz].sum()  # degree-biased sources, repeats allowed
+        reqs.append((rng.choice(nz, size=size, p=p).astype(np.int32), kinds[i % 2]))
+    say(f"[gpu] server mix of {len(reqs)} requests")
+    with lp.Graph(gr.offsets, gr.indices) as g:
+        with lp.Server(g, slots=3, max_batch_sources=300) as srv:
+            tickets = [srv.submit(src, m, L, kq) for src, (m, L, kq) in reqs]
+            results = [srv.wait(t) for t in tickets]
+        batches = {}
+        for (out, rec) in results:
+            assert rec["status"] == 0
+            batches.setdefault(rec["batch"], rec["batch_requests"])
+            assert rec["total_ms"] >= rec["run_ms"] >= 0
+        assert max(batches.values()) > 1, "no request was batched with another"
+        assert sum(batches.values()) == len(reqs)
+        for (src, (m, L, kq)), (out, rec) in zip(reqs, results):
+            c, s, cnt = lp.query(g, src, m, L, kq)
+            assert np.array_equal(out[2], to_np(cnt))
+            for i in range(src.shape[0]):
+                n = out[2][i]
+                assert np.array_equal(out[0][i][:n], to_np(c)[i][:n])
+                assert np.array_equal(out[1][i][:n], to_np(s)[i][:n])
+        for (src, (m, L, kq)), (out, rec) in list(zip(reqs, results))[:6]:
+            ref = oracle.query(gr, L, m, src, kq)
+            for i in range(src.shape[0]):
+                assert_same_query((out[0][i][: out[2][i]], out[1][i][: out[2][i]]), ref[i], m,
+                                  f"server {m} src={src[i]}")
+
+
+def test_server_invalid_requests(lp, config1):
+    gr, _ = config1
+    say("[gpu] server invalid requests")
+    with lp.Graph(gr.offsets, gr.indices) as g:
+        with lp.Server(g) as srv:
+            for bad in (lambda: srv.submit([gr.n], "JC", 256, 10),
+                        lambda: srv.submit([-1], "JC", 256, 10),
+                        lambda: srv.submit([0], "JC", 256, 0),
+                        lambda: srv.submit([0], "JC", -1, 10),
+                        lambda: srv.submit([], "JC", 256, 10)):
+                with pytest.raises(lp.LpError):
+                    bad()
+            t = srv.submit([0, 1, 2], "CN", 256, 3)
+            out, rec = srv.wait(t)
+            assert rec["status"] == 0
+            with pytest.raises(lp.LpError):
+                srv.wait(t)
