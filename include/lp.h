@@ -185,9 +185,10 @@ lp_status lp_last_stats(const lp_graph *g, lp_stats *out);
  * Requests queue until a slot is free; a free slot takes the oldest request
  * and every other queued request with the same measure, hub limit, k_q and
  * threshold, up to max_batch_sources sources and max_batch_paths two-hop
- * paths, and runs them as one query.  The path count of a source s is
- * sum over b in Gamma(s) of d_b, an upper bound of its wedges under any hub
- * limit; it bounds the batch's candidate buffer.  A request above either cap
+ * paths, and runs them as one query.  The path count of a source s under hub
+ * limit L is
+ * min(sum over b in Gamma(s) of d_b, d_s * L), an upper bound of its wedges;
+ * it bounds the batch's candidate buffer.  A request above either cap
  * runs alone.  Each request's result equals lp_query on that request alone.
  * Requests that arrive while batches run join the next batch of the slot that
  * frees first, so work of several requests overlaps on the device.

@@ -1320,18 +1320,21 @@ static lp_status launch_spa(lp_graph* g, Workspace& w, const GView& gv, const Em
   if (nitems == 0) return LP_OK;
   AccConfig cfg = acc_config(g);
   const size_t n = (size_t)g->n;
-  // pool: cfg.spa_wgs slabs of 8n accumulator bytes, then as many key lists of 4n
-  const size_t need = (size_t)cfg.spa_wgs * n * 12;
-  if (w.global_tab.cap < need || w.global_slabs != cfg.spa_wgs) {
+  // pool: one slab of 8n accumulator bytes per workgroup, then as many key
+  // lists of 4n; it grows to the launch's workgroup count (at most
+  // cfg.spa_wgs) and never shrinks
+  const unsigned slabs = (unsigned)std::min<uint64_t>(cfg.spa_wgs, nitems);
+  if (w.global_slabs < slabs) {
     w.global_tab.release();
-    LP_TRY(w.global_tab.ensure(need));
-    LP_HIP(hipMemsetAsync(w.global_tab.p, 0, (size_t)cfg.spa_wgs * n * 8, st));
-    w.global_slabs = cfg.spa_wgs;
+    w.global_slabs = 0;
+    LP_TRY(w.global_tab.ensure((size_t)slabs * n * 12));
+    LP_HIP(hipMemsetAsync(w.global_tab.p, 0, (size_t)slabs * n * 8, st));
+    w.global_slabs = slabs;
   }
   // the accumulators are left zeroed by every workgroup; the key lists need no init
   char* base = w.global_tab.as<char>();
-  uint32_t* spa_keys = reinterpret_cast<uint32_t*>(base + (size_t)cfg.spa_wgs * n * 8);
-  const unsigned wgs = (unsigned)std::min<uint64_t>(cfg.spa_wgs, nitems);
+  uint32_t* spa_keys = reinterpret_cast<uint32_t*>(base + (size_t)w.global_slabs * n * 8);
+  const unsigned wgs = slabs;
   hipLaunchKernelGGL((acc_spa_kernel<kW, kQuery>), dim3(wgs), dim3(kSpaThreads), 0, st, gv, E, wl,
                      ov, base, spa_keys);
   LP_HIP(hipGetLastError());

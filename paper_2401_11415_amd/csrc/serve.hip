@@ -71,6 +71,7 @@ struct lp_server {
   lp_graph* g = nullptr;
   lp_server_config cfg{};
   std::vector<unsigned long long> paths;  // per original id
+  std::vector<uint32_t> degree;           // per original id
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<Request*> queue;
@@ -202,6 +203,11 @@ lp_status lp_server_create(lp_graph* g, const lp_server_config* cfg, lp_server**
       LP_HIP(hipGetLastError());
       LP_HIP(hipMemcpy(s->paths.data(), tmp.p, (size_t)n * 8, hipMemcpyDeviceToHost));
       tmp.release();
+      // degrees in original id order (the graph keeps them sorted by new id)
+      std::vector<uint32_t> rank((size_t)n);
+      LP_HIP(hipMemcpy(rank.data(), g->rank, (size_t)n * 4, hipMemcpyDeviceToHost));
+      s->degree.resize((size_t)n);
+      for (int64_t o = 0; o < n; o++) s->degree[(size_t)o] = g->host_deg[rank[(size_t)o]];
     }
     for (int i = 0; i < s->cfg.slots; i++) {
       auto sl = std::make_unique<lp_server::Slot>();
@@ -260,11 +266,15 @@ lp_status lp_server_submit(lp_server* s, const int32_t* sources, int64_t n_sourc
   try {
     auto r = std::make_unique<Request>();
     r->sources.assign(sources, sources + n_sources);
+    // every explored intermediate has degree <= L, so a source's wedges are
+    // also at most d_s * L
     uint64_t paths = 0;
     for (int32_t v : r->sources) {
       if (v < 0 || (int64_t)v >= s->g->n)
         return set_error(LP_ERR_INVALID_ARGUMENT, "source %d outside [0, n)", (int)v);
-      paths += s->paths[(size_t)v];
+      const unsigned long long by_limit =
+          hub_limit >= (int64_t)UINT32_MAX ? ~0ull : (unsigned long long)s->degree[(size_t)v] * (uint64_t)hub_limit;
+      paths += std::min(s->paths[(size_t)v], by_limit);
     }
     r->paths = paths;
     r->m = (int)m;
