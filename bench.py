@@ -121,6 +121,8 @@ def main():
     ap.add_argument("--qps", type=float, default=200.0, help="--serve: request arrival rate")
     ap.add_argument("--requests", type=int, default=600, help="--serve: requests in the stream")
     ap.add_argument("--slots", type=int, default=2, help="--serve: concurrent batches")
+    ap.add_argument("--sweep", action="store_true",
+                    help="hub-limit sweep instead: time and holdout precision per L")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -144,6 +146,9 @@ def main():
 
     if args.serve:
         serve(args, lp, synth, torch)
+        return
+    if args.sweep:
+        sweep(args, lp, synth, torch)
         return
 
     t0 = time.time()
@@ -262,6 +267,46 @@ def main():
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(obs, L, args.measure, k, args.cpu_seconds)
     print(json.dumps(res), flush=True)
+
+
+def sweep(args, lp, synth, torch):
+    """Hub-limit sweep (the paper's Section 4.4 experiment on a synthetic
+    stand-in): the benchmark graph, one measure, L in {2, 4, ..., 1024} and
+    IBase; per L the device time of lp_predict (median of 3 after a warm-up),
+    the wedges and candidates it handles, the speedup over IBase, and the
+    precision of the k predictions against the held-out edges."""
+    full = synth.rmat(args.scale, 16.0, 0.57, 0.19, 0.19, seed=1)
+    obs, held = synth.holdout(full, 0.1, seed=1)
+    k = int(held.shape[0])
+    del full
+    hu, hv = np.minimum(held[:, 0], held[:, 1]).astype(np.int64), np.maximum(held[:, 0], held[:, 1]).astype(np.int64)
+    held_keys = np.sort(hu * obs.n + hv)
+    torch.cuda.set_device(0)
+    g = lp.Graph(obs.offsets, obs.indices)
+    rows = []
+    for L in [2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, None]:
+        lp.predict(g, args.measure, L, k)
+        ms, st = [], None
+        for _ in range(3):
+            a, c, s = lp.predict(g, args.measure, L, k)
+            st = lp.last_stats(g)
+            ms.append(st["ms_total"])
+        a = a.cpu().numpy().astype(np.int64)
+        c = c.cpu().numpy().astype(np.int64)
+        keys = a * obs.n + c
+        hits = int(np.isin(keys, held_keys, assume_unique=False).sum())
+        n_cand = sum(b["candidates"] for b in st["launches"].values()) if st["retries"] == 0 else None
+        row = {"L": L if L is not None else "IBase", "ms": float(np.median(ms)), "wedges": st["wedges"],
+               "candidates": n_cand, "k_out": int(a.shape[0]), "hits": hits,
+               "precision": hits / max(int(a.shape[0]), 1)}
+        rows.append(row)
+        log(json.dumps(row))
+    g.close()
+    ib = rows[-1]["ms"]
+    for r in rows:
+        r["speedup_vs_ibase"] = ib / r["ms"]
+    print(json.dumps({"sweep": f"R-MAT scale {args.scale}, DLH {args.measure.upper()}, k={k}",
+                      "rows": rows}), flush=True)
 
 
 def serve(args, lp, synth, torch):
