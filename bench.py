@@ -24,24 +24,26 @@ import numpy as np  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 PAPER_DLH_EDGES_PER_S = 38.1e6  # sk-2005, 2x Xeon Gold 6226R (context only)
 
-# Accumulation kernel of each scheduling bucket (count tables: CN, JC, ...,
-# LHN; weighted tables: AA, RA), as rocprofv3 names them, for graphs with
-# fewer than 2^24 vertices (the batched small-source kernels).
+# Main-pass accumulation kernel of each scheduling bucket (count tables: CN,
+# JC, ..., LHN; weighted tables: AA, RA), as rocprofv3 names them, for graphs
+# with fewer than 2^24 vertices (the batched small-source kernels).  The
+# sampling pass runs the same code as separate instantiations (last template
+# argument true).
 BUCKET_KERNELS = {
-    False: {"tiny": "acc_batch_kernel<256, 48, 3072, false, 64>",
-            "small": "acc_batch_kernel<256, 8, 3072, false, 64>",
-            "mid1": "acc_batch_kernel<256, 2, 3072, false, 64>",
-            "mid2": "acc_lds_kernel<256, 256, 3072, false, false, 64>",
-            "mid3": "acc_lds_kernel<512, 512, 6144, false, false, 64>",
-            "large": "acc_lds_kernel<1024, 1024, 14336, false, false, 64>",
-            "global": "acc_spa_kernel<false, false>"},
-    True: {"tiny": "acc_batch_kernel<256, 48, 3072, true, 64>",
-           "small": "acc_batch_kernel<256, 8, 3072, true, 64>",
-           "mid1": "acc_batch_kernel<256, 2, 3072, true, 64>",
-           "mid2": "acc_lds_kernel<256, 256, 3072, true, false, 64>",
-           "mid3": "acc_lds_kernel<512, 512, 4608, true, false, 64>",
-           "large": "acc_lds_kernel<1024, 1024, 7680, true, false, 64>",
-           "global": "acc_spa_kernel<true, false>"},
+    False: {"tiny": "acc_batch_kernel<256, 48, 3072, false, 64, false>",
+            "small": "acc_batch_kernel<256, 8, 3072, false, 64, false>",
+            "mid1": "acc_batch_kernel<256, 2, 3072, false, 64, false>",
+            "mid2": "acc_lds_kernel<256, 256, 3072, false, false, 64, false>",
+            "mid3": "acc_lds_kernel<512, 512, 6144, false, false, 64, false>",
+            "large": "acc_lds_kernel<1024, 1024, 14336, false, false, 64, false>",
+            "global": "acc_spa_kernel<false, false, false>"},
+    True: {"tiny": "acc_batch_kernel<256, 48, 3072, true, 64, false>",
+           "small": "acc_batch_kernel<256, 8, 3072, true, 64, false>",
+           "mid1": "acc_batch_kernel<256, 2, 3072, true, 64, false>",
+           "mid2": "acc_lds_kernel<256, 256, 3072, true, false, 64, false>",
+           "mid3": "acc_lds_kernel<512, 512, 4608, true, false, 64, false>",
+           "large": "acc_lds_kernel<1024, 1024, 7680, true, false, 64, false>",
+           "global": "acc_spa_kernel<true, false, false>"},
 }
 KERNEL_SOURCES = ["paper_2401_11415_amd/csrc/predict.hip", "paper_2401_11415_amd/csrc/kernels.h",
                   "paper_2401_11415_amd/csrc/lp_common.h"]
@@ -194,7 +196,8 @@ def main():
     # |C_L| for the byte model: the kernels count distinct candidates; a
     # repeated pass would count some twice, then the digest call counts them
     if stats["retries"] == 0:
-        n_cand = sum(b["candidates"] for b in stats["launches"].values())
+        n_cand = sum(b["candidates"] for b in stats["launches"].values()) + \
+            sum(b["candidates"] for b in stats["sampled"].values())
     else:
         n_cand = lp.fingerprint(g, L)[0]
     deg = np.diff(obs.offsets)

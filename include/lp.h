@@ -152,9 +152,11 @@ typedef struct {
 lp_status lp_set_tuning(lp_graph *g, const lp_tuning *t);
 
 /* Work done by the accumulation launches of one scheduling bucket during a
- * call, summed over the call's launches of that bucket (a sampling pass and
- * the main pass, and any repeated pass).  Sources whose LDS table overflowed
- * are counted under the global bucket, which re-runs them. */
+ * call, summed over the call's launches of that bucket in one kind of pass
+ * (the main pass and any repeat of it; the sampling pass is kept apart).
+ * Sources whose LDS table overflowed are counted under the global bucket,
+ * which re-runs them.  Times are HIP events on the stream of each launch
+ * (sampling-pass launches run concurrently on internal streams). */
 typedef struct {
   uint64_t launches;    /* kernel launches */
   uint64_t sources;     /* sources completed */
@@ -162,7 +164,7 @@ typedef struct {
   uint64_t arcs;        /* explored arcs a -> b that lead to at least one wedge */
   uint64_t wedges;      /* two-hop paths a - b - c accumulated */
   uint64_t candidates;  /* distinct non-adjacent pairs found (before any threshold) */
-  double ms;            /* device time of the launches (HIP events on the call's stream) */
+  double ms;            /* device time of the launches */
 } lp_bucket_stats;
 
 /* Statistics of the last lp_predict / lp_fingerprint on g (host pointer). */
@@ -173,7 +175,9 @@ typedef struct {
   uint64_t appended;          /* candidates written to the selection buffer */
   uint64_t retries;           /* extra passes after a threshold estimate missed */
   double ms_plan, ms_accumulate, ms_select, ms_total; /* device time per phase */
-  lp_bucket_stats bucket[8];  /* per bucket: tiny, small, mid1, mid2, mid3, large, global */
+  lp_bucket_stats bucket[8];  /* per bucket (tiny, small, mid1, mid2, mid3, large, global):
+                                 the main pass, or the only pass without sampling */
+  lp_bucket_stats sampled[8]; /* the sampling pass that estimates the top-k threshold */
 } lp_stats;
 lp_status lp_last_stats(const lp_graph *g, lp_stats *out);
 

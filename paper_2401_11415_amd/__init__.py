@@ -57,7 +57,8 @@ class _Stats(ctypes.Structure):
                 ("bucket_sources", ctypes.c_uint64 * 8), ("appended", ctypes.c_uint64),
                 ("retries", ctypes.c_uint64), ("ms_plan", ctypes.c_double),
                 ("ms_accumulate", ctypes.c_double), ("ms_select", ctypes.c_double),
-                ("ms_total", ctypes.c_double), ("bucket", _BucketStats * 8)]
+                ("ms_total", ctypes.c_double), ("bucket", _BucketStats * 8),
+                ("sampled", _BucketStats * 8)]
 
 
 class _ServerConfig(ctypes.Structure):
@@ -255,13 +256,15 @@ def set_tuning(g: Graph, lds_wedge_cap: int = 0, global_slots: int = 0, sample_b
 def last_stats(g: Graph) -> dict:
     s = _Stats()
     _check(load().lp_last_stats(g.handle, ctypes.byref(s)))
-    launches = {}
-    for name, b in zip(BUCKETS, s.bucket):
+    launches, sampled = {}, {}
+    for name, b, x in zip(BUCKETS, s.bucket, s.sampled):
         launches[name] = {f: getattr(b, f) for f, _ in _BucketStats._fields_}
+        sampled[name] = {f: getattr(x, f) for f, _ in _BucketStats._fields_}
     return {"wedges": s.wedges, "sources": s.sources,
             "buckets": dict(zip(BUCKETS, list(s.bucket_sources))), "appended": s.appended,
             "retries": s.retries, "ms_plan": s.ms_plan, "ms_accumulate": s.ms_accumulate,
-            "ms_select": s.ms_select, "ms_total": s.ms_total, "launches": launches}
+            "ms_select": s.ms_select, "ms_total": s.ms_total, "launches": launches,
+            "sampled": sampled}
 
 
 class Server:

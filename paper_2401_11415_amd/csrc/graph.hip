@@ -430,6 +430,14 @@ void release_workspace(Workspace& w) {
                    &w.q_cnt, &w.q_wedges, &w.q_rows, &w.q_out};
   for (auto b : all) b->release();
   w.host_stats.release();
+  for (int i = 0; i < Workspace::kSide; i++) {
+    if (w.side[i]) (void)hipStreamDestroy(w.side[i]);
+    if (w.join[i]) (void)hipEventDestroy(w.join[i]);
+    w.side[i] = nullptr;
+    w.join[i] = nullptr;
+  }
+  if (w.fork) (void)hipEventDestroy(w.fork);
+  w.fork = nullptr;
 }
 
 void destroy_graph(lp_graph* g) {

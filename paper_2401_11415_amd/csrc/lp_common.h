@@ -80,6 +80,12 @@ struct Workspace {
   // query
   DevBuf q_src, q_cnt, q_wedges, q_rows, q_out;
   HostBuf host_stats;
+  // side streams for the concurrent launches of a sampling phase (default
+  // priority), forked from and joined back to the caller's stream
+  static constexpr int kSide = 3;
+  hipStream_t side[kSide] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kSide] = {};
 };
 
 }  // namespace lp

@@ -428,7 +428,9 @@ struct LdsTab {
   uint32_t so_c[NW][64];
 };
 
-template <int WGS, int G, int SLOTS, bool kW, bool kQuery, int STAGE>
+// kSampled: the same kernel instantiated separately for the sampling pass,
+// so that profiles and per-launch statistics keep the two passes apart
+template <int WGS, int G, int SLOTS, bool kW, bool kQuery, int STAGE, bool kSampled>
 __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, WorkList wl) {
   static_assert(G % 64 == 0 && (G == 64 || G == WGS), "groups are whole waves");
   static_assert(STAGE >= 64, "a stage holds at least one wave of entries");
@@ -634,7 +636,7 @@ __device__ inline int batch_search(const uint32_t* off, uint32_t q) {
   return lo;
 }
 
-template <int WGS, int B, int SLOTS, bool kW, int STAGE>
+template <int WGS, int B, int SLOTS, bool kW, int STAGE, bool kSampled>
 __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkList wl) {
   static_assert(B <= 64 && B >= 1, "batch fits in one wave");
   constexpr int NW = WGS / 64;
@@ -853,7 +855,7 @@ struct SpaItem {
 constexpr int kSpaThreads = 1024;
 constexpr int kSpaStage = 128;
 
-template <bool kW, bool kQuery>
+template <bool kW, bool kQuery, bool kSampled>
 __global__ __launch_bounds__(kSpaThreads) void acc_spa_kernel(GView g, Emit E, WorkList wl,
                                                               SpaItem ov, char* spa_acc,
                                                               uint32_t* spa_keys) {
@@ -1258,7 +1260,7 @@ static AccConfig acc_config(const lp_graph* g) {
 }
 
 // Launch the accumulation of one work list in the given bucket.
-template <bool kW, bool kQuery>
+template <bool kW, bool kQuery, bool kSampled>
 static lp_status launch_bucket(lp_graph* g, int bucket, const GView& gv, const Emit& E,
                                WorkList wl, uint64_t nitems, hipStream_t st) {
   if (nitems == 0) return LP_OK;
@@ -1267,15 +1269,15 @@ static lp_status launch_bucket(lp_graph* g, int bucket, const GView& gv, const E
     // batches: Tiny 48 sources (<= 1536 wedges), Small 8 (<= 2048), Mid1 2 (<= 2048)
     switch (bucket) {
       case kBucketTiny:
-        hipLaunchKernelGGL((acc_batch_kernel<256, 48, 3072, kW, 64>),
+        hipLaunchKernelGGL((acc_batch_kernel<256, 48, 3072, kW, 64, kSampled>),
                            dim3(grid_for((nitems + 47) / 48, 1, cus * 8)), dim3(256), 0, st, gv, E, wl);
         break;
       case kBucketSmall:
-        hipLaunchKernelGGL((acc_batch_kernel<256, 8, 3072, kW, 64>),
+        hipLaunchKernelGGL((acc_batch_kernel<256, 8, 3072, kW, 64, kSampled>),
                            dim3(grid_for((nitems + 7) / 8, 1, cus * 8)), dim3(256), 0, st, gv, E, wl);
         break;
       default:
-        hipLaunchKernelGGL((acc_batch_kernel<256, 2, 3072, kW, 64>),
+        hipLaunchKernelGGL((acc_batch_kernel<256, 2, 3072, kW, 64, kSampled>),
                            dim3(grid_for((nitems + 1) / 2, 1, cus * 8)), dim3(256), 0, st, gv, E, wl);
         break;
     }
@@ -1284,27 +1286,27 @@ static lp_status launch_bucket(lp_graph* g, int bucket, const GView& gv, const E
   }
   switch (bucket) {
     case kBucketTiny:
-      hipLaunchKernelGGL((acc_lds_kernel<256, 64, 48, kW, kQuery, 128>),
+      hipLaunchKernelGGL((acc_lds_kernel<256, 64, 48, kW, kQuery, 128, kSampled>),
                          dim3(grid_for(nitems, 4, cus * 16)), dim3(256), 0, st, gv, E, wl);
       break;
     case kBucketSmall:
-      hipLaunchKernelGGL((acc_lds_kernel<256, 64, 384, kW, kQuery, 128>),
+      hipLaunchKernelGGL((acc_lds_kernel<256, 64, 384, kW, kQuery, 128, kSampled>),
                          dim3(grid_for(nitems, 4, cus * 16)), dim3(256), 0, st, gv, E, wl);
       break;
     case kBucketMid1:
-      hipLaunchKernelGGL((acc_lds_kernel<128, 128, 1536, kW, kQuery, 128>),
+      hipLaunchKernelGGL((acc_lds_kernel<128, 128, 1536, kW, kQuery, 128, kSampled>),
                          dim3(grid_for(nitems, 1, cus * 16)), dim3(128), 0, st, gv, E, wl);
       break;
     case kBucketMid2:
-      hipLaunchKernelGGL((acc_lds_kernel<256, 256, 3072, kW, kQuery, 64>),
+      hipLaunchKernelGGL((acc_lds_kernel<256, 256, 3072, kW, kQuery, 64, kSampled>),
                          dim3(grid_for(nitems, 1, cus * 8)), dim3(256), 0, st, gv, E, wl);
       break;
     case kBucketMid3:
-      hipLaunchKernelGGL((acc_lds_kernel<512, 512, kW ? 4608 : 6144, kW, kQuery, 64>),
+      hipLaunchKernelGGL((acc_lds_kernel<512, 512, kW ? 4608 : 6144, kW, kQuery, 64, kSampled>),
                          dim3(grid_for(nitems, 1, cus * 4)), dim3(512), 0, st, gv, E, wl);
       break;
     case kBucketLarge:
-      hipLaunchKernelGGL((acc_lds_kernel<1024, 1024, kW ? 7680 : 14336, kW, kQuery, 64>),
+      hipLaunchKernelGGL((acc_lds_kernel<1024, 1024, kW ? 7680 : 14336, kW, kQuery, 64, kSampled>),
                          dim3(grid_for(nitems, 1, cus * 2)), dim3(1024), 0, st, gv, E, wl);
       break;
     default:
@@ -1314,7 +1316,7 @@ static lp_status launch_bucket(lp_graph* g, int bucket, const GView& gv, const E
   return LP_OK;
 }
 
-template <bool kW, bool kQuery>
+template <bool kW, bool kQuery, bool kSampled>
 static lp_status launch_spa(lp_graph* g, Workspace& w, const GView& gv, const Emit& E, WorkList wl,
                             SpaItem ov, uint64_t nitems, hipStream_t st) {
   if (nitems == 0) return LP_OK;
@@ -1335,7 +1337,7 @@ static lp_status launch_spa(lp_graph* g, Workspace& w, const GView& gv, const Em
   char* base = w.global_tab.as<char>();
   uint32_t* spa_keys = reinterpret_cast<uint32_t*>(base + (size_t)w.global_slabs * n * 8);
   const unsigned wgs = slabs;
-  hipLaunchKernelGGL((acc_spa_kernel<kW, kQuery>), dim3(wgs), dim3(kSpaThreads), 0, st, gv, E, wl,
+  hipLaunchKernelGGL((acc_spa_kernel<kW, kQuery, kSampled>), dim3(wgs), dim3(kSpaThreads), 0, st, gv, E, wl,
                      ov, base, spa_keys);
   LP_HIP(hipGetLastError());
   return LP_OK;
@@ -1344,8 +1346,9 @@ static lp_status launch_spa(lp_graph* g, Workspace& w, const GView& gv, const Em
 // HIP events around every accumulation launch of a call, on the call's
 // stream; per-bucket device time and launch counts go to the call's stats.
 struct LaunchClock {
-  hipEvent_t ev[2 * (kBuckets + 1)] = {};
-  bool used[kBuckets + 1] = {};
+  // slots [0, kBuckets]: main pass; [kBuckets + 1, 2 kBuckets + 1]: sampling pass
+  hipEvent_t ev[4 * (kBuckets + 1)] = {};
+  bool used[2 * (kBuckets + 1)] = {};
   lp_stats* stats = nullptr;
   explicit LaunchClock(lp_stats* s) : stats(s) {
     for (auto& e : ev) (void)hipEventCreate(&e);
@@ -1366,11 +1369,13 @@ struct LaunchClock {
   }
   // after the stream has passed every stop event
   void collect() {
-    for (int s = 0; s <= kBuckets; s++) {
+    for (int s = 0; s < 2 * (kBuckets + 1); s++) {
       if (!used[s]) continue;
       float t = 0;
       if (hipEventElapsedTime(&t, ev[2 * s], ev[2 * s + 1]) != hipSuccess) (void)hipGetLastError();
-      lp_bucket_stats& b = stats->bucket[s < kBuckets ? s : kBucketHuge];
+      const int r = s % (kBuckets + 1);
+      lp_bucket_stats* arr = s > kBuckets ? stats->sampled : stats->bucket;
+      lp_bucket_stats& b = arr[r < kBuckets ? r : kBucketHuge];
       b.ms += t;
       b.launches += 1;
       used[s] = false;
@@ -1378,21 +1383,27 @@ struct LaunchClock {
   }
 };
 
-// Work counters of the launches of one call: 8 uint64 per bucket.
+// Work counters of the launches of one call: 8 uint64 per bucket, main pass
+// first, then the sampling pass.
 static unsigned long long* work_counters(Workspace& w) {
   return reinterpret_cast<unsigned long long*>(w.counters.as<char>() + 1024);
 }
+constexpr int kSampledWork = 8 * 8;  // offset of the sampling pass's counters
 
 static lp_status collect_work(Workspace& w, lp_stats* S, hipStream_t st) {
-  unsigned long long h[kBuckets * 8];
+  unsigned long long h[2 * kSampledWork];
   LP_HIP(hipMemcpyAsync(h, work_counters(w), sizeof(h), hipMemcpyDeviceToHost, st));
   LP_HIP(hipStreamSynchronize(st));
-  for (int b = 0; b < kBuckets; b++) {
-    S->bucket[b].sources = h[b * 8 + 0];
-    S->bucket[b].first_order = h[b * 8 + 1];
-    S->bucket[b].arcs = h[b * 8 + 2];
-    S->bucket[b].wedges = h[b * 8 + 3];
-    S->bucket[b].candidates = h[b * 8 + 4];
+  for (int p = 0; p < 2; p++) {
+    lp_bucket_stats* arr = p ? S->sampled : S->bucket;
+    const unsigned long long* x = h + p * kSampledWork;
+    for (int b = 0; b < kBuckets; b++) {
+      arr[b].sources = x[b * 8 + 0];
+      arr[b].first_order = x[b * 8 + 1];
+      arr[b].arcs = x[b * 8 + 2];
+      arr[b].wedges = x[b * 8 + 3];
+      arr[b].candidates = x[b * 8 + 4];
+    }
   }
   return LP_OK;
 }
@@ -1404,6 +1415,23 @@ static lp_status run_phase(lp_graph* g, Workspace& w, const GView& gv, const Emi
                            uint32_t stride, int phase, uint32_t* ovf_host_count, LaunchClock* clk,
                            hipStream_t st) {
   unsigned long long* work = work_counters(w);
+  // The sampling phase launches every bucket with a few sources each: those
+  // launches are latency bound and independent, so they run concurrently on
+  // side streams forked from and joined back to st.  Full phases run in
+  // order on st (concurrent full launches compete for LDS and lose).
+  const bool fan = phase == 1;
+  if (fan) {
+    if (!w.fork) {
+      LP_HIP(hipEventCreateWithFlags(&w.fork, hipEventDisableTiming));
+      for (int j = 0; j < Workspace::kSide; j++) {
+        LP_HIP(hipStreamCreateWithFlags(&w.side[j], hipStreamNonBlocking));
+        LP_HIP(hipEventCreateWithFlags(&w.join[j], hipEventDisableTiming));
+      }
+    }
+    LP_HIP(hipEventRecord(w.fork, st));
+    for (int j = 0; j < Workspace::kSide; j++) LP_HIP(hipStreamWaitEvent(w.side[j], w.fork, 0));
+  }
+  int turn = 0;
   // largest buckets first: their long-running workgroups start early
   for (int b = kBuckets - 1; b >= 0; b--) {
     WorkList wl{lists + (uint64_t)b * list_stride, counts_host[b], stride, phase};
@@ -1415,14 +1443,33 @@ static lp_status run_phase(lp_graph* g, Workspace& w, const GView& gv, const Emi
     }
     if (items == 0) continue;
     Emit E = E0;
-    E.work = work + b * 8;
-    if (clk) LP_TRY(clk->start(b, st));
-    if (b == kBucketHuge) {
-      LP_TRY((launch_spa<kW, kQuery>(g, w, gv, E, wl, SpaItem{nullptr, nullptr, 0, 0}, items, st)));
-    } else {
-      LP_TRY((launch_bucket<kW, kQuery>(g, b, gv, E, wl, items, st)));
+    E.work = work + (fan ? kSampledWork : 0) + b * 8;
+    const int k = fan ? turn++ % (Workspace::kSide + 1) : 0;
+    hipStream_t sb = k == 0 ? st : w.side[k - 1];
+    const int slot = fan ? kBuckets + 1 + b : b;
+    if (clk) LP_TRY(clk->start(slot, sb));
+    if constexpr (!kQuery) {
+      if (fan) {
+        if (b == kBucketHuge)
+          LP_TRY((launch_spa<kW, kQuery, true>(g, w, gv, E, wl, SpaItem{nullptr, nullptr, 0, 0}, items, sb)));
+        else
+          LP_TRY((launch_bucket<kW, kQuery, true>(g, b, gv, E, wl, items, sb)));
+        if (clk) LP_TRY(clk->stop(slot, sb));
+        continue;
+      }
     }
-    if (clk) LP_TRY(clk->stop(b, st));
+    if (b == kBucketHuge) {
+      LP_TRY((launch_spa<kW, kQuery, false>(g, w, gv, E, wl, SpaItem{nullptr, nullptr, 0, 0}, items, sb)));
+    } else {
+      LP_TRY((launch_bucket<kW, kQuery, false>(g, b, gv, E, wl, items, sb)));
+    }
+    if (clk) LP_TRY(clk->stop(slot, sb));
+  }
+  if (fan) {
+    for (int j = 0; j < Workspace::kSide; j++) {
+      LP_HIP(hipEventRecord(w.join[j], w.side[j]));
+      LP_HIP(hipStreamWaitEvent(st, w.join[j], 0));
+    }
   }
   // overflow records written by this phase's LDS kernels
   uint32_t ovf_total = 0;
@@ -1435,7 +1482,7 @@ static lp_status run_phase(lp_graph* g, Workspace& w, const GView& gv, const Emi
     Emit E = E0;
     E.work = work + kBucketHuge * 8;
     if (clk) LP_TRY(clk->start(kBuckets, st));
-    LP_TRY((launch_spa<kW, kQuery>(g, w, gv, E, none, ov, ovf_total - *ovf_host_count, st)));
+    LP_TRY((launch_spa<kW, kQuery, false>(g, w, gv, E, none, ov, ovf_total - *ovf_host_count, st)));
     if (clk) LP_TRY(clk->stop(kBuckets, st));
     *ovf_host_count = ovf_total;
     LP_HIP(hipStreamSynchronize(st));
@@ -1480,7 +1527,10 @@ static lp_status run_select(lp_graph* g, const uint32_t* cs, const uint32_t* ca,
                      oa, oc);
   LP_HIP(hipGetLastError());
   int ping = 0;
-  for (int step = 0; step < 9; step++) {
+  // a threshold needs only the score digits: (score of the k-th key, 0, 0) is
+  // a lower bound of the k-th key
+  const int nsteps = tau_out ? 3 : 9;
+  for (int step = 0; step < nsteps; step++) {
     uint32_t* nxt_s = w.tmp_s[ping].as<uint32_t>();
     uint32_t* nxt_a = w.tmp_a[ping].as<uint32_t>();
     uint32_t* nxt_c = w.tmp_c[ping].as<uint32_t>();
@@ -1489,7 +1539,7 @@ static lp_status run_select(lp_graph* g, const uint32_t* cs, const uint32_t* ca,
     hipLaunchKernelGGL(sel_pick_kernel, dim3(1), dim3(64), 0, st, sst, step, hist);
     hipLaunchKernelGGL(sel_partition_kernel, dim3(grid), dim3(256), 0, st, in_s, in_a, in_c, sst,
                        step, nxt_s, nxt_a, nxt_c, os, oa, oc);
-    hipLaunchKernelGGL(sel_advance_kernel, dim3(1), dim3(1), 0, st, sst, step == 8 ? 1 : 0);
+    hipLaunchKernelGGL(sel_advance_kernel, dim3(1), dim3(1), 0, st, sst, step == nsteps - 1 ? 1 : 0);
     LP_HIP(hipGetLastError());
     in_s = nxt_s;
     in_a = nxt_a;

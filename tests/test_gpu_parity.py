@@ -168,7 +168,7 @@ def test_global_path_and_partitions(lp, config1):
 
 def _launch_sums(st):
     tot = {f: 0 for f in ("launches", "sources", "wedges", "candidates")}
-    for b in st["launches"].values():
+    for b in list(st["launches"].values()) + list(st["sampled"].values()):
         for f in tot:
             tot[f] += b[f]
         assert (b["ms"] > 0) == (b["launches"] > 0)
