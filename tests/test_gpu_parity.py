@@ -428,3 +428,68 @@ def test_server_invalid_requests(lp, config1):
             assert rec["status"] == 0
             with pytest.raises(lp.LpError):
                 srv.wait(t)
+
+
+@pytest.fixture(scope="module")
+def chung_lu_8m():
+    """The AA / RA workload: Chung-Lu, 8M vertices, exponent 2.1, weights capped
+    at 2e5, seed 1, 10% holdout; k = 10% of the edges."""
+    full = synth.chung_lu_8m(seed=1)
+    obs, held = synth.holdout(full, 0.1, seed=1)
+    return obs, int(held.shape[0])
+
+
+def test_full_size_chung_lu_8m_digest(lp, chung_lu_8m):
+    gr, _ = chung_lu_8m
+    say(f"[gpu] Chung-Lu 8M fingerprint L=32 n={gr.n}")
+    with lp.Graph(gr.offsets, gr.indices) as g:
+        assert lp.fingerprint(g, 32) == oracle.fingerprint(gr, 32)
+
+
+def test_full_size_chung_lu_8m_aa_topk(lp, chung_lu_8m):
+    """DLH Adamic-Adar at L = 32 (the paper's choice for AA), k = |held out|:
+    the top-k meets the acceptance rule against the oracle's FP64 list."""
+    gr, k = chung_lu_8m
+    say(f"[gpu] Chung-Lu 8M predict AA L=32 k={k}")
+    with lp.Graph(gr.offsets, gr.indices) as g:
+        got = run_predict(lp, g, "AA", 32, k)
+    ref = oracle.predict(gr, 32, "AA", k)
+    assert_same_list(got, ref, "AA", "Chung-Lu 8M/AA/L=32")
+
+
+@pytest.mark.parametrize("m", ["RA", "AA", "JC"])
+def test_full_size_chung_lu_8m_query(lp, chung_lu_8m, m):
+    """Ranked lists at L = 256 for seeded sources including the 16 of highest
+    degree, whose wedges exceed the LDS tables."""
+    gr, _ = chung_lu_8m
+    src = synth.sample_sources(gr, 256, seed=5, top=16)
+    say(f"[gpu] Chung-Lu 8M query {m} L=256 ns={src.shape[0]}")
+    with lp.Graph(gr.offsets, gr.indices) as g:
+        c, s, cnt = lp.query(g, src, m, 256, 10)
+        c, s, cnt = to_np(c), to_np(s), to_np(cnt)
+    ref = oracle.query(gr, 256, m, src, 10)
+    for i in range(src.shape[0]):
+        assert_same_query((c[i][: cnt[i]], s[i][: cnt[i]]), ref[i], m,
+                          f"Chung-Lu 8M query {m} src={src[i]}")
+
+
+def test_full_size_rmat24_server(lp):
+    """The serving graph (R-MAT scale 24, full): requests of degree-biased
+    sources through the server, DLH AA L = 32 top-10, against the oracle."""
+    gr = synth.rmat24(seed=1)
+    say(f"[gpu] R-MAT-24 server n={gr.n} m={gr.m}")
+    rng = np.random.default_rng(17)
+    deg = gr.degrees().astype(np.float64)
+    nz = np.nonzero(deg > 0)[0]
+    cdf = np.cumsum(deg[nz])
+    reqs = [nz[np.minimum(np.searchsorted(cdf, rng.uniform(0, cdf[-1], n)), nz.shape[0] - 1)]
+            .astype(np.int32) for n in (1, 37, 512, 200)]
+    with lp.Graph(gr.offsets, gr.indices) as g:
+        with lp.Server(g, slots=2) as srv:
+            tickets = [srv.submit(r, "AA", 32, 10) for r in reqs]
+            outs = [srv.wait(t)[0] for t in tickets]
+    for r, out in zip(reqs, outs):
+        ref = oracle.query(gr, 32, "AA", r, 10)
+        for i in range(r.shape[0]):
+            assert_same_query((out[0][i][: out[2][i]], out[1][i][: out[2][i]]), ref[i], "AA",
+                              f"R-MAT-24 server src={r[i]}")
