@@ -181,6 +181,20 @@ typedef struct {
 } lp_stats;
 lp_status lp_last_stats(const lp_graph *g, lp_stats *out);
 
+/* Several graphs in one call (the batched form of Algorithm 1): g holds the
+ * disjoint union of ngraphs graphs, graph i owning the original ids
+ * [vstart[i], vstart[i+1]) (vstart[0] = 0, non-decreasing, vstart[ngraphs] =
+ * n; no edge may join two graphs).  Every accumulation launch covers all the
+ * graphs; thresholds and top-k are per graph.  Graph i gets what lp_predict
+ * returns for it alone with k = k[i] (ids as in g): its rows start at output
+ * offset sum_{j<i} k[j], out_count[i] = k'_i, and rows beyond k'_i in its
+ * range are left untouched.  vstart, k, out_count: host arrays; out_a, out_c,
+ * out_score: sum(k) entries, device or host.  Errors: LP_ERR_INVALID_GRAPH if
+ * an edge joins two graphs, LP_ERR_INVALID_ARGUMENT for bad vstart / k. */
+lp_status lp_predict_multi(lp_graph *g, int64_t ngraphs, const int64_t *vstart, const int64_t *k,
+                           lp_measure m, int64_t hub_limit, float score_threshold, int32_t *out_a,
+                           int32_t *out_c, float *out_score, int64_t *out_count, void *hip_stream);
+
 /* ---------------------------------------------------------------------------
  * Serving: a request loop over the per-source query (lp_query), for the
  * recommendation use the paper describes in Section 1.  A server keeps the

@@ -18,8 +18,8 @@ import os
 
 import numpy as np
 
-__all__ = ["MEASURES", "HUB_NONE", "LpError", "Graph", "predict", "query", "fingerprint",
-           "set_tuning", "last_stats", "Server", "library_path", "load"]
+__all__ = ["MEASURES", "HUB_NONE", "LpError", "Graph", "predict", "predict_multi", "query",
+           "fingerprint", "set_tuning", "last_stats", "Server", "library_path", "load"]
 
 MEASURES = ("CN", "JC", "SI", "SC", "HP", "HD", "LHN", "AA", "RA")
 HUB_NONE = (1 << 63) - 1  # L_H = infinity: IBase
@@ -95,6 +95,8 @@ def load():
     lib.lp_graph_info.argtypes = [vp, vp, vp, vp, vp]
     lib.lp_predict.restype = st
     lib.lp_predict.argtypes = [vp, ctypes.c_int, i64, i64, f32, vp, vp, vp, vp, vp]
+    lib.lp_predict_multi.restype = st
+    lib.lp_predict_multi.argtypes = [vp, i64, vp, vp, ctypes.c_int, i64, f32, vp, vp, vp, vp, vp]
     lib.lp_query.restype = st
     lib.lp_query.argtypes = [vp, vp, i64, ctypes.c_int, i64, i32, f32, vp, vp, vp, vp]
     lib.lp_fingerprint.restype = st
@@ -218,6 +220,33 @@ def predict(g: Graph, measure, hub_limit, k: int, score_threshold: float = 0.0, 
                           _ptr(a), _ptr(c), _ptr(s), ctypes.byref(cnt), _stream(stream)))
     n = cnt.value
     return a[:n], c[:n], s[:n]
+
+
+def predict_multi(g: Graph, vstart, ks, measure, hub_limit, score_threshold: float = 0.0,
+                  stream=None):
+    """Several graphs in one call (lp_predict_multi).  vstart: ngraphs + 1
+    original-id boundaries; ks: per-graph k.  Returns a list of per-graph
+    (a, c, score) CUDA tensors of length k'_i."""
+    import torch
+    lib = load()
+    vs = np.ascontiguousarray(np.asarray(vstart, dtype=np.int64))
+    kk = np.ascontiguousarray(np.asarray(ks, dtype=np.int64))
+    ng = int(kk.shape[0])
+    tot = int(kk.sum())
+    dev = torch.device("cuda", torch.cuda.current_device())
+    a = torch.empty(max(tot, 1), dtype=torch.int32, device=dev)
+    c = torch.empty(max(tot, 1), dtype=torch.int32, device=dev)
+    s = torch.empty(max(tot, 1), dtype=torch.float32, device=dev)
+    cnt = np.zeros(ng, dtype=np.int64)
+    _check(lib.lp_predict_multi(g.handle, ng, _ptr(vs), _ptr(kk), _measure(measure), _hub(hub_limit),
+                                float(score_threshold), _ptr(a), _ptr(c), _ptr(s), _ptr(cnt),
+                                _stream(stream)))
+    out, off = [], 0
+    for i in range(ng):
+        n = int(cnt[i])
+        out.append((a[off:off + n], c[off:off + n], s[off:off + n]))
+        off += int(kk[i])
+    return out
 
 
 def query(g: Graph, sources, measure, hub_limit, k_q: int, score_threshold: float = 0.0,

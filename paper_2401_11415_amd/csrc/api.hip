@@ -12,6 +12,9 @@ void destroy_graph(lp_graph* g);
 lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int32_t* out_a,
                       int32_t* out_c, float* out_score, int64_t* out_count, hipStream_t st);
 lp_status run_fingerprint(lp_graph* g, int64_t L, uint64_t* out, hipStream_t st);
+lp_status run_predict_multi(lp_graph* g, int64_t ng, const int64_t* vstart, const int64_t* kk, int m,
+                            int64_t L, float s_th, int32_t* out_a, int32_t* out_c, float* out_score,
+                            int64_t* out_count, hipStream_t st);
 lp_status run_query(lp_graph* g, Workspace& w, const int32_t* sources, int64_t nq, int m, int64_t L,
                     int32_t kq,
                     float s_th, int32_t* out_c, float* out_score, int32_t* out_count,
@@ -133,6 +136,34 @@ lp_status lp_predict(lp_graph* g, lp_measure m, int64_t hub_limit, int64_t k, fl
     LP_TRY(select_device(g));
     return run_predict(g, (int)m, hub_limit, k, score_threshold, out_a, out_c, out_score, out_count,
                        (hipStream_t)hip_stream);
+  });
+}
+
+lp_status lp_predict_multi(lp_graph* g, int64_t ngraphs, const int64_t* vstart, const int64_t* k,
+                           lp_measure m, int64_t hub_limit, float score_threshold, int32_t* out_a,
+                           int32_t* out_c, float* out_score, int64_t* out_count, void* hip_stream) {
+  clear_error();
+  return guarded([&]() -> lp_status {
+    LP_TRY(check_common(g, (int)m, hub_limit, score_threshold));
+    if (ngraphs < 1 || ngraphs > INT32_MAX)
+      return set_error(LP_ERR_INVALID_ARGUMENT, "ngraphs must be in [1, 2^31 - 1]");
+    if (!vstart || !k || !out_count) return set_error(LP_ERR_INVALID_ARGUMENT, "array pointer is NULL");
+    if (vstart[0] != 0 || vstart[ngraphs] != g->n)
+      return set_error(LP_ERR_INVALID_ARGUMENT, "vstart must run from 0 to n");
+    uint64_t ktot = 0;
+    for (int64_t i = 0; i < ngraphs; i++) {
+      if (vstart[i + 1] < vstart[i]) return set_error(LP_ERR_INVALID_ARGUMENT, "vstart decreases");
+      if (k[i] < 0) return set_error(LP_ERR_INVALID_ARGUMENT, "k[%lld] < 0", (long long)i);
+      ktot += (uint64_t)k[i];
+    }
+    if (ktot >= (1ull << 32)) return set_error(LP_ERR_INVALID_ARGUMENT, "sum of k too large");
+    if (ktot > 0 && (!out_a || !out_c || !out_score))
+      return set_error(LP_ERR_INVALID_ARGUMENT, "output pointer is NULL");
+    BusyGuard busy(g);
+    if (!busy.ok) return set_error(LP_ERR_BUSY, "graph is in use by another thread");
+    LP_TRY(select_device(g));
+    return run_predict_multi(g, ngraphs, vstart, k, (int)m, hub_limit, score_threshold, out_a, out_c,
+                             out_score, out_count, (hipStream_t)hip_stream);
   });
 }
 

@@ -244,14 +244,14 @@ lp_status build_graph(int64_t n, const int64_t* offsets, const int32_t* indices,
   DevBuf& d_val = t.b[6];
   DevBuf& d_suflen = t.b[7];
   DevBuf& d_incl = t.b[8];
-  DevBuf sort_tmp[3];
+  DevBuf sort_tmp[4];
   DevBuf counts, scan_tmp;
   struct Rel {
-    DevBuf* b[5];
+    DevBuf* b[6];
     ~Rel() {
       for (auto x : b) x->release();
     }
-  } rel{{&sort_tmp[0], &sort_tmp[1], &sort_tmp[2], &counts, &scan_tmp}};
+  } rel{{&sort_tmp[0], &sort_tmp[1], &sort_tmp[2], &sort_tmp[3], &counts, &scan_tmp}};
 
   LP_TRY(d_off_old.ensure((size_t)(n + 1) * 8));
   LP_HIP(hipMemcpyAsync(d_off_old.p, offsets, (size_t)(n + 1) * 8, hipMemcpyDefault, st));
@@ -426,8 +426,8 @@ void release_workspace(Workspace& w) {
   DevBuf* all[] = {&w.cnt, &w.wedges, &w.lists, &w.counters, &w.stats, &w.cand_s, &w.cand_a,
                    &w.cand_c, &w.tmp_s[0], &w.tmp_s[1], &w.tmp_a[0], &w.tmp_a[1], &w.tmp_c[0],
                    &w.tmp_c[1], &w.hist, &w.sel_state, &w.sort_tmp[0], &w.sort_tmp[1],
-                   &w.sort_tmp[2], &w.sort_counts, &w.scan_tmp, &w.global_tab, &w.q_src,
-                   &w.q_cnt, &w.q_wedges, &w.q_rows, &w.q_out};
+                   &w.sort_tmp[2], &w.sort_tmp[3], &w.sort_counts, &w.scan_tmp, &w.global_tab, &w.q_src,
+                   &w.q_cnt, &w.q_wedges, &w.q_rows, &w.q_out, &w.m_graph, &w.m_gid};
   for (auto b : all) b->release();
   w.host_stats.release();
   for (int i = 0; i < Workspace::kSide; i++) {

@@ -45,7 +45,28 @@ struct Emit {
   uint32_t ovf_cap;
   uint32_t* err;           // error flags
   unsigned long long* work;  // [5] this launch's work counters (lp_bucket_stats order)
+  // several graphs at once: graph i owns original ids [gstart[i], gstart[i+1])
+  // and keeps keys >= gtau[3i..3i+2]; null gtau: tau applies to every source
+  const uint32_t* gtau;
+  const uint32_t* gstart;
+  uint32_t ngraphs;
 };
+
+// Graph of an original id (several-graph calls only).
+__device__ inline uint32_t graph_of(const Emit& E, uint32_t key) {
+  uint32_t lo = 0, hi = E.ngraphs;  // gstart[lo] <= key < gstart[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (E.gstart[mid] <= key) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Threshold key of the source with original id key (predict orientation).
+__device__ inline const uint32_t* tau_of(const Emit& E, uint32_t key) {
+  return E.gtau ? E.gtau + 3 * graph_of(E, key) : E.tau;
+}
 
 // Work counters of one lane (sources, sum d_a, arcs, wedges, candidates),
 // added to the launch's totals once per wave at the end of a kernel.
@@ -234,6 +255,7 @@ __device__ inline uint64_t min_wsum(int m, uint32_t ts_bits, int shift) {
   if (ts_bits <= 1u || (m != LP_AA && m != LP_RA)) return 1ull;
   const double below = (double)__uint_as_float(ts_bits - 1u);  // positive floats: bits are ordered
   const double est = floor(ldexp(below, shift));
+  if (!(est < 1.8e19)) return ~0ull;  // no fixed-point sum reaches it
   return est < 1.0 ? 1ull : (uint64_t)est;
 }
 
@@ -295,13 +317,20 @@ __device__ inline void stage_score(const Emit& E, const GView& g, Stage& S, FpAc
   if (S.n == 0) return;
   wave_fence();
   const bool want_dc = needs_dc(E.measure);
-  const uint32_t t0 = E.tau[0], t1 = E.tau[1], t2 = E.tau[2];
-  const double lo = pass_edge(E.fp_mode ? 0u : t0, E.s_th);
+  uint32_t t0 = E.tau[0], t1 = E.tau[1], t2 = E.tau[2];
+  double lo = pass_edge(E.fp_mode ? 0u : t0, E.s_th);
   for (uint32_t j0 = 0; j0 < S.n; j0 += 64) {
     const uint32_t j = j0 + lane_id();
     const bool in = j < S.n;
     const uint32_t jc = in ? j : 0u;
     const uint32_t c = S.c[jc], h = S.h[jc], k = S.k[jc], da = S.d[jc];
+    if (!kQuery && E.gtau) {  // each source keeps its own graph's threshold
+      const uint32_t* t = tau_of(E, k);
+      t0 = t[0];
+      t1 = t[1];
+      t2 = t[2];
+      lo = pass_edge(t0, E.s_th);
+    }
     const uint64_t wsum = kW ? (((uint64_t)S.w2[jc] << 32) | h) : 0ull;
     const uint32_t dc = want_dc ? g.deg[c] : 0u;
     // most staged candidates fail the threshold: reject those without

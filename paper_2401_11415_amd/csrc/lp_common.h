@@ -74,11 +74,13 @@ struct Workspace {
   // candidate buffers (score bits, original a, original c) and selection
   DevBuf cand_s, cand_a, cand_c;
   DevBuf tmp_s[2], tmp_a[2], tmp_c[2];
-  DevBuf hist, sel_state, sort_tmp[3], sort_counts, scan_tmp;
+  DevBuf hist, sel_state, sort_tmp[4], sort_counts, scan_tmp;
   DevBuf global_tab;
   unsigned global_slabs = 0;  // accumulator slabs in global_tab
   // query
   DevBuf q_src, q_cnt, q_wedges, q_rows, q_out;
+  // several graphs at once: per-graph tables, candidate graph ids
+  DevBuf m_graph, m_gid;
   HostBuf host_stats;
   // side streams for the concurrent launches of a sampling phase (default
   // priority), forked from and joined back to the caller's stream
@@ -139,13 +141,13 @@ lp_status scan_inclusive_u32_u64(const uint32_t* in, uint64_t* out, int64_t n, D
 // Stable LSD radix sort of n records with up to three uint32 words, ordered
 // ascending by the (possibly complemented) key words, most significant first.
 struct SortSpec {
-  uint32_t* w[3];       // record words (sorted in place)
-  int nwords;           // 1..3
+  uint32_t* w[4];       // record words (sorted in place)
+  int nwords;           // 1..4
   int nkeys;            // the first nkeys words are the key, word 0 most significant
-  int key_bits[3];      // significant bits per key word (<= 32)
-  bool invert[3];       // complement this key word (descending order)
+  int key_bits[4];      // significant bits per key word (<= 32)
+  bool invert[4];       // complement this key word (descending order)
 };
-lp_status radix_sort(const SortSpec& spec, int64_t n, DevBuf tmp[3], DevBuf& counts,
+lp_status radix_sort(const SortSpec& spec, int64_t n, DevBuf tmp[4], DevBuf& counts,
                      DevBuf& scan_tmp, hipStream_t st);
 
 int num_cus();

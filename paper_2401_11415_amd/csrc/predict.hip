@@ -453,9 +453,6 @@ __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, WorkList 
   Retry<kW> RT{L.rt_key[wv], L.rt_h[wv], kW ? L.rt_w[wv] : nullptr};
   FpAcc fa;
   WorkAcc wk;
-  const uint32_t ts_bits = E.fp_mode ? 0u : E.tau[0];
-  const uint64_t wmin = kW ? min_wsum(E.measure, ts_bits, E.shift) : 1ull;
-  const double lo = E.fp_mode ? 0.0 : pass_edge(ts_bits, E.s_th);
   const uint32_t total = uniform(work_count(wl));
   // slots [0, clean) of the group's table are empty: every sweep empties the
   // slots it reads, so only growth beyond the largest table so far is cleared
@@ -480,6 +477,10 @@ __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, WorkList 
     const uint32_t xb = xe < s.x1 ? g.adj[xe] : kEmpty32;
     uint32_t P, S;
     table_geometry(s.U + (s.x1 - s.x0), SLOTS, &P, &S);
+    // the source's threshold (its graph's, when several graphs run at once)
+    const uint32_t ts_bits = E.fp_mode ? 0u : uniform((kQuery ? E.tau : tau_of(E, s.key))[0]);
+    const uint64_t wmin = kW ? min_wsum(E.measure, ts_bits, E.shift) : 1ull;
+    const double lo = E.fp_mode ? 0.0 : pass_edge(ts_bits, E.s_th);
     const uint32_t hmin = kW ? 1u : min_count(E.measure, ts_bits, s.da, !kQuery);
     const uint32_t cut1 = kW ? 0xFFFFFFFFu : uniform(id_cutoff(E.measure, 1, s.da, lo, g, !kQuery));
     const uint32_t cut2 = kW ? 0xFFFFFFFFu : uniform(id_cutoff(E.measure, 2, s.da, lo, g, !kQuery));
@@ -610,6 +611,7 @@ struct BatchTab {
   uint32_t wedoff[B + 1];  // prefix of wedges
   uint32_t xoff[B + 1];    // prefix of first-order neighbours to exclude
   uint32_t hmin[B];
+  uint64_t wmin[kW ? B : 1];
   uint32_t cut[B][2];
   int ovf;
   uint8_t mark[NW][64];
@@ -651,9 +653,6 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
   Retry<kW> RT{L.rt_key[wv], L.rt_h[wv], kW ? L.rt_w[wv] : nullptr};
   FpAcc fa;
   WorkAcc wk;
-  const uint32_t ts_bits = E.fp_mode ? 0u : E.tau[0];
-  const uint64_t wmin = kW ? min_wsum(E.measure, ts_bits, E.shift) : 1ull;
-  const double lo = E.fp_mode ? 0.0 : pass_edge(ts_bits, E.s_th);
   const uint32_t total = uniform(work_count(wl));
   const uint32_t nbatch = (total + B - 1) / B;
   uint32_t clean = 0;  // slots [0, clean) of the table are empty
@@ -675,7 +674,11 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
         U = r.U;
         nx = r.x1 - r.x0;
         L.rec[tid] = r;
+        // the source's threshold (its graph's, when several graphs run at once)
+        const uint32_t ts_bits = E.fp_mode ? 0u : tau_of(E, r.key)[0];
+        const double lo = E.fp_mode ? 0.0 : pass_edge(ts_bits, E.s_th);
         L.hmin[tid] = kW ? 1u : min_count(E.measure, ts_bits, r.da, true);
+        if (kW) L.wmin[tid] = min_wsum(E.measure, ts_bits, E.shift);
         if (!kW) {
           cut0 = id_cutoff(E.measure, 1, r.da, lo, g, true);
           cut1 = id_cutoff(E.measure, 2, r.da, lo, g, true);
@@ -816,7 +819,7 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
         }
         ok = t < S && key != kEmpty32 && (wsum >> 63) == 0;
         wk.v[4] += ok ? 1u : 0u;
-        ok = ok && wsum >= wmin;
+        ok = ok && wsum >= L.wmin[ok ? key >> kBatchIdBits : 0u];
       } else {
         const uint64_t v = L.tab[tc];
         if (t < S) L.tab[t] = kSlotEmpty;
@@ -882,8 +885,6 @@ __global__ __launch_bounds__(kSpaThreads) void acc_spa_kernel(GView g, Emit E, W
   uint32_t* K = spa_keys + (uint64_t)blockIdx.x * g.n;
   FpAcc fa;
   WorkAcc wk;
-  const uint32_t ts_bits = E.fp_mode ? 0u : E.tau[0];
-  const uint64_t wmin = kW ? min_wsum(E.measure, ts_bits, E.shift) : 1ull;
   const uint32_t total = ov.ovf ? (ov.ovf_end - ov.ovf_begin) : uniform(work_count(wl));
   for (uint32_t i = blockIdx.x; i < total; i += gridDim.x) {
     SrcRec s;
@@ -896,6 +897,8 @@ __global__ __launch_bounds__(kSpaThreads) void acc_spa_kernel(GView g, Emit E, W
     } else {
       s = uniform_rec(load_rec(wl, i));
     }
+    const uint32_t ts_bits = E.fp_mode ? 0u : uniform((kQuery ? E.tau : tau_of(E, s.key))[0]);
+    const uint64_t wmin = kW ? min_wsum(E.measure, ts_bits, E.shift) : 1ull;
     const uint32_t hmin = kW ? 1u : min_count(E.measure, ts_bits, s.da, !kQuery);
     if (threadIdx.x == 0) nkeys = 0;
     __syncthreads();
@@ -1852,6 +1855,388 @@ lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int3
     S.ms_total = tm.ms(0, 3);
     return LP_OK;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Several graphs in one call.  The resident graph is the disjoint union of
+// ngraphs graphs, graph i owning original ids [gstart[i], gstart[i+1]).  Every
+// accumulation launch covers all graphs (no two-hop path leaves a graph, so
+// candidates never mix); thresholds and the final top-k are per graph.
+// ---------------------------------------------------------------------------
+
+__device__ inline uint32_t graph_of_id(const uint32_t* gstart, uint32_t ng, uint32_t key) {
+  uint32_t lo = 0, hi = ng;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (gstart[mid] <= key) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// err |= 1 if an edge joins two graphs
+__global__ void cross_check_kernel(const uint32_t* __restrict__ off, const uint32_t* __restrict__ adj,
+                                   const uint32_t* __restrict__ rank, const uint32_t* __restrict__ perm,
+                                   const uint32_t* __restrict__ gstart, uint32_t ng, int64_t n,
+                                   uint32_t* err) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= n) return;
+  const uint32_t gi = graph_of_id(gstart, ng, (uint32_t)o);
+  const uint32_t lo = gstart[gi], hi = gstart[gi + 1];
+  const uint32_t v = rank[o];
+  bool bad = false;
+  for (uint32_t e = off[v]; e < off[v + 1]; e++) {
+    const uint32_t b = perm[adj[e]];
+    bad = bad || b < lo || b >= hi;
+  }
+  if (bad) atomicOr(err, 1u);
+}
+
+// graph id of each candidate (by its smaller original id) and per-graph counts
+__global__ void graph_id_kernel(const uint32_t* __restrict__ a, unsigned long long n,
+                                const uint32_t* __restrict__ gstart, uint32_t ng,
+                                uint32_t* __restrict__ gid, uint32_t* __restrict__ gcount) {
+  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (unsigned long long)gridDim.x * blockDim.x) {
+    const uint32_t gi = graph_of_id(gstart, ng, a[i]);
+    gid[i] = gi;
+    atomicAdd(&gcount[gi], 1u);
+  }
+}
+
+// Per-graph threshold from the sample sorted by (graph, score desc): the
+// score of the graph's r-th best sampled candidate with ids 0 (a lower bound
+// of that key), r = 1.5 k / stride + 64; no threshold when the graph sampled
+// fewer; k = 0 keeps nothing.
+__global__ void graph_tau_kernel(uint32_t ng, const uint32_t* __restrict__ gcount,
+                                 const uint32_t* __restrict__ gseg, const uint32_t* __restrict__ s_sorted,
+                                 const unsigned long long* __restrict__ gk, uint32_t stride,
+                                 uint32_t* __restrict__ gtau) {
+  const uint32_t gi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gi >= ng) return;
+  const unsigned long long k = gk[gi];
+  uint32_t t = 0;
+  const bool none = k == 0;
+  if (none) {
+    t = 0x7F800000u;  // +inf: no finite score reaches it
+  } else {
+    const unsigned long long r = (3 * k + 2 * (unsigned long long)stride - 1) / (2 * (unsigned long long)stride) + 64;
+    if (gcount[gi] >= r) t = s_sorted[gseg[gi] + r - 1];
+  }
+  gtau[3 * gi] = t;
+  gtau[3 * gi + 1] = none ? 0xFFFFFFFFu : 0u;
+  gtau[3 * gi + 2] = none ? 0xFFFFFFFFu : 0u;
+}
+
+// per-graph number of buffer entries whose key is >= the graph's threshold
+__global__ void graph_count_ge_kernel(const uint32_t* __restrict__ ks, const uint32_t* __restrict__ ka,
+                                      const uint32_t* __restrict__ kc, unsigned long long n,
+                                      const uint32_t* __restrict__ gstart, uint32_t ng,
+                                      const uint32_t* __restrict__ gtau, unsigned long long* out) {
+  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (unsigned long long)gridDim.x * blockDim.x) {
+    const uint32_t gi = graph_of_id(gstart, ng, ka[i]);
+    const uint32_t t0 = gtau[3 * gi], t1 = gtau[3 * gi + 1], t2 = gtau[3 * gi + 2];
+    const uint32_t s = ks[i], a = ~ka[i], x = ~kc[i];
+    if (s > t0 || (s == t0 && (a > t1 || (a == t1 && x >= t2)))) atomicAdd(&out[gi], 1ull);
+  }
+}
+
+// the first k_g entries of each graph's segment of the sorted buffer
+__global__ void graph_take_kernel(const uint32_t* __restrict__ gid, const uint32_t* __restrict__ s,
+                                  const uint32_t* __restrict__ a, const uint32_t* __restrict__ c,
+                                  unsigned long long n, const uint32_t* __restrict__ gseg,
+                                  const unsigned long long* __restrict__ gk,
+                                  const unsigned long long* __restrict__ goff, int32_t* __restrict__ oa,
+                                  int32_t* __restrict__ oc, float* __restrict__ os) {
+  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (unsigned long long)gridDim.x * blockDim.x) {
+    const uint32_t gi = gid[i];
+    const unsigned long long r = i - gseg[gi];
+    if (r < gk[gi]) {
+      const unsigned long long pos = goff[gi] + r;
+      oa[pos] = (int32_t)a[i];
+      oc[pos] = (int32_t)c[i];
+      os[pos] = __uint_as_float(s[i]);
+    }
+  }
+}
+
+lp_status run_predict_multi(lp_graph* g, int64_t ng, const int64_t* vstart, const int64_t* kk, int m,
+                            int64_t L, float s_th, int32_t* out_a, int32_t* out_c, float* out_score,
+                            int64_t* out_count, hipStream_t st) {
+  Workspace& w = g->ws;
+  lp_stats& S = g->last;
+  S = lp_stats{};
+  for (int64_t i = 0; i < ng; i++) out_count[i] = 0;
+  const uint32_t NG = (uint32_t)ng;
+  // per-graph tables: gstart[ng+1] u32, gtau[3ng] u32, gcount[ng] u32, gseg[ng] u32,
+  // gk[ng] u64, goff[ng] u64, gge[ng] u64
+  uint64_t ktot = 0;
+  std::vector<uint32_t> hstart(NG + 1);
+  std::vector<unsigned long long> hk(NG), hoff(NG);
+  for (uint32_t i = 0; i <= NG; i++) hstart[i] = (uint32_t)vstart[i];
+  for (uint32_t i = 0; i < NG; i++) {
+    hk[i] = (unsigned long long)kk[i];
+    hoff[i] = ktot;
+    ktot += hk[i];
+  }
+  const size_t u32n = ((size_t)NG + 1 + 3 * (size_t)NG + 2 * (size_t)NG + 63) & ~(size_t)63;
+  LP_TRY(w.m_graph.ensure(u32n * 4 + (size_t)NG * 8 * 3 + 256));
+  uint32_t* gstart = w.m_graph.as<uint32_t>();
+  uint32_t* gtau = gstart + NG + 1;
+  uint32_t* gcount = gtau + 3 * (size_t)NG;
+  uint32_t* gseg = gcount + NG;
+  unsigned long long* gk = reinterpret_cast<unsigned long long*>(w.m_graph.as<char>() + u32n * 4);
+  unsigned long long* goff = gk + NG;
+  unsigned long long* gge = goff + NG;
+  LP_HIP(hipMemcpyAsync(gstart, hstart.data(), (NG + 1) * 4, hipMemcpyHostToDevice, st));
+  LP_HIP(hipMemcpyAsync(gk, hk.data(), NG * 8, hipMemcpyHostToDevice, st));
+  LP_HIP(hipMemcpyAsync(goff, hoff.data(), NG * 8, hipMemcpyHostToDevice, st));
+  LP_HIP(hipMemsetAsync(gtau, 0, (size_t)NG * 12, st));
+  uint32_t *ovf, *ovf_count, *err, *tau;
+  void* ovf_rec;
+  unsigned long long *count, *fp;
+  uint32_t ovf_cap;
+  LP_TRY(ensure_ovf(w, &ovf, &ovf_rec, &ovf_count, &ovf_cap, &err, &count, &fp, &tau, st));
+  if (g->n > 0) {
+    hipLaunchKernelGGL(cross_check_kernel, dim3(grid_for((uint64_t)g->n, 256, 0x7FFFFFFF)), dim3(256), 0,
+                       st, g->off, g->adj, g->rank, g->perm, gstart, NG, g->n, err);
+    LP_HIP(hipGetLastError());
+    uint32_t herr = 0;
+    LP_HIP(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, st));
+    LP_HIP(hipStreamSynchronize(st));
+    if (herr) return set_error(LP_ERR_INVALID_GRAPH, "an edge joins two of the graphs");
+  }
+  Timer tm;
+  LP_HIP(hipEventRecord(tm.ev[0], st));
+  PlanResult pr;
+  LP_TRY(run_plan(g, L, &pr, st));
+  LP_HIP(hipEventRecord(tm.ev[1], st));
+  S.wedges = pr.out.wedges;
+  S.sources = pr.out.sources;
+  for (int b = 0; b < kBuckets; b++) S.bucket_sources[b] = pr.out.count[b];
+  if (ktot == 0 || pr.out.wedges == 0) {
+    LP_HIP(hipStreamSynchronize(st));
+    return LP_OK;
+  }
+  const GView gv = view_of(g);
+  const uint64_t total_w = pr.out.wedges;
+  const uint64_t budget = g->tuning.sample_budget > 0 ? (uint64_t)g->tuning.sample_budget
+                                                      : (g->tuning.sample_budget < 0 ? 0 : (1ull << 22));
+  const bool sample = budget > 0 && total_w > budget && total_w > 8ull * ktot;
+  uint32_t stride = 1;
+  if (sample) {
+    const uint64_t sd = (total_w + budget - 1) / budget;
+    stride = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(sd, 2), 1u << 20);
+  }
+  uint64_t cap = sample ? 2 * (total_w / stride) + 4 * ktot + (1u << 20) : total_w;
+  cap = std::min<uint64_t>(cap, total_w);
+  cap = std::min<uint64_t>(cap, (1ull << 32) - 1);
+  LP_TRY(w.cand_s.ensure(cap * 4));
+  LP_TRY(w.cand_a.ensure(cap * 4));
+  LP_TRY(w.cand_c.ensure(cap * 4));
+  LP_TRY(w.m_gid.ensure(cap * 4));
+  LP_TRY(ensure_select_bufs(w, cap));
+  Emit E{};
+  E.measure = m;
+  E.shift = g->fixed_shift;
+  E.s_th = s_th;
+  E.tau = tau;
+  E.out_s = w.cand_s.as<uint32_t>();
+  E.out_a = w.cand_a.as<uint32_t>();
+  E.out_c = w.cand_c.as<uint32_t>();
+  E.out_count = count;
+  E.cap = cap;
+  E.fp = fp;
+  E.ovf = ovf;
+  E.ovf_rec = ovf_rec;
+  E.ovf_count = ovf_count;
+  E.ovf_cap = ovf_cap;
+  E.err = err;
+  E.gtau = gtau;
+  E.gstart = gstart;
+  E.ngraphs = NG;
+  const SrcRec* lists = w.lists.as<SrcRec>();
+  uint32_t ovf_host = 0;
+  unsigned long long n_sample = 0;
+  LaunchClock clk(&S);
+  uint32_t* gid = w.m_gid.as<uint32_t>();
+  const unsigned cus = (unsigned)num_cus();
+  if (sample) {
+    // sampled sources without thresholds, then each graph's threshold
+    LP_TRY(run_phase_any<false>(g, w, gv, E, lists, (uint64_t)g->n, pr.out.count, stride, 1, &ovf_host,
+                                &clk, st));
+    LP_HIP(hipMemcpyAsync(&n_sample, count, 8, hipMemcpyDeviceToHost, st));
+    LP_HIP(hipStreamSynchronize(st));
+    if (n_sample > cap) return set_error(LP_ERR_OUT_OF_MEMORY, "sample exceeded its buffer");
+    LP_HIP(hipMemsetAsync(gcount, 0, (size_t)NG * 4, st));
+    uint32_t* ts = w.tmp_s[0].as<uint32_t>();
+    uint32_t* tg = w.tmp_a[0].as<uint32_t>();
+    if (n_sample > 0) {
+      hipLaunchKernelGGL(graph_id_kernel, dim3(grid_for(n_sample, 256, cus * 8)), dim3(256), 0, st,
+                         E.out_a, n_sample, gstart, NG, tg, gcount);
+      LP_HIP(hipGetLastError());
+      LP_HIP(hipMemcpyAsync(ts, E.out_s, n_sample * 4, hipMemcpyDeviceToDevice, st));
+      SortSpec sp{};
+      sp.w[0] = tg;
+      sp.w[1] = ts;
+      sp.nwords = 2;
+      sp.nkeys = 2;
+      sp.key_bits[0] = id_bits(NG);
+      sp.key_bits[1] = 32;
+      sp.invert[1] = true;
+      LP_TRY(radix_sort(sp, (int64_t)n_sample, w.sort_tmp, w.sort_counts, w.scan_tmp, st));
+    }
+    LP_TRY(scan_exclusive_u32(gcount, gseg, (int64_t)NG, w.scan_tmp, st));
+    hipLaunchKernelGGL(graph_tau_kernel, dim3((NG + 255) / 256), dim3(256), 0, st, NG, gcount, gseg, ts,
+                       gk, stride, gtau);
+    LP_HIP(hipGetLastError());
+  }
+  unsigned long long n_total = 0;
+  for (int attempt = 0;; attempt++) {
+    if (attempt > 4) return set_error(LP_ERR_DEVICE, "per-graph thresholds did not converge");
+    if (sample) {
+      LP_HIP(hipMemcpyAsync(count, &n_sample, 8, hipMemcpyHostToDevice, st));
+      LP_TRY(run_phase_any<false>(g, w, gv, E, lists, (uint64_t)g->n, pr.out.count, stride, 2,
+                                  &ovf_host, &clk, st));
+    } else {
+      LP_TRY(run_phase_any<false>(g, w, gv, E, lists, (uint64_t)g->n, pr.out.count, 1, 0, &ovf_host,
+                                  &clk, st));
+    }
+    LP_HIP(hipMemcpyAsync(&n_total, count, 8, hipMemcpyDeviceToHost, st));
+    LP_HIP(hipStreamSynchronize(st));
+    if (n_total > cap) {
+      // graphs without a threshold kept more than the buffer holds: the pass
+      // counted every entry, so grow to that and run it again
+      if (n_total >= (1ull << 32) - 1)
+        return set_error(LP_ERR_OUT_OF_MEMORY, "candidate buffer overflow (%llu)",
+                         (unsigned long long)n_total);
+      const uint64_t ncap = n_total;
+      const unsigned long long keep = sample ? n_sample : 0;
+      if (keep > 0) {  // the sampled entries move with the buffers
+        LP_TRY(w.tmp_s[1].ensure(keep * 4));
+        LP_TRY(w.tmp_a[1].ensure(keep * 4));
+        LP_TRY(w.tmp_c[1].ensure(keep * 4));
+        LP_HIP(hipMemcpyAsync(w.tmp_s[1].p, E.out_s, keep * 4, hipMemcpyDeviceToDevice, st));
+        LP_HIP(hipMemcpyAsync(w.tmp_a[1].p, E.out_a, keep * 4, hipMemcpyDeviceToDevice, st));
+        LP_HIP(hipMemcpyAsync(w.tmp_c[1].p, E.out_c, keep * 4, hipMemcpyDeviceToDevice, st));
+        LP_HIP(hipStreamSynchronize(st));
+      }
+      w.cand_s.release();
+      w.cand_a.release();
+      w.cand_c.release();
+      LP_TRY(w.cand_s.ensure(ncap * 4));
+      LP_TRY(w.cand_a.ensure(ncap * 4));
+      LP_TRY(w.cand_c.ensure(ncap * 4));
+      LP_TRY(w.m_gid.ensure(ncap * 4));
+      if (keep > 0) {
+        LP_HIP(hipMemcpyAsync(w.cand_s.p, w.tmp_s[1].p, keep * 4, hipMemcpyDeviceToDevice, st));
+        LP_HIP(hipMemcpyAsync(w.cand_a.p, w.tmp_a[1].p, keep * 4, hipMemcpyDeviceToDevice, st));
+        LP_HIP(hipMemcpyAsync(w.cand_c.p, w.tmp_c[1].p, keep * 4, hipMemcpyDeviceToDevice, st));
+      }
+      cap = ncap;
+      E.cap = cap;
+      E.out_s = w.cand_s.as<uint32_t>();
+      E.out_a = w.cand_a.as<uint32_t>();
+      E.out_c = w.cand_c.as<uint32_t>();
+      gid = w.m_gid.as<uint32_t>();
+      if (!sample) LP_HIP(hipMemsetAsync(count, 0, 8, st));
+      S.retries++;
+      continue;
+    }
+    if (!sample) break;
+    // a graph's answer is in the buffer iff at least k of its keys are >= its threshold
+    LP_HIP(hipMemsetAsync(gge, 0, (size_t)NG * 8, st));
+    hipLaunchKernelGGL(graph_count_ge_kernel, dim3(grid_for(n_total, 256, cus * 8)), dim3(256), 0, st,
+                       E.out_s, E.out_a, E.out_c, n_total, gstart, NG, gtau, gge);
+    LP_HIP(hipGetLastError());
+    std::vector<unsigned long long> hge(NG);
+    std::vector<uint32_t> htau(3 * (size_t)NG);
+    LP_HIP(hipMemcpyAsync(hge.data(), gge, NG * 8, hipMemcpyDeviceToHost, st));
+    LP_HIP(hipMemcpyAsync(htau.data(), gtau, NG * 12, hipMemcpyDeviceToHost, st));
+    LP_HIP(hipStreamSynchronize(st));
+    bool redo = false;
+    for (uint32_t i = 0; i < NG; i++) {
+      const bool has_tau = (htau[3 * i] | htau[3 * i + 1] | htau[3 * i + 2]) != 0;
+      if (has_tau && hk[i] > 0 && hge[i] < hk[i]) {
+        htau[3 * i] = htau[3 * i + 1] = htau[3 * i + 2] = 0;
+        redo = true;
+      }
+    }
+    if (!redo) break;
+    S.retries++;
+    LP_HIP(hipMemcpyAsync(gtau, htau.data(), NG * 12, hipMemcpyHostToDevice, st));
+  }
+  S.appended = n_total;
+  LP_HIP(hipEventRecord(tm.ev[2], st));
+  // sort the buffer by (graph, score desc, a, c) and take each graph's first k
+  LP_HIP(hipMemsetAsync(gcount, 0, (size_t)NG * 4, st));
+  std::vector<uint32_t> hcount(NG);
+  if (n_total > 0) {
+    hipLaunchKernelGGL(graph_id_kernel, dim3(grid_for(n_total, 256, cus * 8)), dim3(256), 0, st, E.out_a,
+                       n_total, gstart, NG, gid, gcount);
+    LP_HIP(hipGetLastError());
+    SortSpec sp{};
+    sp.w[0] = gid;
+    sp.w[1] = E.out_s;
+    sp.w[2] = E.out_a;
+    sp.w[3] = E.out_c;
+    sp.nwords = 4;
+    sp.nkeys = 4;
+    sp.key_bits[0] = id_bits(NG);
+    sp.key_bits[1] = 32;
+    sp.key_bits[2] = id_bits((uint64_t)g->n);
+    sp.key_bits[3] = id_bits((uint64_t)g->n);
+    sp.invert[1] = true;
+    LP_TRY(radix_sort(sp, (int64_t)n_total, w.sort_tmp, w.sort_counts, w.scan_tmp, st));
+  }
+  LP_TRY(scan_exclusive_u32(gcount, gseg, (int64_t)NG, w.scan_tmp, st));
+  hipPointerAttribute_t at;
+  const bool dev_out =
+      hipPointerGetAttributes(&at, out_a) == hipSuccess && at.type == hipMemoryTypeDevice &&
+      hipPointerGetAttributes(&at, out_c) == hipSuccess && at.type == hipMemoryTypeDevice &&
+      hipPointerGetAttributes(&at, out_score) == hipSuccess && at.type == hipMemoryTypeDevice;
+  (void)hipGetLastError();
+  int32_t* xa = out_a;
+  int32_t* xc = out_c;
+  float* xs = out_score;
+  if (!dev_out) {
+    LP_TRY(w.q_out.ensure(ktot * 12 + 64));
+    xa = w.q_out.as<int32_t>();
+    xc = xa + ktot;
+    xs = reinterpret_cast<float*>(xc + ktot);
+  }
+  if (n_total > 0) {
+    hipLaunchKernelGGL(graph_take_kernel, dim3(grid_for(n_total, 256, cus * 8)), dim3(256), 0, st, gid,
+                       E.out_s, E.out_a, E.out_c, n_total, gseg, gk, goff, xa, xc, xs);
+    LP_HIP(hipGetLastError());
+  }
+  LP_HIP(hipMemcpyAsync(hcount.data(), gcount, NG * 4, hipMemcpyDeviceToHost, st));
+  LP_HIP(hipEventRecord(tm.ev[3], st));
+  LP_HIP(hipStreamSynchronize(st));
+  if (!dev_out) {
+    // each graph's rows sit at its output offset; copy only the filled ones
+    for (uint32_t i = 0; i < NG; i++) {
+      const uint64_t kout = std::min<uint64_t>(hk[i], hcount[i]);
+      if (!kout) continue;
+      LP_HIP(hipMemcpyAsync(out_a + hoff[i], xa + hoff[i], kout * 4, hipMemcpyDefault, st));
+      LP_HIP(hipMemcpyAsync(out_c + hoff[i], xc + hoff[i], kout * 4, hipMemcpyDefault, st));
+      LP_HIP(hipMemcpyAsync(out_score + hoff[i], xs + hoff[i], kout * 4, hipMemcpyDefault, st));
+    }
+    LP_HIP(hipStreamSynchronize(st));
+  }
+  uint32_t herr = 0;
+  LP_HIP(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, st));
+  LP_HIP(hipStreamSynchronize(st));
+  if (herr) return set_error(LP_ERR_DEVICE, "device error flags 0x%x", herr);
+  for (uint32_t i = 0; i < NG; i++) out_count[i] = (int64_t)std::min<uint64_t>(hk[i], hcount[i]);
+  LP_TRY(collect_work(w, &S, st));
+  S.ms_plan = tm.ms(0, 1);
+  S.ms_accumulate = tm.ms(1, 2);
+  S.ms_total = tm.ms(0, 3);
+  S.ms_select = S.ms_total - S.ms_plan - S.ms_accumulate;
+  return LP_OK;
 }
 
 lp_status run_fingerprint(lp_graph* g, int64_t L, uint64_t* out, hipStream_t st) {

@@ -228,8 +228,8 @@ constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;
 
 struct PassArgs {
-  const uint32_t* in[3];
-  uint32_t* out[3];
+  const uint32_t* in[4];
+  uint32_t* out[4];
   int nwords;
   int key_word;
   int shift;
@@ -293,7 +293,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(PassArgs p,
   }
 }
 
-lp_status radix_sort(const SortSpec& spec, int64_t n, DevBuf tmp[3], DevBuf& counts,
+lp_status radix_sort(const SortSpec& spec, int64_t n, DevBuf tmp[4], DevBuf& counts,
                      DevBuf& scan_tmp, hipStream_t st) {
   if (n <= 1) return LP_OK;
   if (n >= (int64_t)UINT32_MAX) return set_error(LP_ERR_INVALID_ARGUMENT, "sort too large");
@@ -302,13 +302,14 @@ lp_status radix_sort(const SortSpec& spec, int64_t n, DevBuf tmp[3], DevBuf& cou
   LP_TRY(counts.ensure((size_t)ntiles * 256 * 4 * 2));
   uint32_t* cnts = counts.as<uint32_t>();
   uint32_t* offs = cnts + ntiles * 256;
-  uint32_t* cur[3] = {spec.w[0], spec.w[1], spec.w[2]};
-  uint32_t* alt[3] = {tmp[0].as<uint32_t>(), tmp[1].as<uint32_t>(), tmp[2].as<uint32_t>()};
+  uint32_t* cur[4] = {spec.w[0], spec.w[1], spec.w[2], spec.w[3]};
+  uint32_t* alt[4] = {tmp[0].as<uint32_t>(), tmp[1].as<uint32_t>(), tmp[2].as<uint32_t>(),
+                      tmp[3].as<uint32_t>()};
   int passes = 0;
   for (int kw = spec.nkeys - 1; kw >= 0; kw--) {
     for (int shift = 0; shift < spec.key_bits[kw]; shift += 8) {
       PassArgs pa{};
-      for (int k = 0; k < 3; k++) {
+      for (int k = 0; k < 4; k++) {
         pa.in[k] = cur[k];
         pa.out[k] = alt[k];
       }
@@ -323,7 +324,7 @@ lp_status radix_sort(const SortSpec& spec, int64_t n, DevBuf tmp[3], DevBuf& cou
       hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)ntiles), dim3(kSortThreads), 0, st,
                          pa, n, (const uint32_t*)offs, ntiles);
       LP_HIP(hipGetLastError());
-      for (int k = 0; k < 3; k++) {
+      for (int k = 0; k < 4; k++) {
         uint32_t* t = cur[k];
         cur[k] = alt[k];
         alt[k] = t;

@@ -201,3 +201,30 @@ def sample_sources(g: Graph, count: int, seed: int, top: int = 0) -> np.ndarray:
         hubs = np.argsort(-deg, kind="stable")[:top]
         pick = np.concatenate([pick, hubs])
     return np.unique(pick).astype(np.int32)
+
+
+def disjoint_union(graphs):
+    """One graph holding `graphs` side by side: graph i keeps its vertex order
+    and owns ids [vstart[i], vstart[i+1]).  Returns (Graph, vstart int64)."""
+    ns = np.array([g.n for g in graphs], dtype=np.int64)
+    vstart = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+    nnz = np.array([g.nnz for g in graphs], dtype=np.int64)
+    estart = np.concatenate([[0], np.cumsum(nnz)]).astype(np.int64)
+    off = np.empty(int(vstart[-1]) + 1, dtype=np.int64)
+    idx = np.empty(int(estart[-1]), dtype=np.int32)
+    for i, g in enumerate(graphs):
+        off[vstart[i]:vstart[i + 1]] = g.offsets[:-1] + estart[i]
+        idx[estart[i]:estart[i + 1]] = g.indices + np.int32(vstart[i])
+    off[-1] = estart[-1]
+    return Graph(off, idx, f"union({len(graphs)})"), vstart
+
+
+def chung_lu_batch(count: int, n_min: int, n_max: int, seed: int, gamma: float = 2.3,
+                   d_min: float = 8.0, d_max: float = 32.0):
+    """`count` Chung-Lu graphs of uneven size: n log-uniform in [n_min, n_max],
+    mean degree uniform in [d_min, d_max], exponent gamma, graph i seeded
+    1000 + i (sizes and degrees drawn from `seed`)."""
+    rng = np.random.default_rng(seed)
+    ns = np.exp(rng.uniform(np.log(n_min), np.log(n_max), count)).astype(np.int64)
+    ds = rng.uniform(d_min, d_max, count)
+    return [chung_lu(int(n), float(d), gamma, 1000 + i) for i, (n, d) in enumerate(zip(ns, ds))]

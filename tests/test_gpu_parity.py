@@ -493,3 +493,50 @@ def test_full_size_rmat24_server(lp):
         for i in range(r.shape[0]):
             assert_same_query((out[0][i][: out[2][i]], out[1][i][: out[2][i]]), ref[i], "AA",
                               f"R-MAT-24 server src={r[i]}")
+
+
+@pytest.mark.parametrize("budget", [-1, 3000])
+def test_predict_multi_equals_alone(lp, budget):
+    """Several graphs in one call: each graph's top-k equals lp_predict on that
+    graph alone and the oracle's list (ids shifted by the graph's start), with
+    and without per-graph thresholds from a sample."""
+    gs = synth.chung_lu_batch(24, 60, 6000, seed=9)
+    u, vs = synth.disjoint_union(gs)
+    ks = [max(0, gr.m // 10) for gr in gs]
+    ks[3] = 0
+    say(f"[gpu] predict_multi {len(gs)} graphs n={u.n} budget={budget}")
+    with lp.Graph(u.offsets, u.indices) as g:
+        lp.set_tuning(g, sample_budget=budget)
+        sampled = 0
+        for m, L in (("JC", 256), ("AA", None), ("CN", 8)):
+            res = lp.predict_multi(g, vs, ks, m, L)
+            st = lp.last_stats(g)
+            for i, gr in enumerate(gs):
+                a, c, s = (to_np(x) for x in res[i])
+                got = (a - vs[i], c - vs[i], s)
+                ref = oracle.predict(gr, L, m, ks[i])
+                assert_same_list(got, ref, m, f"multi graph {i} {m} L={L}")
+                if m != "AA":
+                    with lp.Graph(gr.offsets, gr.indices) as gi:
+                        alone = run_predict(lp, gi, m, L, ks[i])
+                    assert np.array_equal(got[0], alone[0]) and np.array_equal(got[1], alone[1])
+                    assert np.array_equal(got[2], alone[2])
+            sampled += sum(b["launches"] for b in st["sampled"].values())
+        assert (sampled > 0) == (budget > 0)
+
+
+def test_predict_multi_invalid(lp):
+    gs = synth.chung_lu_batch(3, 50, 200, seed=4)
+    u, vs = synth.disjoint_union(gs)
+    say("[gpu] predict_multi invalid")
+    with lp.Graph(u.offsets, u.indices) as g:
+        with pytest.raises(lp.LpError):
+            lp.predict_multi(g, [0, 10, u.n - 1], [1, 1], "JC", 256)  # does not end at n
+        with pytest.raises(lp.LpError):
+            lp.predict_multi(g, [0, 30, 20, u.n], [1, 1, 1], "JC", 256)  # decreasing
+        with pytest.raises(lp.LpError):
+            lp.predict_multi(g, vs, [1, -1, 1], "JC", 256)
+        with pytest.raises(lp.LpError) as e:
+            cut = int(vs[1]) + int(np.argmax(gs[1].degrees())) + 1  # a hub of graph 1 left behind
+            lp.predict_multi(g, [0, cut, u.n], [5, 5], "JC", 256)
+        assert e.value.name == "LP_ERR_INVALID_GRAPH"
