@@ -127,6 +127,11 @@ def main():
     ap.add_argument("--slots", type=int, default=2, help="--serve: concurrent batches")
     ap.add_argument("--sweep", action="store_true",
                     help="hub-limit sweep instead: time and holdout precision per L")
+    ap.add_argument("--multi", action="store_true",
+                    help="batched workload instead: many uneven graphs in one lp_predict_multi "
+                         "call (default and autotuned knobs) vs one lp_predict call per graph")
+    ap.add_argument("--graphs", type=int, default=512, help="--multi: number of graphs")
+    ap.add_argument("--n-max", type=int, default=1_000_000, help="--multi: largest graph size")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -153,6 +158,9 @@ def main():
         return
     if args.sweep:
         sweep(args, lp, synth, torch)
+        return
+    if args.multi:
+        multi(args, lp, synth, torch)
         return
 
     t0 = time.time()
@@ -387,6 +395,113 @@ def serve(args, lp, synth, torch):
                                   f"arrivals, 1-4096 sources per request (log-uniform, "
                                   f"degree-biased); DLH {measure} L={L}, top-{kq} per source",
                       "vertices": gr.n, "edges": gr.m}}
+    print(json.dumps(res), flush=True)
+
+
+def multi(args, lp, synth, torch):
+    """Batched workload: --graphs independent Chung-Lu graphs of uneven size
+    (vertices log-uniform in [1000, --n-max], mean degree uniform in [8, 32],
+    exponent 2.3, graph i seeded 1000 + i, sizes drawn with seed 5), used as
+    observed graphs (no holdout); graph i predicts k_i = m_i // 10 edges by
+    DLH Jaccard (hub limit --hub).  Times one lp_predict_multi call over the
+    disjoint union (default knobs, then the knobs the autotuner picks)
+    against one lp_predict call per graph with each graph resident on its own.
+    Every timed call returns after its device work; the host clock brackets
+    it, so launch and host overheads count on both sides."""
+    from paper_2401_11415_amd import tune
+    t0 = time.time()
+    graphs = synth.chung_lu_batch(
+        args.graphs, 1000, args.n_max, seed=5,
+        progress=lambda i: (i + 1) % 64 == 0 and log(f"generated {i + 1}/{args.graphs} graphs "
+                                                     f"({time.time() - t0:.1f}s)"))
+    ks = np.array([gr.m // 10 for gr in graphs], dtype=np.int64)
+    union, vstart = synth.disjoint_union(graphs)
+    log(f"union: n={union.n} m={union.m} sum k={int(ks.sum())} ({time.time() - t0:.1f}s)")
+    torch.cuda.set_device(0)
+    L, measure = args.hub, args.measure.upper()
+    g = lp.Graph(union.offsets, union.indices)
+    n_union, m_union = union.n, union.m
+    del union
+
+    def run():
+        out = lp.predict_multi(g, vstart, ks, measure, L)
+        torch.cuda.synchronize()
+        return out
+
+    def timed(steps):
+        ts = []
+        for _ in range(steps):
+            t = time.perf_counter()
+            out = run()
+            ts.append((time.perf_counter() - t) * 1e3)
+        return float(np.median(ts)), float(np.mean(ts)), out
+
+    for i in range(args.warmup):
+        run()
+        log(f"multi warmup {i}: {lp.last_stats(g)['ms_total']:.3f} ms device")
+    med_default, mean_default, out = timed(args.steps)
+    stats_default = lp.last_stats(g)
+    k_out = sum(int(a.shape[0]) for a, _, _ in out)
+    log(f"one call, default knobs: median {med_default:.3f} ms")
+    tuned = tune.autotune(g, run, repeats=3, log=log)
+    for i in range(args.warmup):
+        run()
+    med_tuned, mean_tuned, out = timed(args.steps)
+    stats_tuned = lp.last_stats(g)
+    log(f"one call, tuned knobs {tuned['setting']}: median {med_tuned:.3f} ms")
+    g.close()
+
+    per_graph_ms = []
+    for i, gr in enumerate(graphs):
+        gi = lp.Graph(gr.offsets, gr.indices)
+        k = int(ks[i])
+        dev = torch.device("cuda", 0)
+        buf = (torch.empty(max(k, 1), dtype=torch.int32, device=dev),
+               torch.empty(max(k, 1), dtype=torch.int32, device=dev),
+               torch.empty(max(k, 1), dtype=torch.float32, device=dev))
+        for _ in range(max(1, args.warmup)):
+            lp.predict(gi, measure, L, k, out=buf)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(args.steps):
+            t = time.perf_counter()
+            lp.predict(gi, measure, L, k, out=buf)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t) * 1e3)
+        per_graph_ms.append(float(np.median(ts)))
+        gi.close()
+        if (i + 1) % 64 == 0:
+            log(f"per-graph calls: {i + 1}/{len(graphs)} graphs, {sum(per_graph_ms):.1f} ms so far")
+    loop_ms = float(sum(per_graph_ms))
+
+    def buckets(st):
+        return {name: {"sources": b["sources"], "launches": b["launches"], "wedges": b["wedges"],
+                       "ms": b["ms"]}
+                for name, b in st["launches"].items() if b["launches"]}
+
+    res = {
+        "metric": f"predicted edges/s (DLH, {'Jaccard' if measure == 'JC' else measure}), "
+                  f"{args.graphs} graphs per call",
+        "value": k_out / (med_tuned * 1e-3), "unit": "edges/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": med_tuned,
+        "higher_is_better": True, "dtype": "u32 counts, f64 scores", "data": "synthetic",
+        "ms_one_call_default_knobs": med_default,
+        "ms_one_call_per_graph": loop_ms,
+        "speedup_vs_one_call_per_graph": loop_ms / med_tuned,
+        "speedup_of_tuning": med_default / med_tuned,
+        "tuned_knobs": tuned["setting"], "tuning_trials": len(tuned["trials"]),
+        "device": {name: {f: st[f] for f in ("ms_total", "ms_plan", "ms_accumulate", "ms_select",
+                                             "wedges", "appended", "retries")}
+                   for name, st in (("default", stats_default), ("tuned", stats_tuned))},
+        "buckets_tuned": buckets(stats_tuned),
+        "per_graph_ms": {"min": min(per_graph_ms), "median": float(np.median(per_graph_ms)),
+                         "max": max(per_graph_ms)},
+        "config": {"workload": f"{args.graphs} Chung-Lu graphs, 1000-{args.n_max} vertices "
+                               f"(log-uniform), mean degree 8-32, exponent 2.3, graph i seeded "
+                               f"1000 + i; DLH {measure}, hub limit {L}, k_i = m_i / 10",
+                   "vertices": n_union, "edges": m_union, "k": int(ks.sum()), "k_out": k_out,
+                   "graphs": args.graphs},
+    }
     print(json.dumps(res), flush=True)
 
 

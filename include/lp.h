@@ -138,16 +138,33 @@ lp_status lp_query(lp_graph *g, const int32_t *sources, int64_t n_sources, lp_me
 lp_status lp_fingerprint(lp_graph *g, int64_t hub_limit, uint64_t *out, void *hip_stream);
 
 /* Tuning knobs of the scheduler; 0 keeps the default.  Values apply to later
- * calls on g.  lds_wedge_cap caps the per-source wedge count handled with an
- * LDS table (larger sources use the global-memory table); global_slots caps
- * the global table size per workgroup (larger sources run in several hash
- * partitions); sample_budget is the wedge budget of the sampling pass that
- * sets the top-k filter threshold (0 disables sampling). */
+ * calls on g (host pointer; copied).
+ *   lds_wedge_cap: T = U + d_a (wedges plus degree of a source) above which a
+ *     source uses the global-memory accumulator instead of an LDS table
+ *     (default 65536);
+ *   global_slots: workgroups of the global-memory path, each holding a dense
+ *     accumulator of 12 bytes per vertex (default: one per compute unit; the
+ *     pool is also kept within a quarter of the device memory);
+ *   sample_budget: wedge budget of the sampling pass that sets the top-k
+ *     filter threshold (default 2^22; a negative value disables sampling);
+ *   bucket_max[b]: upper bound of T for the scheduling buckets tiny, small,
+ *     mid1, mid2, mid3 (defaults 32, 256, 1024, 2048, 4096, the table sizes
+ *     the kernels are built for; a value may only lower its default, moving
+ *     sources to the next bucket);
+ *   batch_sources[2]: sources sharing one 256-lane workgroup in the tiny
+ *     bucket (48 or 32; 48 needs fewer than 2^26 vertices, else 32 is used)
+ *     and in the small bucket (8 or 4).
+ * Results do not depend on the knobs.  Errors: LP_ERR_INVALID_ARGUMENT for
+ * NULL arguments, negative lds_wedge_cap or global_slots, a bucket_max
+ * outside [0, its default] or another batch_sources value; g then keeps its
+ * previous knobs. */
 typedef struct {
   int64_t lds_wedge_cap;
   int64_t global_slots;
   int64_t sample_budget;
-  int64_t reserved[5];
+  int64_t bucket_max[5];
+  int64_t batch_sources[2];
+  int64_t reserved[2];
 } lp_tuning;
 lp_status lp_set_tuning(lp_graph *g, const lp_tuning *t);
 

@@ -19,7 +19,8 @@ import os
 import numpy as np
 
 __all__ = ["MEASURES", "HUB_NONE", "LpError", "Graph", "predict", "predict_multi", "query",
-           "fingerprint", "set_tuning", "last_stats", "Server", "library_path", "load"]
+           "fingerprint", "set_tuning", "last_stats", "Server", "library_path", "load",
+           "BUCKET_MAX_DEFAULT"]
 
 MEASURES = ("CN", "JC", "SI", "SC", "HP", "HD", "LHN", "AA", "RA")
 HUB_NONE = (1 << 63) - 1  # L_H = infinity: IBase
@@ -42,7 +43,8 @@ class LpError(RuntimeError):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("lds_wedge_cap", ctypes.c_int64), ("global_slots", ctypes.c_int64),
-                ("sample_budget", ctypes.c_int64), ("reserved", ctypes.c_int64 * 5)]
+                ("sample_budget", ctypes.c_int64), ("bucket_max", ctypes.c_int64 * 5),
+                ("batch_sources", ctypes.c_int64 * 2), ("reserved", ctypes.c_int64 * 2)]
 
 
 class _BucketStats(ctypes.Structure):
@@ -277,8 +279,22 @@ def fingerprint(g: Graph, hub_limit, stream=None):
     return tuple(int(x) for x in out)
 
 
-def set_tuning(g: Graph, lds_wedge_cap: int = 0, global_slots: int = 0, sample_budget: int = 0):
-    t = _Tuning(lds_wedge_cap, global_slots, sample_budget)
+# default upper bounds of T = U + d_a for the buckets tiny .. mid3
+BUCKET_MAX_DEFAULT = (32, 256, 1024, 2048, 4096)
+
+
+def set_tuning(g: Graph, lds_wedge_cap: int = 0, global_slots: int = 0, sample_budget: int = 0,
+               bucket_max=None, tiny_batch: int = 0, small_batch: int = 0):
+    """Scheduler knobs of g (lp_set_tuning); 0 keeps a knob's default.
+    bucket_max: up to five T bounds for tiny .. mid3, each at most its
+    default (BUCKET_MAX_DEFAULT); tiny_batch / small_batch: sources per
+    workgroup in the tiny (48 or 32) and small (8 or 4) buckets."""
+    bm = list(bucket_max or [])
+    if len(bm) > 5:
+        raise ValueError("bucket_max holds at most 5 bounds")
+    bm += [0] * (5 - len(bm))
+    t = _Tuning(lds_wedge_cap, global_slots, sample_budget, (ctypes.c_int64 * 5)(*bm),
+                (ctypes.c_int64 * 2)(tiny_batch, small_batch))
     _check(load().lp_set_tuning(g.handle, ctypes.byref(t)))
 
 

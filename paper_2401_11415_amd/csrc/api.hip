@@ -205,6 +205,12 @@ lp_status lp_set_tuning(lp_graph* g, const lp_tuning* t) {
   if (!g || !t) return set_error(LP_ERR_INVALID_ARGUMENT, "NULL argument");
   if (t->lds_wedge_cap < 0 || t->global_slots < 0)
     return set_error(LP_ERR_INVALID_ARGUMENT, "tuning values must be >= 0");
+  for (int b = 0; b < 5; b++)
+    if (t->bucket_max[b] < 0 || t->bucket_max[b] > lp::kBucketMaxDefault[b])
+      return set_error(LP_ERR_INVALID_ARGUMENT, "bucket_max[b] must lie in [0, its default]");
+  if ((t->batch_sources[0] != 0 && t->batch_sources[0] != 48 && t->batch_sources[0] != 32) ||
+      (t->batch_sources[1] != 0 && t->batch_sources[1] != 8 && t->batch_sources[1] != 4))
+    return set_error(LP_ERR_INVALID_ARGUMENT, "batch_sources: tiny 48 or 32, small 8 or 4");
   g->tuning = *t;
   return LP_OK;
 }

@@ -151,5 +151,11 @@ lp_status radix_sort(const SortSpec& spec, int64_t n, DevBuf tmp[4], DevBuf& cou
                      DevBuf& scan_tmp, hipStream_t st);
 
 int num_cus();
+// total memory of the current device in bytes (cached on first use)
+size_t device_memory();
+
+// default upper bounds of T = U + d_a for the buckets tiny .. mid3: the
+// table sizes the kernels are built for (a tuning may only lower them)
+constexpr int64_t kBucketMaxDefault[5] = {32, 256, 1024, 2048, 4096};
 
 }  // namespace lp

@@ -77,14 +77,19 @@ __device__ inline uint32_t lower_bound_dev(const uint32_t* __restrict__ a, uint3
 
 // Bucket of a source with U wedges and T = U + (first-order neighbours to
 // exclude) table entries at most; sources without wedges have no candidates.
-__device__ inline int bucket_of(uint32_t U, uint32_t T, uint32_t lds_cap) {
+// Upper bounds of T = U + d_a per bucket: tiny .. mid3, then the LDS cap
+// (larger sources take the global path).  The defaults are the table sizes
+// the kernels are built for; a tuning may only lower the first five.
+struct BucketCuts {
+  uint32_t t[kBucketHuge];
+};
+
+__device__ inline int bucket_of(uint32_t U, uint32_t T, const BucketCuts& cut) {
   if (U == 0) return -1;
-  if (T > lds_cap) return kBucketHuge;
-  if (T <= 32) return kBucketTiny;
-  if (T <= 256) return kBucketSmall;
-  if (T <= 1024) return kBucketMid1;
-  if (T <= 2048) return kBucketMid2;
-  if (T <= 4096) return kBucketMid3;
+  if (T > cut.t[kBucketLarge]) return kBucketHuge;
+#pragma unroll
+  for (int b = kBucketTiny; b < kBucketLarge; b++)
+    if (T <= cut.t[b]) return b;
   return kBucketLarge;
 }
 
@@ -92,7 +97,7 @@ constexpr int kPlanItems = 16;  // sources per thread of the plan kernel
 
 // Bucket a tile of 256 * kPlanItems sources with one global atomic per
 // (workgroup, bucket); records land in lists[bucket * stride + position].
-__global__ __launch_bounds__(256) void plan_kernel(GView g, uint32_t hub_start, uint32_t lds_cap,
+__global__ __launch_bounds__(256) void plan_kernel(GView g, uint32_t hub_start, BucketCuts cuts,
                                                    SrcRec* __restrict__ lists,
                                                    PlanOut* __restrict__ out) {
   __shared__ uint32_t wtot[kBuckets][4];
@@ -116,7 +121,7 @@ __global__ __launch_bounds__(256) void plan_kernel(GView g, uint32_t hub_start, 
         const uint64_t t = (uint64_t)U + (g.off[a + 1] - g.off[a] - g.below[a]);
         T = t > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)t;
       }
-      const int b = bucket_of(U, T, lds_cap);
+      const int b = bucket_of(U, T, cuts);
       if (b >= 0) {
         bk[j] = (uint8_t)b;
         nb[b]++;
@@ -192,7 +197,7 @@ __global__ __launch_bounds__(256) void plan_kernel(GView g, uint32_t hub_start, 
 // query: map sources to new ids, explored prefix of the row and an upper
 // bound of the wedges (all of Gamma_b for explored b), one workgroup per query
 __global__ __launch_bounds__(256) void query_plan_kernel(GView g, uint32_t hub_start,
-                                                         uint32_t lds_cap,
+                                                         BucketCuts cuts,
                                                          const int32_t* __restrict__ src,
                                                          const uint32_t* __restrict__ rank,
                                                          uint32_t nq, SrcRec* __restrict__ lists,
@@ -214,7 +219,7 @@ __global__ __launch_bounds__(256) void query_plan_kernel(GView g, uint32_t hub_s
       const unsigned long long tot = part[0] + part[1] + part[2] + part[3];
       const uint32_t U = tot > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)tot;
       const uint64_t t = (uint64_t)U + (e1 - e0);
-      const int b = bucket_of(U, t > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)t, lds_cap);
+      const int b = bucket_of(U, t > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)t, cuts);
       if (b >= 0) {
         SrcRec r;
         r.a = s;
@@ -590,11 +595,25 @@ __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, WorkList 
 // workgroup takes B consecutive sources of a bucket and accumulates all their
 // wedges into one table keyed by (position in the batch, c), so the batch pays
 // the dependent global round trips (records, arcs, wedges, first-order rows)
-// once instead of once per source.  Needs ids below 2^24 and B <= 64.
+// once instead of once per source.  A key packs the position in the batch
+// above the id bits, so B bounds the vertex count (BatchKey::kMaxN).
 // ---------------------------------------------------------------------------
 
-constexpr uint32_t kBatchIdBits = 24;
-constexpr uint32_t kBatchIdMask = (1u << kBatchIdBits) - 1;
+template <int B>
+struct BatchKey {
+  static_assert(B >= 1 && B <= 64, "batch fits in one wave");
+  static constexpr int kSrcBits = B <= 2 ? 1 : B <= 4 ? 2 : B <= 8 ? 3 : B <= 16 ? 4 : B <= 32 ? 5 : 6;
+  static constexpr int kIdBits = 32 - kSrcBits;
+  static constexpr uint32_t kIdMask = (1u << kIdBits) - 1;
+  // largest vertex count whose keys all stay below the empty key
+  static constexpr uint64_t kMaxN =
+      (1ull << kIdBits) < 0xFFFFFFFFull - ((uint64_t)(B - 1) << kIdBits)
+          ? (1ull << kIdBits)
+          : 0xFFFFFFFFull - ((uint64_t)(B - 1) << kIdBits);
+};
+static_assert(BatchKey<48>::kMaxN == (1ull << 26) && BatchKey<32>::kMaxN == (1ull << 27) - 1 &&
+                  BatchKey<2>::kMaxN == (1ull << 31) - 1,
+              "batch key ranges");
 
 template <int WGS, int B, int SLOTS, bool kW, int STAGE>
 struct BatchTab {
@@ -640,7 +659,7 @@ __device__ inline int batch_search(const uint32_t* off, uint32_t q) {
 
 template <int WGS, int B, int SLOTS, bool kW, int STAGE, bool kSampled>
 __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkList wl) {
-  static_assert(B <= 64 && B >= 1, "batch fits in one wave");
+  using KB = BatchKey<B>;
   constexpr int NW = WGS / 64;
   __shared__ BatchTab<WGS, B, SLOTS, kW, STAGE> L;
   const int tid = threadIdx.x;
@@ -718,7 +737,7 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
     if ((uint32_t)(WGS - 1 - tid) < NX) {
       const uint32_t xq = (uint32_t)(WGS - 1 - tid);
       const uint32_t xi = (uint32_t)batch_search<B>(L.xoff, xq);
-      xkey = (xi << kBatchIdBits) | g.adj[L.rec[xi].x0 + (xq - L.xoff[xi])];
+      xkey = (xi << KB::kIdBits) | g.adj[L.rec[xi].x0 + (xq - L.xoff[xi])];
     }
     if (S > clean) {
       for (uint32_t t = clean + tid; t < S; t += WGS) {
@@ -760,7 +779,7 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
                               const bool (&v)[kWin]) {
 #pragma unroll
         for (int u = 0; u < kWin; u++) {
-          const uint32_t k = (L.srcof[arc[u]] << kBatchIdBits) | (c[u] & kBatchIdMask);
+          const uint32_t k = (L.srcof[arc[u]] << KB::kIdBits) | (c[u] & KB::kIdMask);
           const uint64_t w = kW ? L.w[arc[u]] : kSlotOne;
           const bool ok = tab_insert<kW>(L.tab, L.keys, L.vals, S, v[u] ? k : kEmpty32, key_slot(k, S), w, RT);
           full = full | !ok;
@@ -778,7 +797,7 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
       uint32_t key = x0 == 0 ? xkey : kEmpty32;
       if (x0 != 0 && x < NX) {
         const uint32_t i = (uint32_t)batch_search<B>(L.xoff, x);
-        key = (i << kBatchIdBits) | g.adj[L.rec[i].x0 + (x - L.xoff[i])];
+        key = (i << KB::kIdBits) | g.adj[L.rec[i].x0 + (x - L.xoff[i])];
       }
       const bool ok = tab_insert<kW>(L.tab, L.keys, L.vals, S, key, key_slot(key, S),
                                      kW ? kBlocked64W : kBlocked64, RT);
@@ -819,7 +838,7 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
         }
         ok = t < S && key != kEmpty32 && (wsum >> 63) == 0;
         wk.v[4] += ok ? 1u : 0u;
-        ok = ok && wsum >= L.wmin[ok ? key >> kBatchIdBits : 0u];
+        ok = ok && wsum >= L.wmin[ok ? key >> KB::kIdBits : 0u];
       } else {
         const uint64_t v = L.tab[tc];
         if (t < S) L.tab[t] = kSlotEmpty;
@@ -828,12 +847,12 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
         ok = t < S && key != kEmpty32 && (h & kBlocked) == 0;
         wk.v[4] += ok ? 1u : 0u;
       }
-      const uint32_t i = ok ? key >> kBatchIdBits : 0u;
+      const uint32_t i = ok ? key >> KB::kIdBits : 0u;
       if (!kW) {
-        const uint32_t c = key & kBatchIdMask;
+        const uint32_t c = key & KB::kIdMask;
         ok = ok && h >= L.hmin[i] && !(h == 1 && c >= L.cut[i][0]) && !(h == 2 && c >= L.cut[i][1]);
       }
-      stage_add<false, kW>(E, g, SG, ok, key & kBatchIdMask, h, wsum, L.rec[i].key, L.rec[i].da, fa);
+      stage_add<false, kW>(E, g, SG, ok, key & KB::kIdMask, h, wsum, L.rec[i].key, L.rec[i].da, fa);
     }
     __syncthreads();
   }
@@ -1250,14 +1269,17 @@ static unsigned grid_for(uint64_t items, int per_block, unsigned cap_blocks) {
 }
 
 struct AccConfig {
-  uint32_t lds_cap;   // wedges above which a source uses the global path
+  BucketCuts cuts;    // bucket bounds; cuts.t[kBucketLarge]: T above which a source uses the global path
   unsigned spa_wgs;   // workgroups (dense accumulators) of the global path
 };
 
 static AccConfig acc_config(const lp_graph* g) {
   AccConfig c;
-  c.lds_cap = g->tuning.lds_wedge_cap > 0 ? (uint32_t)std::min<int64_t>(g->tuning.lds_wedge_cap, 1u << 30)
-                                          : 65536u;
+  for (int b = kBucketTiny; b < kBucketLarge; b++)
+    c.cuts.t[b] = (uint32_t)(g->tuning.bucket_max[b] > 0 ? g->tuning.bucket_max[b] : kBucketMaxDefault[b]);
+  c.cuts.t[kBucketLarge] = g->tuning.lds_wedge_cap > 0
+                               ? (uint32_t)std::min<int64_t>(g->tuning.lds_wedge_cap, 1u << 30)
+                               : 65536u;
   c.spa_wgs = (unsigned)(g->tuning.global_slots > 0 ? g->tuning.global_slots : num_cus());
   return c;
 }
@@ -1268,24 +1290,35 @@ static lp_status launch_bucket(lp_graph* g, int bucket, const GView& gv, const E
                                WorkList wl, uint64_t nitems, hipStream_t st) {
   if (nitems == 0) return LP_OK;
   const unsigned cus = (unsigned)num_cus();
-  if (!kQuery && g->n <= (int64_t)kBatchIdMask + 1 && bucket <= kBucketMid1) {
-    // batches: Tiny 48 sources (<= 1536 wedges), Small 8 (<= 2048), Mid1 2 (<= 2048)
-    switch (bucket) {
-      case kBucketTiny:
-        hipLaunchKernelGGL((acc_batch_kernel<256, 48, 3072, kW, 64, kSampled>),
-                           dim3(grid_for((nitems + 47) / 48, 1, cus * 8)), dim3(256), 0, st, gv, E, wl);
-        break;
-      case kBucketSmall:
-        hipLaunchKernelGGL((acc_batch_kernel<256, 8, 3072, kW, 64, kSampled>),
-                           dim3(grid_for((nitems + 7) / 8, 1, cus * 8)), dim3(256), 0, st, gv, E, wl);
-        break;
-      default:
-        hipLaunchKernelGGL((acc_batch_kernel<256, 2, 3072, kW, 64, kSampled>),
-                           dim3(grid_for((nitems + 1) / 2, 1, cus * 8)), dim3(256), 0, st, gv, E, wl);
-        break;
+  const uint64_t n = (uint64_t)g->n;
+  if (!kQuery && bucket <= kBucketMid1) {
+    // batches: Tiny 48 sources (<= 1536 wedges; 32 above 2^26 vertices),
+    // Small 8 (<= 2048), Mid1 2 (<= 2048)
+    // (the tuning may ask for 32 tiny or 4 small sources per workgroup)
+    const bool tiny32 = g->tuning.batch_sources[0] == 32;
+    const bool small4 = g->tuning.batch_sources[1] == 4;
+    bool done = true;
+    if (bucket == kBucketTiny && !tiny32 && n <= BatchKey<48>::kMaxN)
+      hipLaunchKernelGGL((acc_batch_kernel<256, 48, 3072, kW, 64, kSampled>),
+                         dim3(grid_for((nitems + 47) / 48, 1, cus * 8)), dim3(256), 0, st, gv, E, wl);
+    else if (bucket == kBucketTiny && n <= BatchKey<32>::kMaxN)
+      hipLaunchKernelGGL((acc_batch_kernel<256, 32, 3072, kW, 64, kSampled>),
+                         dim3(grid_for((nitems + 31) / 32, 1, cus * 8)), dim3(256), 0, st, gv, E, wl);
+    else if (bucket == kBucketSmall && !small4 && n <= BatchKey<8>::kMaxN)
+      hipLaunchKernelGGL((acc_batch_kernel<256, 8, 3072, kW, 64, kSampled>),
+                         dim3(grid_for((nitems + 7) / 8, 1, cus * 8)), dim3(256), 0, st, gv, E, wl);
+    else if (bucket == kBucketSmall && n <= BatchKey<4>::kMaxN)
+      hipLaunchKernelGGL((acc_batch_kernel<256, 4, 3072, kW, 64, kSampled>),
+                         dim3(grid_for((nitems + 3) / 4, 1, cus * 8)), dim3(256), 0, st, gv, E, wl);
+    else if (bucket == kBucketMid1 && n <= BatchKey<2>::kMaxN)
+      hipLaunchKernelGGL((acc_batch_kernel<256, 2, 3072, kW, 64, kSampled>),
+                         dim3(grid_for((nitems + 1) / 2, 1, cus * 8)), dim3(256), 0, st, gv, E, wl);
+    else
+      done = false;
+    if (done) {
+      LP_HIP(hipGetLastError());
+      return LP_OK;
     }
-    LP_HIP(hipGetLastError());
-    return LP_OK;
   }
   switch (bucket) {
     case kBucketTiny:
@@ -1327,8 +1360,9 @@ static lp_status launch_spa(lp_graph* g, Workspace& w, const GView& gv, const Em
   const size_t n = (size_t)g->n;
   // pool: one slab of 8n accumulator bytes per workgroup, then as many key
   // lists of 4n; it grows to the launch's workgroup count (at most
-  // cfg.spa_wgs) and never shrinks
-  const unsigned slabs = (unsigned)std::min<uint64_t>(cfg.spa_wgs, nitems);
+  // cfg.spa_wgs, and at most a quarter of the device memory) and never shrinks
+  const uint64_t mem_cap = std::max<uint64_t>(1, device_memory() / 4 / (n * 12 + 1));
+  const unsigned slabs = (unsigned)std::min<uint64_t>(std::min<uint64_t>(cfg.spa_wgs, nitems), mem_cap);
   if (w.global_slabs < slabs) {
     w.global_tab.release();
     w.global_slabs = 0;
@@ -1607,7 +1641,7 @@ static lp_status run_plan(lp_graph* g, int64_t L, PlanResult* pr, hipStream_t st
   const AccConfig cfg = acc_config(g);
   if (n > 0) {
     hipLaunchKernelGGL(plan_kernel, dim3(grid_for(n, 256 * kPlanItems, 0x7FFFFFFF)), dim3(256), 0, st,
-                       view_of(g), pr->hub, cfg.lds_cap, w.lists.as<SrcRec>(), d_out);
+                       view_of(g), pr->hub, cfg.cuts, w.lists.as<SrcRec>(), d_out);
     LP_HIP(hipGetLastError());
   }
   PlanOut* h = w.host_stats.as<PlanOut>();
@@ -2305,7 +2339,7 @@ lp_status run_query(lp_graph* g, Workspace& w, const int32_t* sources, int64_t n
   const AccConfig cfg = acc_config(g);
   const GView gv = view_of(g);
   hipLaunchKernelGGL(query_plan_kernel, dim3(grid_for(Q, 1, 65536)), dim3(256), 0, st, gv, hub,
-                     cfg.lds_cap, w.q_src.as<int32_t>(), g->rank, (uint32_t)Q, qlists, d_out);
+                     cfg.cuts, w.q_src.as<int32_t>(), g->rank, (uint32_t)Q, qlists, d_out);
   LP_HIP(hipGetLastError());
   PlanOut* hp = w.host_stats.as<PlanOut>();
   LP_HIP(hipMemcpyAsync(hp, d_out, sizeof(PlanOut), hipMemcpyDeviceToHost, st));

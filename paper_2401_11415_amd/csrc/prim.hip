@@ -86,6 +86,15 @@ int num_cus() {
   return cached;
 }
 
+size_t device_memory() {
+  static size_t cached = 0;
+  if (!cached) {
+    size_t free_b = 0, total_b = 0;
+    cached = hipMemGetInfo(&free_b, &total_b) == hipSuccess && total_b > 0 ? total_b : (size_t)64 << 30;
+  }
+  return cached;
+}
+
 // ---------------------------------------------------------------------------
 // Block scan helpers (256 threads = 4 waves of 64)
 // ---------------------------------------------------------------------------

@@ -220,11 +220,17 @@ def disjoint_union(graphs):
 
 
 def chung_lu_batch(count: int, n_min: int, n_max: int, seed: int, gamma: float = 2.3,
-                   d_min: float = 8.0, d_max: float = 32.0):
+                   d_min: float = 8.0, d_max: float = 32.0, progress=None):
     """`count` Chung-Lu graphs of uneven size: n log-uniform in [n_min, n_max],
     mean degree uniform in [d_min, d_max], exponent gamma, graph i seeded
-    1000 + i (sizes and degrees drawn from `seed`)."""
+    1000 + i (sizes and degrees drawn from `seed`).  progress(i) is called
+    after each graph when given."""
     rng = np.random.default_rng(seed)
     ns = np.exp(rng.uniform(np.log(n_min), np.log(n_max), count)).astype(np.int64)
     ds = rng.uniform(d_min, d_max, count)
-    return [chung_lu(int(n), float(d), gamma, 1000 + i) for i, (n, d) in enumerate(zip(ns, ds))]
+    out = []
+    for i, (n, d) in enumerate(zip(ns, ds)):
+        out.append(chung_lu(int(n), float(d), gamma, 1000 + i))
+        if progress:
+            progress(i)
+    return out

@@ -540,3 +540,102 @@ def test_predict_multi_invalid(lp):
             cut = int(vs[1]) + int(np.argmax(gs[1].degrees())) + 1  # a hub of graph 1 left behind
             lp.predict_multi(g, [0, cut, u.n], [5, 5], "JC", 256)
         assert e.value.name == "LP_ERR_INVALID_GRAPH"
+
+
+BUCKET_SETTINGS = [
+    {"bucket_max": (16, 64, 512, 1536, 3072)},
+    {"bucket_max": (32, 33, 34, 35, 36)},
+    {"bucket_max": (1, 1, 1, 1, 1)},  # nearly every source in the 1024-lane kernel
+    {"bucket_max": (1, 1, 1, 1, 1), "lds_wedge_cap": 200},
+    {"tiny_batch": 32, "small_batch": 4},
+    {"bucket_max": (16, 128), "tiny_batch": 32, "small_batch": 4, "lds_wedge_cap": 3000},
+]
+
+
+@pytest.mark.parametrize("which", range(len(BUCKET_SETTINGS)))
+def test_bucket_bounds_same_result(lp, config1, which):
+    """The bucket bounds only move sources between kernels: lists, digests,
+    queries and the several-graph call are bit-identical to the defaults."""
+    gr, k = config1
+    setting = BUCKET_SETTINGS[which]
+    say(f"[gpu] bucket bounds {setting}")
+    src = synth.sample_sources(gr, 40, seed=8, top=4)
+    gs = synth.chung_lu_batch(8, 60, 3000, seed=13)
+    u, vs = synth.disjoint_union(gs)
+    ks = [gr_i.m // 10 for gr_i in gs]
+    with lp.Graph(gr.offsets, gr.indices) as g, lp.Graph(u.offsets, u.indices) as gu:
+        base = {}
+        for m in ("JC", "AA", "CN"):
+            base[m] = (run_predict(lp, g, m, 256, k), lp.fingerprint(g, 256),
+                       tuple(to_np(x) for x in lp.query(g, src, m, 256, 10)))
+        base_multi = [tuple(to_np(x) for x in r) for r in lp.predict_multi(gu, vs, ks, "JC", 256)]
+        lp.set_tuning(g, **setting)
+        lp.set_tuning(gu, **setting)
+        for m in ("JC", "AA", "CN"):
+            got = run_predict(lp, g, m, 256, k)
+            st = lp.last_stats(g)
+            for x, y in zip(got, base[m][0]):
+                assert np.array_equal(x, y), f"{setting} {m}"
+            assert lp.fingerprint(g, 256) == base[m][1]
+            q = tuple(to_np(x) for x in lp.query(g, src, m, 256, 10))
+            for x, y in zip(q, base[m][2]):
+                assert np.array_equal(x, y), f"query {setting} {m}"
+        if len(setting.get("bucket_max", ())) == 5 and setting["bucket_max"][4] == 1:
+            nb = st["buckets"]
+            assert nb["small"] == nb["mid1"] == nb["mid2"] == nb["mid3"] == 0
+            assert nb["large"] + nb["global"] > nb["tiny"]
+        for r, b in zip(lp.predict_multi(gu, vs, ks, "JC", 256), base_multi):
+            for x, y in zip((to_np(x) for x in r), b):
+                assert np.array_equal(x, y), f"multi {setting}"
+        ref = oracle.predict(gr, 256, "JC", k)
+        assert_same_list(run_predict(lp, g, "JC", 256, k), ref, "JC", f"oracle {setting}")
+
+
+def test_tuning_invalid(lp, config1):
+    gr, k = config1
+    say("[gpu] tuning invalid")
+    with lp.Graph(gr.offsets, gr.indices) as g:
+        before = run_predict(lp, g, "JC", 256, k)
+        lp.set_tuning(g, bucket_max=(8, 8, 8, 8, 8))
+        for bad in ((33, 0, 0, 0, 0), (0, 0, 0, 0, 4097), (-1, 0, 0, 0, 0)):
+            with pytest.raises(lp.LpError):
+                lp.set_tuning(g, bucket_max=bad)
+        with pytest.raises(lp.LpError):
+            lp.set_tuning(g, lds_wedge_cap=-5)
+        with pytest.raises(lp.LpError):
+            lp.set_tuning(g, tiny_batch=40)
+        with pytest.raises(lp.LpError):
+            lp.set_tuning(g, small_batch=16)
+        with pytest.raises(ValueError):
+            lp.set_tuning(g, bucket_max=(1, 1, 1, 1, 1, 1))
+        run_predict(lp, g, "JC", 256, k)
+        assert lp.last_stats(g)["buckets"]["small"] == 0  # the valid knobs stayed
+        after = run_predict(lp, g, "JC", 256, k)
+        for x, y in zip(before, after):
+            assert np.array_equal(x, y)
+
+
+def test_autotune_keeps_results(lp):
+    """The autotuner over a small space on a several-graph call: it leaves the
+    graph at the best setting it measured, and the lists do not change."""
+    from paper_2401_11415_amd import tune
+    import torch
+    gs = synth.chung_lu_batch(16, 100, 20000, seed=21)
+    u, vs = synth.disjoint_union(gs)
+    ks = [gr_i.m // 10 for gr_i in gs]
+    say(f"[gpu] autotune n={u.n}")
+    with lp.Graph(u.offsets, u.indices) as g:
+        base = [tuple(to_np(x) for x in r) for r in lp.predict_multi(g, vs, ks, "JC", 256)]
+
+        def run():
+            lp.predict_multi(g, vs, ks, "JC", 256)
+            torch.cuda.synchronize()
+
+        space = {"bucket_max0": (32, 16), "tiny_batch": (48, 32), "lds_wedge_cap": (65536, 512)}
+        res = tune.autotune(g, run, space=space, repeats=1)
+        assert len(res["trials"]) == 4
+        assert res["ms"] <= res["default_ms"]
+        assert set(res["setting"]) == set(space)
+        for r, b in zip(lp.predict_multi(g, vs, ks, "JC", 256), base):
+            for x, y in zip((to_np(x) for x in r), b):
+                assert np.array_equal(x, y)
