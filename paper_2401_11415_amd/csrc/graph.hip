@@ -427,9 +427,11 @@ void release_workspace(Workspace& w) {
                    &w.cand_c, &w.tmp_s[0], &w.tmp_s[1], &w.tmp_a[0], &w.tmp_a[1], &w.tmp_c[0],
                    &w.tmp_c[1], &w.hist, &w.sel_state, &w.sort_tmp[0], &w.sort_tmp[1],
                    &w.sort_tmp[2], &w.sort_tmp[3], &w.sort_counts, &w.scan_tmp, &w.global_tab, &w.q_src,
-                   &w.q_cnt, &w.q_wedges, &w.q_rows, &w.q_out, &w.m_graph, &w.m_gid};
+                   &w.q_cnt, &w.q_wedges, &w.q_rows, &w.q_out, &w.m_graph, &w.m_gid,
+                   &w.m_lists};
   for (auto b : all) b->release();
   w.host_stats.release();
+  w.m_checked.clear();
   for (int i = 0; i < Workspace::kSide; i++) {
     if (w.side[i]) (void)hipStreamDestroy(w.side[i]);
     if (w.join[i]) (void)hipEventDestroy(w.join[i]);

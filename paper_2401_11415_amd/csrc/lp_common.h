@@ -79,8 +79,10 @@ struct Workspace {
   unsigned global_slabs = 0;  // accumulator slabs in global_tab
   // query
   DevBuf q_src, q_cnt, q_wedges, q_rows, q_out;
-  // several graphs at once: per-graph tables, candidate graph ids
-  DevBuf m_graph, m_gid;
+  // several graphs at once: per-graph tables, candidate graph ids, the
+  // bucket lists split into sample and rest
+  DevBuf m_graph, m_gid, m_lists;
+  std::vector<uint32_t> m_checked;  // graph boundaries already checked for joining edges
   HostBuf host_stats;
   // side streams for the concurrent launches of a sampling phase (default
   // priority), forked from and joined back to the caller's stream

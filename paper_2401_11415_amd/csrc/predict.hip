@@ -1450,7 +1450,7 @@ template <bool kW, bool kQuery>
 static lp_status run_phase(lp_graph* g, Workspace& w, const GView& gv, const Emit& E0,
                            const SrcRec* lists, uint64_t list_stride, const uint32_t* counts_host,
                            uint32_t stride, int phase, uint32_t* ovf_host_count, LaunchClock* clk,
-                           hipStream_t st) {
+                           hipStream_t st, const uint32_t* first = nullptr) {
   unsigned long long* work = work_counters(w);
   // The sampling phase launches every bucket with a few sources each: those
   // launches are latency bound and independent, so they run concurrently on
@@ -1471,7 +1471,7 @@ static lp_status run_phase(lp_graph* g, Workspace& w, const GView& gv, const Emi
   int turn = 0;
   // largest buckets first: their long-running workgroups start early
   for (int b = kBuckets - 1; b >= 0; b--) {
-    WorkList wl{lists + (uint64_t)b * list_stride, counts_host[b], stride, phase};
+    WorkList wl{lists + (uint64_t)b * list_stride + (first ? first[b] : 0u), counts_host[b], stride, phase};
     uint64_t items;
     if (phase == 0 || stride <= 1) items = phase == 2 ? 0 : counts_host[b];
     else {
@@ -1532,12 +1532,13 @@ template <bool kQuery>
 static lp_status run_phase_any(lp_graph* g, Workspace& w, const GView& gv, const Emit& E,
                                const SrcRec* lists, uint64_t list_stride,
                                const uint32_t* counts_host, uint32_t stride, int phase,
-                               uint32_t* ovf_host_count, LaunchClock* clk, hipStream_t st) {
+                               uint32_t* ovf_host_count, LaunchClock* clk, hipStream_t st,
+                               const uint32_t* first = nullptr) {
   if (E.measure == LP_AA || E.measure == LP_RA)
     return run_phase<true, kQuery>(g, w, gv, E, lists, list_stride, counts_host, stride, phase,
-                                   ovf_host_count, clk, st);
+                                   ovf_host_count, clk, st, first);
   return run_phase<false, kQuery>(g, w, gv, E, lists, list_stride, counts_host, stride, phase,
-                                  ovf_host_count, clk, st);
+                                  ovf_host_count, clk, st, first);
 }
 
 // Radix select of the k largest keys among entries [base, count) of the
@@ -1926,35 +1927,153 @@ __global__ void cross_check_kernel(const uint32_t* __restrict__ off, const uint3
   if (bad) atomicOr(err, 1u);
 }
 
+// Per-graph histograms of the kernels below: in LDS while the graphs fit
+// (flushed once per workgroup), else straight to global memory.  The graph
+// boundaries are staged in LDS alongside.
+constexpr uint32_t kGraphLds = 2048;
+
+struct GraphLds {
+  uint32_t start[kGraphLds + 1];
+  uint32_t hist[kGraphLds];
+};
+
+__device__ inline const uint32_t* graph_lds_init(GraphLds& L, const uint32_t* gstart, uint32_t ng) {
+  const bool lds = ng <= kGraphLds;
+  if (lds)
+    for (uint32_t t = threadIdx.x; t <= ng; t += blockDim.x) {
+      L.start[t] = gstart[t];
+      if (t < ng) L.hist[t] = 0;
+    }
+  __syncthreads();
+  return lds ? L.start : gstart;
+}
+
 // graph id of each candidate (by its smaller original id) and per-graph counts
-__global__ void graph_id_kernel(const uint32_t* __restrict__ a, unsigned long long n,
-                                const uint32_t* __restrict__ gstart, uint32_t ng,
-                                uint32_t* __restrict__ gid, uint32_t* __restrict__ gcount) {
+__global__ __launch_bounds__(256) void graph_id_kernel(const uint32_t* __restrict__ a, unsigned long long n,
+                                                       const uint32_t* __restrict__ gstart, uint32_t ng,
+                                                       uint32_t* __restrict__ gid, uint32_t* __restrict__ gcount) {
+  __shared__ GraphLds L;
+  const bool lds = ng <= kGraphLds;
+  const uint32_t* gs = graph_lds_init(L, gstart, ng);
   for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (unsigned long long)gridDim.x * blockDim.x) {
-    const uint32_t gi = graph_of_id(gstart, ng, a[i]);
+    const uint32_t gi = graph_of_id(gs, ng, a[i]);
     gid[i] = gi;
-    atomicAdd(&gcount[gi], 1u);
+    atomicAdd(lds ? &L.hist[gi] : &gcount[gi], 1u);
+  }
+  __syncthreads();
+  if (lds)
+    for (uint32_t t = threadIdx.x; t < ng; t += blockDim.x)
+      if (L.hist[t]) atomicAdd(&gcount[t], L.hist[t]);
+}
+
+// murmur3's 32-bit finaliser: spreads the original ids for the sample draw
+__device__ inline uint32_t sample_hash(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x85EBCA6Bu;
+  x ^= x >> 13;
+  x *= 0xC2B2AE35u;
+  x ^= x >> 16;
+  return x;
+}
+
+// Split one bucket list by each source's graph sampling stride: a source is
+// in the sample when the hash of its original id is a multiple of the stride.
+// The rest fill out[0, rest) and the sample fills out[count - sampled, count)
+// (from the top down); ctr[0] / ctr[1] count them.  One pair of atomics per
+// tile of 1024 records.
+constexpr int kSplitRounds = 4;
+
+__global__ __launch_bounds__(256) void graph_split_kernel(const SrcRec* __restrict__ in, uint32_t count,
+                                                          const uint32_t* __restrict__ gstart, uint32_t ng,
+                                                          const uint32_t* __restrict__ gstride,
+                                                          SrcRec* __restrict__ out, uint32_t* __restrict__ ctr,
+                                                          unsigned long long* __restrict__ sampled_wedges) {
+  __shared__ uint32_t cnt[kSplitRounds][4][2];
+  __shared__ uint32_t base[2];
+  __shared__ unsigned long long wsum[4];
+  unsigned long long my_w = 0;
+  const int lane = lane_id(), wid = threadIdx.x >> 6;
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  constexpr uint64_t kTile = 256ull * kSplitRounds;
+  for (uint64_t t0 = (uint64_t)blockIdx.x * kTile; t0 < count; t0 += (uint64_t)gridDim.x * kTile) {
+    SrcRec r[kSplitRounds];
+    bool valid[kSplitRounds], samp[kSplitRounds];
+    uint64_t bs[kSplitRounds], br[kSplitRounds];
+#pragma unroll
+    for (int j = 0; j < kSplitRounds; j++) {
+      const uint64_t i = t0 + (uint64_t)j * 256 + threadIdx.x;
+      valid[j] = i < count;
+      samp[j] = false;
+      if (valid[j]) {
+        r[j] = in[i];
+        const uint32_t sd = gstride[graph_of_id(gstart, ng, r[j].key)];
+        samp[j] = sd <= 1 || sample_hash(r[j].key) % sd == 0;
+        if (samp[j]) my_w += r[j].U;
+      }
+      bs[j] = __ballot(valid[j] && samp[j]);
+      br[j] = __ballot(valid[j] && !samp[j]);
+      if (lane == 0) {
+        cnt[j][wid][0] = (uint32_t)__popcll(br[j]);
+        cnt[j][wid][1] = (uint32_t)__popcll(bs[j]);
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+      uint32_t tot = 0;
+      for (int j = 0; j < kSplitRounds; j++)
+        for (int w = 0; w < 4; w++) tot += cnt[j][w][threadIdx.x];
+      base[threadIdx.x] = tot ? atomicAdd(&ctr[threadIdx.x], tot) : 0u;
+    }
+    __syncthreads();
+    uint32_t pr = base[0], ps = base[1];
+#pragma unroll
+    for (int j = 0; j < kSplitRounds; j++) {
+      uint32_t wr = 0, ws = 0;
+      for (int w = 0; w < 4; w++) {
+        if (w < wid) {
+          wr += cnt[j][w][0];
+          ws += cnt[j][w][1];
+        }
+      }
+      if (valid[j]) {
+        if (samp[j]) out[count - 1 - (ps + ws + (uint32_t)__popcll(bs[j] & lt))] = r[j];
+        else out[pr + wr + (uint32_t)__popcll(br[j] & lt)] = r[j];
+      }
+      for (int w = 0; w < 4; w++) {
+        pr += cnt[j][w][0];
+        ps += cnt[j][w][1];
+      }
+    }
+    __syncthreads();
+  }
+  for (int o = 32; o >= 1; o >>= 1) my_w += __shfl_xor(my_w, o);
+  if (lane == 0) wsum[wid] = my_w;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long t = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    if (t) atomicAdd(sampled_wedges, t);
   }
 }
 
 // Per-graph threshold from the sample sorted by (graph, score desc): the
 // score of the graph's r-th best sampled candidate with ids 0 (a lower bound
-// of that key), r = 1.5 k / stride + 64; no threshold when the graph sampled
-// fewer; k = 0 keeps nothing.
+// of that key), r = 1.5 k / stride + 64 with the graph's sampling stride; no
+// threshold when the graph sampled fewer; k = 0 keeps nothing.
 __global__ void graph_tau_kernel(uint32_t ng, const uint32_t* __restrict__ gcount,
                                  const uint32_t* __restrict__ gseg, const uint32_t* __restrict__ s_sorted,
-                                 const unsigned long long* __restrict__ gk, uint32_t stride,
-                                 uint32_t* __restrict__ gtau) {
+                                 const unsigned long long* __restrict__ gk,
+                                 const uint32_t* __restrict__ gstride, uint32_t* __restrict__ gtau) {
   const uint32_t gi = blockIdx.x * blockDim.x + threadIdx.x;
   if (gi >= ng) return;
   const unsigned long long k = gk[gi];
+  const unsigned long long stride = gstride[gi] > 0 ? gstride[gi] : 1;
   uint32_t t = 0;
   const bool none = k == 0;
   if (none) {
     t = 0x7F800000u;  // +inf: no finite score reaches it
   } else {
-    const unsigned long long r = (3 * k + 2 * (unsigned long long)stride - 1) / (2 * (unsigned long long)stride) + 64;
+    const unsigned long long r = (3 * k + 2 * stride - 1) / (2 * stride) + 64;
     if (gcount[gi] >= r) t = s_sorted[gseg[gi] + r - 1];
   }
   gtau[3 * gi] = t;
@@ -1963,17 +2082,27 @@ __global__ void graph_tau_kernel(uint32_t ng, const uint32_t* __restrict__ gcoun
 }
 
 // per-graph number of buffer entries whose key is >= the graph's threshold
-__global__ void graph_count_ge_kernel(const uint32_t* __restrict__ ks, const uint32_t* __restrict__ ka,
-                                      const uint32_t* __restrict__ kc, unsigned long long n,
-                                      const uint32_t* __restrict__ gstart, uint32_t ng,
-                                      const uint32_t* __restrict__ gtau, unsigned long long* out) {
+__global__ __launch_bounds__(256) void graph_count_ge_kernel(
+    const uint32_t* __restrict__ ks, const uint32_t* __restrict__ ka, const uint32_t* __restrict__ kc,
+    unsigned long long n, const uint32_t* __restrict__ gstart, uint32_t ng,
+    const uint32_t* __restrict__ gtau, unsigned long long* out) {
+  __shared__ GraphLds L;
+  const bool lds = ng <= kGraphLds;
+  const uint32_t* gs = graph_lds_init(L, gstart, ng);
   for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (unsigned long long)gridDim.x * blockDim.x) {
-    const uint32_t gi = graph_of_id(gstart, ng, ka[i]);
+    const uint32_t gi = graph_of_id(gs, ng, ka[i]);
     const uint32_t t0 = gtau[3 * gi], t1 = gtau[3 * gi + 1], t2 = gtau[3 * gi + 2];
     const uint32_t s = ks[i], a = ~ka[i], x = ~kc[i];
-    if (s > t0 || (s == t0 && (a > t1 || (a == t1 && x >= t2)))) atomicAdd(&out[gi], 1ull);
+    if (s > t0 || (s == t0 && (a > t1 || (a == t1 && x >= t2)))) {
+      if (lds) atomicAdd(&L.hist[gi], 1u);
+      else atomicAdd(&out[gi], 1ull);
+    }
   }
+  __syncthreads();
+  if (lds)
+    for (uint32_t t = threadIdx.x; t < ng; t += blockDim.x)
+      if (L.hist[t]) atomicAdd(&out[t], (unsigned long long)L.hist[t]);
 }
 
 // the first k_g entries of each graph's segment of the sorted buffer
@@ -2005,7 +2134,8 @@ lp_status run_predict_multi(lp_graph* g, int64_t ng, const int64_t* vstart, cons
   for (int64_t i = 0; i < ng; i++) out_count[i] = 0;
   const uint32_t NG = (uint32_t)ng;
   // per-graph tables: gstart[ng+1] u32, gtau[3ng] u32, gcount[ng] u32, gseg[ng] u32,
-  // gk[ng] u64, goff[ng] u64, gge[ng] u64
+  // gstride[ng] u32, split counters [2 kBuckets] u32, then gk[ng] u64,
+  // goff[ng] u64, gge[ng] u64, sampled wedges u64
   uint64_t ktot = 0;
   std::vector<uint32_t> hstart(NG + 1);
   std::vector<unsigned long long> hk(NG), hoff(NG);
@@ -2015,15 +2145,18 @@ lp_status run_predict_multi(lp_graph* g, int64_t ng, const int64_t* vstart, cons
     hoff[i] = ktot;
     ktot += hk[i];
   }
-  const size_t u32n = ((size_t)NG + 1 + 3 * (size_t)NG + 2 * (size_t)NG + 63) & ~(size_t)63;
+  const size_t u32n = ((size_t)NG + 1 + 3 * (size_t)NG + 3 * (size_t)NG + 2 * kBuckets + 63) & ~(size_t)63;
   LP_TRY(w.m_graph.ensure(u32n * 4 + (size_t)NG * 8 * 3 + 256));
   uint32_t* gstart = w.m_graph.as<uint32_t>();
   uint32_t* gtau = gstart + NG + 1;
   uint32_t* gcount = gtau + 3 * (size_t)NG;
   uint32_t* gseg = gcount + NG;
+  uint32_t* gstride = gseg + NG;
+  uint32_t* split_ctr = gstride + NG;
   unsigned long long* gk = reinterpret_cast<unsigned long long*>(w.m_graph.as<char>() + u32n * 4);
   unsigned long long* goff = gk + NG;
   unsigned long long* gge = goff + NG;
+  unsigned long long* samp_w = gge + NG;
   LP_HIP(hipMemcpyAsync(gstart, hstart.data(), (NG + 1) * 4, hipMemcpyHostToDevice, st));
   LP_HIP(hipMemcpyAsync(gk, hk.data(), NG * 8, hipMemcpyHostToDevice, st));
   LP_HIP(hipMemcpyAsync(goff, hoff.data(), NG * 8, hipMemcpyHostToDevice, st));
@@ -2033,7 +2166,8 @@ lp_status run_predict_multi(lp_graph* g, int64_t ng, const int64_t* vstart, cons
   unsigned long long *count, *fp;
   uint32_t ovf_cap;
   LP_TRY(ensure_ovf(w, &ovf, &ovf_rec, &ovf_count, &ovf_cap, &err, &count, &fp, &tau, st));
-  if (g->n > 0) {
+  // the graph never changes: a layout checked once stays valid
+  if (g->n > 0 && w.m_checked != hstart) {
     hipLaunchKernelGGL(cross_check_kernel, dim3(grid_for((uint64_t)g->n, 256, 0x7FFFFFFF)), dim3(256), 0,
                        st, g->off, g->adj, g->rank, g->perm, gstart, NG, g->n, err);
     LP_HIP(hipGetLastError());
@@ -2041,6 +2175,7 @@ lp_status run_predict_multi(lp_graph* g, int64_t ng, const int64_t* vstart, cons
     LP_HIP(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, st));
     LP_HIP(hipStreamSynchronize(st));
     if (herr) return set_error(LP_ERR_INVALID_GRAPH, "an edge joins two of the graphs");
+    w.m_checked = hstart;
   }
   Timer tm;
   LP_HIP(hipEventRecord(tm.ev[0], st));
@@ -2060,11 +2195,51 @@ lp_status run_predict_multi(lp_graph* g, int64_t ng, const int64_t* vstart, cons
                                                       : (g->tuning.sample_budget < 0 ? 0 : (1ull << 22));
   const bool sample = budget > 0 && total_w > budget && total_w > 8ull * ktot;
   uint32_t stride = 1;
+  const unsigned cus = (unsigned)num_cus();
+  const SrcRec* lists = w.lists.as<SrcRec>();
+  const uint64_t nl = (uint64_t)g->n;  // list stride of the bucket lists
+  // With sampling, every graph draws its own sample: the global stride
+  // W / budget, but at least one source in n_i / kMinSampled for a graph of
+  // n_i vertices (every source of a small one), so that each threshold rests
+  // on many sources.  The bucket lists are split into the sample and the
+  // rest (w.m_lists).
+  constexpr uint64_t kMinSampled = 256;
+  uint32_t first[kBuckets] = {}, n_samp[kBuckets] = {}, n_rest[kBuckets] = {};
+  unsigned long long samp_wedges = 0;
+  const SrcRec* split_lists = nullptr;
   if (sample) {
     const uint64_t sd = (total_w + budget - 1) / budget;
     stride = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(sd, 2), 1u << 20);
+    std::vector<uint32_t> hsd(NG);
+    for (uint32_t i = 0; i < NG; i++)
+      hsd[i] = (uint32_t)std::max<uint64_t>(
+          1, std::min<uint64_t>(stride, (uint64_t)(hstart[i + 1] - hstart[i]) / kMinSampled));
+    LP_HIP(hipMemcpyAsync(gstride, hsd.data(), (size_t)NG * 4, hipMemcpyHostToDevice, st));
+    LP_TRY(w.m_lists.ensure(std::max<uint64_t>(nl, 1) * sizeof(SrcRec) * kBuckets));
+    LP_HIP(hipMemsetAsync(split_ctr, 0, 2 * kBuckets * 4, st));
+    LP_HIP(hipMemsetAsync(samp_w, 0, 8, st));
+    for (int b = 0; b < kBuckets; b++) {
+      if (pr.out.count[b] == 0) continue;
+      hipLaunchKernelGGL(graph_split_kernel,
+                         dim3(grid_for(pr.out.count[b], 256 * kSplitRounds, cus * 4)), dim3(256), 0, st,
+                         lists + (uint64_t)b * nl, pr.out.count[b], gstart, NG, gstride,
+                         w.m_lists.as<SrcRec>() + (uint64_t)b * nl, split_ctr + 2 * b, samp_w);
+      LP_HIP(hipGetLastError());
+    }
+    uint32_t hc[2 * kBuckets];
+    LP_HIP(hipMemcpyAsync(hc, split_ctr, sizeof(hc), hipMemcpyDeviceToHost, st));
+    LP_HIP(hipMemcpyAsync(&samp_wedges, samp_w, 8, hipMemcpyDeviceToHost, st));
+    LP_HIP(hipStreamSynchronize(st));
+    for (int b = 0; b < kBuckets; b++) {
+      n_rest[b] = hc[2 * b];
+      n_samp[b] = hc[2 * b + 1];
+      if (n_rest[b] + n_samp[b] != pr.out.count[b]) return set_error(LP_ERR_DEVICE, "list split lost records");
+      first[b] = pr.out.count[b] - n_samp[b];
+    }
+    split_lists = w.m_lists.as<SrcRec>();
   }
-  uint64_t cap = sample ? 2 * (total_w / stride) + 4 * ktot + (1u << 20) : total_w;
+  // the sample keeps every candidate of its sources (at most its wedges)
+  uint64_t cap = sample ? samp_wedges + 4 * ktot + (1u << 20) : total_w;
   cap = std::min<uint64_t>(cap, total_w);
   cap = std::min<uint64_t>(cap, (1ull << 32) - 1);
   LP_TRY(w.cand_s.ensure(cap * 4));
@@ -2091,16 +2266,13 @@ lp_status run_predict_multi(lp_graph* g, int64_t ng, const int64_t* vstart, cons
   E.gtau = gtau;
   E.gstart = gstart;
   E.ngraphs = NG;
-  const SrcRec* lists = w.lists.as<SrcRec>();
   uint32_t ovf_host = 0;
   unsigned long long n_sample = 0;
   LaunchClock clk(&S);
   uint32_t* gid = w.m_gid.as<uint32_t>();
-  const unsigned cus = (unsigned)num_cus();
   if (sample) {
     // sampled sources without thresholds, then each graph's threshold
-    LP_TRY(run_phase_any<false>(g, w, gv, E, lists, (uint64_t)g->n, pr.out.count, stride, 1, &ovf_host,
-                                &clk, st));
+    LP_TRY(run_phase_any<false>(g, w, gv, E, split_lists, nl, n_samp, 1, 1, &ovf_host, &clk, st, first));
     LP_HIP(hipMemcpyAsync(&n_sample, count, 8, hipMemcpyDeviceToHost, st));
     LP_HIP(hipStreamSynchronize(st));
     if (n_sample > cap) return set_error(LP_ERR_OUT_OF_MEMORY, "sample exceeded its buffer");
@@ -2124,7 +2296,7 @@ lp_status run_predict_multi(lp_graph* g, int64_t ng, const int64_t* vstart, cons
     }
     LP_TRY(scan_exclusive_u32(gcount, gseg, (int64_t)NG, w.scan_tmp, st));
     hipLaunchKernelGGL(graph_tau_kernel, dim3((NG + 255) / 256), dim3(256), 0, st, NG, gcount, gseg, ts,
-                       gk, stride, gtau);
+                       gk, gstride, gtau);
     LP_HIP(hipGetLastError());
   }
   unsigned long long n_total = 0;
@@ -2132,8 +2304,7 @@ lp_status run_predict_multi(lp_graph* g, int64_t ng, const int64_t* vstart, cons
     if (attempt > 4) return set_error(LP_ERR_DEVICE, "per-graph thresholds did not converge");
     if (sample) {
       LP_HIP(hipMemcpyAsync(count, &n_sample, 8, hipMemcpyHostToDevice, st));
-      LP_TRY(run_phase_any<false>(g, w, gv, E, lists, (uint64_t)g->n, pr.out.count, stride, 2,
-                                  &ovf_host, &clk, st));
+      LP_TRY(run_phase_any<false>(g, w, gv, E, split_lists, nl, n_rest, 1, 0, &ovf_host, &clk, st));
     } else {
       LP_TRY(run_phase_any<false>(g, w, gv, E, lists, (uint64_t)g->n, pr.out.count, 1, 0, &ovf_host,
                                   &clk, st));

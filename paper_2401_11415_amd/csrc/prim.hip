@@ -229,7 +229,7 @@ lp_status scan_inclusive_u32_u64(const uint32_t* in, uint64_t* out, int64_t n, D
 // ---------------------------------------------------------------------------
 // Stable LSD radix sort: 8-bit digits, tiles of 4096 records per workgroup.
 // Pass = per-tile digit histogram -> digit-major exclusive scan -> stable
-// scatter (ranks inside a wave from ballots, waves serialised per sub-round).
+// scatter through LDS.
 // ---------------------------------------------------------------------------
 
 constexpr int kSortThreads = 256;
@@ -266,39 +266,90 @@ __global__ __launch_bounds__(kSortThreads) void radix_count_kernel(PassArgs p, i
   counts[(int64_t)threadIdx.x * ntiles + blockIdx.x] = hist[threadIdx.x];
 }
 
+// Stable scatter of one tile: every wave ranks its 1024 records by digit
+// (ballot match per round of 64, running per-digit counts in LDS), the tile
+// is staged in LDS in digit order, and the staged records leave in runs of
+// equal digits, so that neighbouring lanes write neighbouring addresses.
+template <int NW>
+struct ScatterLds {
+  uint32_t words[NW][kSortTile];
+  uint8_t dig[kSortTile];
+  uint32_t wcnt[kSortThreads / 64][256];  // per-wave digit counts, then per-wave digit starts
+  uint32_t dstart[256];                    // tile-local start of each digit
+  uint32_t gbase[256];                     // global start of each digit for this tile
+  uint32_t lds4[4];
+};
+
+template <int NW>
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(PassArgs p, int64_t n,
                                                                      const uint32_t* __restrict__ offs,
                                                                      int64_t ntiles) {
-  __shared__ uint32_t base[256];
-  __shared__ uint32_t wbase[kSortThreads / 64][256];
+  __shared__ ScatterLds<NW> L;
+  constexpr int kWaves = kSortThreads / 64;
+  constexpr int kRounds = kSortTile / kWaves / 64;  // 16 rounds of 64 records per wave
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  base[threadIdx.x] = offs[(int64_t)threadIdx.x * ntiles + blockIdx.x];
-  __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int w = 0; w < kWaves; w++) L.wcnt[w][threadIdx.x] = 0;
+  L.gbase[threadIdx.x] = offs[(int64_t)threadIdx.x * ntiles + blockIdx.x];
+  __syncthreads();
   const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
-  for (int r = 0; r < kSortItems; r++) {
-    const int64_t i = tile0 + (int64_t)r * kSortThreads + threadIdx.x;
-    const bool valid = i < n;
-    const uint32_t d = valid ? digit_of(p, i) : 0u;
+  const int tile_n = (int)(n - tile0 < kSortTile ? n - tile0 : kSortTile);
+  uint32_t item[kRounds][NW];
+  uint32_t dg[kRounds], loc[kRounds];
+#pragma unroll
+  for (int r = 0; r < kRounds; r++) {
+    const int t = (wid * kRounds + r) * 64 + lane;
+    const bool valid = t < tile_n;
+    uint32_t d = 0;
+#pragma unroll
+    for (int k = 0; k < NW; k++) item[r][k] = valid ? p.in[k][tile0 + t] : 0u;
+    uint32_t key = item[r][0];  // select the key word without indexing registers
+#pragma unroll
+    for (int k = 1; k < NW; k++) key = p.key_word == k ? item[r][k] : key;
+    if (valid) d = ((key ^ p.invert) >> p.shift) & 255u;
     uint64_t m = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; b++) {
-      uint64_t bb = __ballot((d >> b) & 1u);
+      const uint64_t bb = __ballot((d >> b) & 1u);
       m &= ((d >> b) & 1u) ? bb : ~bb;
     }
-    const uint32_t rank = (uint32_t)__popcll(m & lt);
-    const uint32_t cnt = (uint32_t)__popcll(m);
-    for (int w = 0; w < kSortThreads / 64; w++) {
-      if (wid == w && valid && rank == 0) {
-        wbase[w][d] = base[d];
-        base[d] += cnt;
-      }
-      __syncthreads();
+    // every lane reads its digit's running count before the leader (the
+    // lowest lane with that digit) advances it
+    const uint32_t base = L.wcnt[wid][d];
+    if (valid && (m & lt) == 0) L.wcnt[wid][d] = base + (uint32_t)__popcll(m);
+    dg[r] = d;
+    loc[r] = base + (uint32_t)__popcll(m & lt);
+  }
+  __syncthreads();
+  // digit totals -> tile-local digit starts -> per-wave starts
+  uint32_t tot = 0;
+  for (int w = 0; w < kWaves; w++) tot += L.wcnt[w][threadIdx.x];
+  uint32_t all;
+  const uint32_t ds = block_exclusive_scan<uint32_t>(tot, L.lds4, &all);
+  L.dstart[threadIdx.x] = ds;
+  uint32_t run = ds;
+  for (int w = 0; w < kWaves; w++) {
+    const uint32_t c = L.wcnt[w][threadIdx.x];
+    L.wcnt[w][threadIdx.x] = run;
+    run += c;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRounds; r++) {
+    const int t = (wid * kRounds + r) * 64 + lane;
+    if (t < tile_n) {
+      const uint32_t pos = L.wcnt[wid][dg[r]] + loc[r];
+#pragma unroll
+      for (int k = 0; k < NW; k++) L.words[k][pos] = item[r][k];
+      L.dig[pos] = (uint8_t)dg[r];
     }
-    if (valid) {
-      const uint32_t dst = wbase[wid][d] + rank;
-      for (int k = 0; k < p.nwords; k++) p.out[k][dst] = p.in[k][i];
-    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < tile_n; q += kSortThreads) {
+    const uint32_t d = L.dig[q];
+    const uint32_t dst = L.gbase[d] + ((uint32_t)q - L.dstart[d]);
+#pragma unroll
+    for (int k = 0; k < NW; k++) p.out[k][dst] = L.words[k][q];
   }
 }
 
@@ -330,8 +381,24 @@ lp_status radix_sort(const SortSpec& spec, int64_t n, DevBuf tmp[4], DevBuf& cou
                          n, cnts, ntiles);
       LP_HIP(hipGetLastError());
       LP_TRY(scan_exclusive_u32(cnts, offs, ntiles * 256, scan_tmp, st));
-      hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)ntiles), dim3(kSortThreads), 0, st,
-                         pa, n, (const uint32_t*)offs, ntiles);
+      switch (spec.nwords) {
+        case 1:
+          hipLaunchKernelGGL(radix_scatter_kernel<1>, dim3((unsigned)ntiles), dim3(kSortThreads), 0, st, pa, n,
+                             (const uint32_t*)offs, ntiles);
+          break;
+        case 2:
+          hipLaunchKernelGGL(radix_scatter_kernel<2>, dim3((unsigned)ntiles), dim3(kSortThreads), 0, st, pa, n,
+                             (const uint32_t*)offs, ntiles);
+          break;
+        case 3:
+          hipLaunchKernelGGL(radix_scatter_kernel<3>, dim3((unsigned)ntiles), dim3(kSortThreads), 0, st, pa, n,
+                             (const uint32_t*)offs, ntiles);
+          break;
+        default:
+          hipLaunchKernelGGL(radix_scatter_kernel<4>, dim3((unsigned)ntiles), dim3(kSortThreads), 0, st, pa, n,
+                             (const uint32_t*)offs, ntiles);
+          break;
+      }
       LP_HIP(hipGetLastError());
       for (int k = 0; k < 4; k++) {
         uint32_t* t = cur[k];
