@@ -180,7 +180,9 @@ typedef struct {
   uint64_t first_order; /* sum of the sources' degrees d_a */
   uint64_t arcs;        /* explored arcs a -> b that lead to at least one wedge */
   uint64_t wedges;      /* two-hop paths a - b - c accumulated */
-  uint64_t candidates;  /* distinct non-adjacent pairs found (before any threshold) */
+  uint64_t candidates;  /* distinct non-adjacent pairs accumulated (without a threshold:
+                           all of them; with one, a source skips the ids its degree
+                           bound rules out for any count) */
   double ms;            /* device time of the launches */
 } lp_bucket_stats;
 

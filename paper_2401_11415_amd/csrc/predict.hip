@@ -489,6 +489,11 @@ __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, WorkList 
     const uint32_t hmin = kW ? 1u : min_count(E.measure, ts_bits, s.da, !kQuery);
     const uint32_t cut1 = kW ? 0xFFFFFFFFu : uniform(id_cutoff(E.measure, 1, s.da, lo, g, !kQuery));
     const uint32_t cut2 = kW ? 0xFFFFFFFFu : uniform(id_cutoff(E.measure, 2, s.da, lo, g, !kQuery));
+    // no count exceeds the explored arcs: ids at or above the cutoff for that
+    // count cannot pass, so their wedges are not accumulated at all
+    const uint32_t cut_all = (kW || kQuery) ? 0xFFFFFFFFu
+                                            : uniform(id_cutoff(E.measure, s.na < s.da ? s.na : s.da, s.da,
+                                                                lo, g, true));
     bool handed = false;
     for (uint32_t pass = 0; pass < P; pass++) {
       if (S > clean) {
@@ -516,7 +521,7 @@ __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, WorkList 
                                   const bool (&v)[kWin]) {
 #pragma unroll
           for (int u = 0; u < kWin; u++) {
-            bool live = v[u];
+            bool live = v[u] & (c[u] < cut_all);
             if (kQuery) live = live & (c[u] != s.a);
             if (P > 1) live = live & (key_part(c[u], P) == pass);
             const uint64_t inc = kW ? s_w[arc[u]] : kSlotOne;
@@ -530,6 +535,7 @@ __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, WorkList 
       for (uint32_t e0 = s.x0; e0 < s.x1; e0 += G) {
         const uint32_t e = e0 + (G - 1 - gl);
         uint32_t b = e0 == s.x0 ? xb : (e < s.x1 ? g.adj[e] : kEmpty32);
+        if (b >= cut_all) b = kEmpty32;  // no wedge key at or above the cutoff exists
         if (P > 1 && b != kEmpty32 && key_part(b, P) != pass) b = kEmpty32;
         const bool ok = tab_insert<kW>(tab, keys, vals, S, b, key_slot(b, S),
                                        kW ? kBlocked64W : kBlocked64, RT);
@@ -632,6 +638,7 @@ struct BatchTab {
   uint32_t hmin[B];
   uint64_t wmin[kW ? B : 1];
   uint32_t cut[B][2];
+  uint32_t cut_all[B];
   int ovf;
   uint8_t mark[NW][64];
   uint32_t rt_key[NW][64];
@@ -683,7 +690,7 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
     const uint32_t nb = total - i0 < (uint32_t)B ? total - i0 : (uint32_t)B;
     // records and their prefix sums (first wave); the id cutoffs are loaded
     // here and published after the accumulation, off the critical path
-    uint32_t cut0 = 0xFFFFFFFFu, cut1 = 0xFFFFFFFFu;
+    uint32_t cut0 = 0xFFFFFFFFu, cut1 = 0xFFFFFFFFu, cutv = 0xFFFFFFFFu;
     if (tid < 64) {
       SrcRec r{};
       uint32_t na = 0, U = 0, nx = 0;
@@ -701,6 +708,9 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
         if (!kW) {
           cut0 = id_cutoff(E.measure, 1, r.da, lo, g, true);
           cut1 = id_cutoff(E.measure, 2, r.da, lo, g, true);
+          // no count exceeds the explored arcs: wedges to ids at or above the
+          // cutoff for that count are not accumulated
+          cutv = id_cutoff(E.measure, r.na < r.da ? r.na : r.da, r.da, lo, g, true);
         }
       }
       const uint32_t inext = i0 + gridDim.x * B + tid;
@@ -767,6 +777,7 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
       L.start[tid] = start;
       L.srcof[tid] = si;
       if (kW) L.w[tid] = w;
+      if (!kW && cb == 0 && tid < B) L.cut_all[tid] = cutv;
       // flat wedge range of this chunk
       const uint32_t qlast = (cb + WGS < NA ? cb + WGS : NA) - 1;
       const uint32_t sl = (uint32_t)batch_search<B>(L.arcoff, qlast);
@@ -779,9 +790,11 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
                               const bool (&v)[kWin]) {
 #pragma unroll
         for (int u = 0; u < kWin; u++) {
-          const uint32_t k = (L.srcof[arc[u]] << KB::kIdBits) | (c[u] & KB::kIdMask);
+          const uint32_t si = L.srcof[arc[u]];
+          const uint32_t k = (si << KB::kIdBits) | (c[u] & KB::kIdMask);
           const uint64_t w = kW ? L.w[arc[u]] : kSlotOne;
-          const bool ok = tab_insert<kW>(L.tab, L.keys, L.vals, S, v[u] ? k : kEmpty32, key_slot(k, S), w, RT);
+          const bool live = kW ? v[u] : (v[u] && c[u] < L.cut_all[si]);
+          const bool ok = tab_insert<kW>(L.tab, L.keys, L.vals, S, live ? k : kEmpty32, key_slot(k, S), w, RT);
           full = full | !ok;
         }
       });
@@ -799,6 +812,8 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
         const uint32_t i = (uint32_t)batch_search<B>(L.xoff, x);
         key = (i << KB::kIdBits) | g.adj[L.rec[i].x0 + (x - L.xoff[i])];
       }
+      // no wedge key at or above the source's cutoff exists
+      if (!kW && key != kEmpty32 && (key & KB::kIdMask) >= L.cut_all[key >> KB::kIdBits]) key = kEmpty32;
       const bool ok = tab_insert<kW>(L.tab, L.keys, L.vals, S, key, key_slot(key, S),
                                      kW ? kBlocked64W : kBlocked64, RT);
       full = full | !ok;

@@ -200,7 +200,9 @@ def test_launch_work_counters(lp, config1, L):
         tot = _launch_sums(st)
         if st["retries"] == 0:
             assert tot["wedges"] == ref[3]
-            assert tot["candidates"] == ref[0]
+            # with a threshold, pairs beyond a source's degree cutoff are not
+            # accumulated at all
+            assert tot["candidates"] <= ref[0]
 
 
 def test_sampled_threshold_path(lp, config1):
