@@ -118,6 +118,8 @@ __global__ __launch_bounds__(256) void plan_kernel(GView g, uint32_t hub_start, 
       if (h1 > h0) {
         const uint32_t k = lower_bound_dev(g.hb, h0, h1, hub_start) - h0;
         U = k ? g.hpsum[h0 + k - 1] : 0u;
+        // the bucket follows the work (wedges), not the key bound: a source
+        // with many wedges but few reachable keys still needs many lanes
         const uint64_t t = (uint64_t)U + (g.off[a + 1] - g.off[a] - g.below[a]);
         T = t > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)t;
       }
@@ -480,8 +482,6 @@ __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, WorkList 
     // the group's last wave on, which has the lightest share of the wedges)
     const uint32_t xe = s.x0 + (G - 1 - gl);
     const uint32_t xb = xe < s.x1 ? g.adj[xe] : kEmpty32;
-    uint32_t P, S;
-    table_geometry(s.U + (s.x1 - s.x0), SLOTS, &P, &S);
     // the source's threshold (its graph's, when several graphs run at once)
     const uint32_t ts_bits = E.fp_mode ? 0u : uniform((kQuery ? E.tau : tau_of(E, s.key))[0]);
     const uint64_t wmin = kW ? min_wsum(E.measure, ts_bits, E.shift) : 1ull;
@@ -494,6 +494,16 @@ __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, WorkList 
     const uint32_t cut_all = (kW || kQuery) ? 0xFFFFFFFFu
                                             : uniform(id_cutoff(E.measure, s.na < s.da ? s.na : s.da, s.da,
                                                                 lo, g, true));
+    // every key lies in (a, min(n, cut_all)) in the prediction orientation,
+    // which bounds the distinct keys far below the wedges for high-rank sources
+    uint32_t keys_max = s.U + (s.x1 - s.x0);
+    if (!kQuery) {
+      const uint32_t top = cut_all < g.n ? cut_all : g.n;
+      const uint32_t room = top > s.a + 1 ? top - s.a - 1 : 0u;
+      keys_max = room < keys_max ? room : keys_max;
+    }
+    uint32_t P, S;
+    table_geometry(keys_max, SLOTS, &P, &S);
     bool handed = false;
     for (uint32_t pass = 0; pass < P; pass++) {
       if (S > clean) {
@@ -635,6 +645,7 @@ struct BatchTab {
   uint32_t arcoff[B + 1];  // prefix of explored arcs
   uint32_t wedoff[B + 1];  // prefix of wedges
   uint32_t xoff[B + 1];    // prefix of first-order neighbours to exclude
+  uint32_t keys_max;       // bound of the batch's distinct keys
   uint32_t hmin[B];
   uint64_t wmin[kW ? B : 1];
   uint32_t cut[B][2];
@@ -693,12 +704,15 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
     uint32_t cut0 = 0xFFFFFFFFu, cut1 = 0xFFFFFFFFu, cutv = 0xFFFFFFFFu;
     if (tid < 64) {
       SrcRec r{};
-      uint32_t na = 0, U = 0, nx = 0;
+      uint32_t na = 0, U = 0, nx = 0, km = 0;
       if (tid < (int)nb) {
         r = nrec;
         na = r.na;
         U = r.U;
         nx = r.x1 - r.x0;
+        // keys lie in (a, n)
+        const uint32_t room = g.n - 1 - r.a;
+        km = U + nx < room ? U + nx : room;
         L.rec[tid] = r;
         // the source's threshold (its graph's, when several graphs run at once)
         const uint32_t ts_bits = E.fp_mode ? 0u : tau_of(E, r.key)[0];
@@ -719,12 +733,14 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
 #pragma unroll
       for (int o = 1; o < 64; o <<= 1) {
         const uint32_t ya = __shfl_up(xa, o, 64), yu = __shfl_up(xu, o, 64), yx = __shfl_up(xx, o, 64);
+        km += __shfl_xor(km, o, 64);
         if (tid >= o) {
           xa += ya;
           xu += yu;
           xx += yx;
         }
       }
+      if (tid == 0) L.keys_max = km;
       if (tid < B) {
         L.arcoff[tid] = xa - na;
         L.wedoff[tid] = xu - U;
@@ -738,8 +754,8 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
       if (tid == 0) L.ovf = 0;
     }
     __syncthreads();
-    const uint32_t NA = uniform(L.arcoff[B]), UT = uniform(L.wedoff[B]), NX = uniform(L.xoff[B]);
-    uint32_t S = (uint32_t)(((uint64_t)(UT + NX) * 3 + 1) / 2);
+    const uint32_t NA = uniform(L.arcoff[B]), NX = uniform(L.xoff[B]);
+    uint32_t S = (uint32_t)(((uint64_t)uniform(L.keys_max) * 3 + 1) / 2);
     if (S < 16) S = 16;
     if (S > (uint32_t)SLOTS) S = SLOTS;  // cannot happen within the bucket's bounds
     // first batch of first-order keys, in flight during the accumulation
@@ -1561,7 +1577,8 @@ static lp_status run_phase_any(lp_graph* g, Workspace& w, const GView& gv, const
 static lp_status run_select(lp_graph* g, const uint32_t* cs, const uint32_t* ca, const uint32_t* cc,
                             unsigned long long* count_dev, unsigned long long cap,
                             unsigned long long base, unsigned long long k, uint32_t* os,
-                            uint32_t* oa, uint32_t* oc, uint32_t* tau_out, hipStream_t st) {
+                            uint32_t* oa, uint32_t* oc, uint32_t* tau_out, hipStream_t st,
+                            bool full_key = false) {
   Workspace& w = g->ws;
   LP_TRY(w.sel_state.ensure(sizeof(SelState) + 64));
   LP_TRY(w.hist.ensure(2048 * 4));
@@ -1580,9 +1597,9 @@ static lp_status run_select(lp_graph* g, const uint32_t* cs, const uint32_t* ca,
                      oa, oc);
   LP_HIP(hipGetLastError());
   int ping = 0;
-  // a threshold needs only the score digits: (score of the k-th key, 0, 0) is
-  // a lower bound of the k-th key
-  const int nsteps = tau_out ? 3 : 9;
+  // a threshold estimate needs only the score digits: (score of the k-th key,
+  // 0, 0) is a lower bound of the k-th key; full_key asks for the key itself
+  const int nsteps = tau_out && !full_key ? 3 : 9;
   for (int step = 0; step < nsteps; step++) {
     uint32_t* nxt_s = w.tmp_s[ping].as<uint32_t>();
     uint32_t* nxt_a = w.tmp_a[ping].as<uint32_t>();
@@ -1833,9 +1850,10 @@ lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int3
       if (!sample)
         return set_error(LP_ERR_OUT_OF_MEMORY, "candidate buffer overflow (%llu > %llu)",
                          (unsigned long long)n_total, (unsigned long long)cap);
-      // the buffer holds >= k real candidates: its k-th best key is a safe tau
+      // the buffer holds >= k real candidates: its k-th best key (in full,
+      // since the score alone does not separate ties) is a safe tau
       LP_TRY(run_select(g, E.out_s, E.out_a, E.out_c, count, cap, 0, (unsigned long long)k, ts, ta,
-                        tc, tau, st));
+                        tc, tau, st, true));
       need_tau = false;
       continue;
     }

@@ -141,7 +141,8 @@ def test_config1_fingerprint(lp, config1, L):
 
 def test_global_path_and_partitions(lp, config1):
     """Force the dense global accumulator (tiny LDS cap), and exercise hash
-    partitions with a graph whose sources own > 8192 wedges."""
+    partitions with a graph whose sources can reach more distinct keys than
+    one LDS table holds (K_{4,12000}: a leaf reaches up to 12,003 others)."""
     gr, k = config1
     say("[gpu] forced global path")
     with lp.Graph(gr.offsets, gr.indices) as g:
@@ -154,13 +155,13 @@ def test_global_path_and_partitions(lp, config1):
             assert lp.fingerprint(g, None) == oracle.fingerprint(gr, None)
             st = lp.last_stats(g)
             assert st["buckets"]["global"] > 0
-    say("[gpu] hash partitions K_{5,4000}")
-    kb = synth.from_edges(4005, [(h, 5 + i) for h in range(5) for i in range(4000)])
+    say("[gpu] hash partitions K_{4,12000}")
+    kb = synth.from_edges(12004, [(h, 4 + i) for h in range(4) for i in range(12000)])
     with lp.Graph(kb.offsets, kb.indices) as g:
         for m in ("JC", "AA", "CN"):
             ref = oracle.predict(kb, None, m, 3000)
             got = run_predict(lp, g, m, None, 3000)
-            assert_same_list(got, ref, m, f"K5,4000/{m}")
+            assert_same_list(got, ref, m, f"K4,12000/{m}")
         assert lp.fingerprint(g, None) == oracle.fingerprint(kb, None)
         st = lp.last_stats(g)
         assert st["buckets"]["large"] > 0
