@@ -132,6 +132,8 @@ def main():
                          "call (default and autotuned knobs) vs one lp_predict call per graph")
     ap.add_argument("--graphs", type=int, default=512, help="--multi: number of graphs")
     ap.add_argument("--n-max", type=int, default=1_000_000, help="--multi: largest graph size")
+    ap.add_argument("--one-call-only", action="store_true",
+                    help="--multi: time only the one-call path with default knobs (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -443,6 +445,12 @@ def multi(args, lp, synth, torch):
     stats_default = lp.last_stats(g)
     k_out = sum(int(a.shape[0]) for a, _, _ in out)
     log(f"one call, default knobs: median {med_default:.3f} ms")
+    if args.one_call_only:
+        g.close()
+        print(json.dumps({"metric": "several-graph call only (default knobs)", "ms_per_step": med_default,
+                          "value": k_out / (med_default * 1e-3), "unit": "edges/s",
+                          "device_ms": stats_default["ms_total"], "graphs": args.graphs}), flush=True)
+        return
     tuned = tune.autotune(g, run, repeats=3, log=log)
     for i in range(args.warmup):
         run()
