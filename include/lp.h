@@ -146,7 +146,8 @@ lp_status lp_fingerprint(lp_graph *g, int64_t hub_limit, uint64_t *out, void *hi
  *     accumulator of 12 bytes per vertex (default: one per compute unit; the
  *     pool is also kept within a quarter of the device memory);
  *   sample_budget: wedge budget of the sampling pass that sets the top-k
- *     filter threshold (default 2^22; a negative value disables sampling);
+ *     filter threshold (default: about 0.1% of the call's wedges, clamped to
+ *     [2^20, 2^22]; a negative value disables sampling);
  *   bucket_max[b]: upper bound of T for the scheduling buckets tiny, small,
  *     mid1, mid2, mid3 (defaults 32, 256, 1024, 2048, 4096, the table sizes
  *     the kernels are built for; a value may only lower its default, moving

@@ -1299,6 +1299,16 @@ static unsigned grid_for(uint64_t items, int per_block, unsigned cap_blocks) {
   return (unsigned)b;
 }
 
+// Wedge budget of the sampling pass: the tuning's, else about 0.1% of the
+// wedges, clamped to [2^20, 2^22] (the sample's launches are latency bound,
+// so a larger one costs time and a smaller one loosens the threshold); 0
+// turns sampling off.
+static uint64_t sample_budget(const lp_graph* g, uint64_t total_w) {
+  if (g->tuning.sample_budget < 0) return 0;
+  if (g->tuning.sample_budget > 0) return (uint64_t)g->tuning.sample_budget;
+  return std::min<uint64_t>(1ull << 22, std::max<uint64_t>(1ull << 20, total_w >> 10));
+}
+
 struct AccConfig {
   BucketCuts cuts;    // bucket bounds; cuts.t[kBucketLarge]: T above which a source uses the global path
   unsigned spa_wgs;   // workgroups (dense accumulators) of the global path
@@ -1767,8 +1777,7 @@ lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int3
     return LP_OK;
   }
   const uint64_t total_w = pr.out.wedges;
-  const uint64_t budget = g->tuning.sample_budget > 0 ? (uint64_t)g->tuning.sample_budget
-                                                      : (g->tuning.sample_budget < 0 ? 0 : (1ull << 22));
+  const uint64_t budget = sample_budget(g, total_w);
   // Sampling pays off only when candidates far outnumber k: a sampled subset
   // of sources (every stride-th of each bucket) is scored first, without a
   // threshold; tau is then a lower bound of its r-th best key with
@@ -2224,8 +2233,7 @@ lp_status run_predict_multi(lp_graph* g, int64_t ng, const int64_t* vstart, cons
   }
   const GView gv = view_of(g);
   const uint64_t total_w = pr.out.wedges;
-  const uint64_t budget = g->tuning.sample_budget > 0 ? (uint64_t)g->tuning.sample_budget
-                                                      : (g->tuning.sample_budget < 0 ? 0 : (1ull << 22));
+  const uint64_t budget = sample_budget(g, total_w);
   const bool sample = budget > 0 && total_w > budget && total_w > 8ull * ktot;
   uint32_t stride = 1;
   const unsigned cus = (unsigned)num_cus();

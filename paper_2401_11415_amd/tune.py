@@ -30,7 +30,7 @@ DEFAULT_SPACE = {
     "bucket_max4": (4096, 3072),
     "lds_wedge_cap": (65536, 32768, 16384, 131072, 262144),
     "global_slots": (0, 128, 512),
-    "sample_budget": (1 << 22, 1 << 20, 1 << 24),
+    "sample_budget": (0, 1 << 20, 1 << 22, 1 << 24),  # 0: the library's default rule
 }
 
 
