@@ -642,3 +642,38 @@ def test_autotune_keeps_results(lp):
         for r, b in zip(lp.predict_multi(g, vs, ks, "JC", 256), base):
             for x, y in zip((to_np(x) for x in r), b):
                 assert np.array_equal(x, y)
+
+
+@pytest.fixture(scope="module")
+def batch512():
+    """The batched workload: 512 Chung-Lu graphs of 1,000-1,000,000 vertices
+    (log-uniform), mean degree 8-32, exponent 2.3, graph i seeded 1000 + i,
+    sizes drawn with seed 5; k_i = m_i / 10."""
+    gs = synth.chung_lu_batch(512, 1000, 1_000_000, seed=5)
+    u, vs = synth.disjoint_union(gs)
+    return gs, u, vs, [gr.m // 10 for gr in gs]
+
+
+def test_full_size_batch512(lp, batch512):
+    """The several-graph call at the batched workload's full size (71.8 M
+    vertices in one union, DLH JC L = 256, default knobs, as bench.py --multi
+    times it): the lists of a seeded sample of graphs, and of the largest
+    one, equal the oracle's on each graph alone.  The union has more than
+    2^26 vertices, so its tiny sources run 32 per workgroup."""
+    gs, u, vs, ks = batch512
+    rng = np.random.default_rng(17)
+    order = np.argsort([gr.n for gr in gs])
+    picks = sorted(set(rng.choice(order[:384], size=10, replace=False).tolist()) | {int(order[-1])})
+    say(f"[gpu] batch of 512 graphs n={u.n} picks={picks}")
+    assert u.n > (1 << 26)
+    with lp.Graph(u.offsets, u.indices) as g:
+        res = lp.predict_multi(g, vs, ks, "JC", 256)
+        st = lp.last_stats(g)
+        got = {i: tuple(to_np(x) for x in res[i]) for i in picks}
+        sizes = [int(r[0].shape[0]) for r in res]
+    assert st["launches"]["tiny"]["launches"] > 0
+    assert all(sz <= k for sz, k in zip(sizes, ks))
+    for i in picks:
+        a, c, s = got[i]
+        ref = oracle.predict(gs[i], 256, "JC", ks[i])
+        assert_same_list((a - vs[i], c - vs[i], s), ref, "JC", f"batch graph {i} n={gs[i].n}")
