@@ -187,7 +187,10 @@ typedef struct {
   double ms;            /* device time of the launches */
 } lp_bucket_stats;
 
-/* Statistics of the last lp_predict / lp_fingerprint on g (host pointer). */
+/* Statistics of the last lp_predict / lp_fingerprint / lp_query on g (host
+ * pointer).  For lp_query, wedges is the plan's upper bound, appended the
+ * candidates written for the final sort, and only the main-pass launch
+ * counters and times are filled. */
 typedef struct {
   uint64_t wedges;            /* two-hop paths accumulated */
   uint64_t sources;           /* sources with at least one wedge */

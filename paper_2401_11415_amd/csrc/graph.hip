@@ -428,7 +428,7 @@ void release_workspace(Workspace& w) {
                    &w.tmp_c[1], &w.hist, &w.sel_state, &w.sort_tmp[0], &w.sort_tmp[1],
                    &w.sort_tmp[2], &w.sort_tmp[3], &w.sort_counts, &w.scan_tmp, &w.global_tab, &w.q_src,
                    &w.q_cnt, &w.q_wedges, &w.q_rows, &w.q_out, &w.m_graph, &w.m_gid,
-                   &w.m_lists};
+                   &w.m_lists, &w.spa_meta};
   for (auto b : all) b->release();
   w.host_stats.release();
   w.m_checked.clear();

@@ -50,7 +50,23 @@ struct Emit {
   const uint32_t* gtau;
   const uint32_t* gstart;
   uint32_t ngraphs;
+  uint32_t kq;  // query: results wanted per source (0: keep every candidate)
 };
+
+// Log-scale bins of a positive fixed-point sum: values below 8 have a bin
+// each, then eight bins per octave (bin order = value order), 496 in all.
+constexpr uint32_t kSumBins = 512;
+__device__ inline uint32_t sum_bin(uint64_t v) {
+  if (v < 8) return (uint32_t)v;
+  const uint32_t o = 63u - (uint32_t)__clzll((long long)v);  // octave, >= 3
+  return 8u + (o - 3u) * 8u + (uint32_t)((v >> (o - 3u)) & 7u);
+}
+// smallest sum in bin b
+__device__ inline uint64_t sum_bin_floor(uint32_t b) {
+  if (b < 8) return b;
+  const uint32_t o = (b - 8u) / 8u + 3u, sub = (b - 8u) % 8u;
+  return (uint64_t)(8u + sub) << (o - 3u);
+}
 
 // Graph of an original id (several-graph calls only).
 __device__ inline uint32_t graph_of(const Emit& E, uint32_t key) {
@@ -287,7 +303,42 @@ struct Stage {
 };
 
 __device__ inline void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
+// The floor of the highest bin that completes k_q sums, from one wave over a
+// kSumBins histogram (0 when there are fewer than k_q sums: keep all).
+// Lane l reads bins [8 l, 8 l + 8); the result is wave-uniform.
+__device__ inline uint64_t sum_floor_wave(const uint32_t* h, uint32_t kq) {
+  const int lane = lane_id();
+  const uint32_t* mine = h + lane * 8;
+  uint32_t sum = 0;
+  for (int i = 0; i < 8; i++) sum += mine[i];
+  // entries in the lanes above (suffix sums over lanes)
+  uint32_t above = sum;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_down(above, o, 64);
+    if (lane + o < 64) above += y;
+  }
+  above -= sum;
+  // the bin that completes k_q: at most one lane has it
+  uint32_t bin = 0xFFFFFFFFu;
+  if (above < kq && above + sum >= kq) {
+    uint32_t run = above;
+    for (int i = 7; i >= 0 && bin == 0xFFFFFFFFu; i--) {
+      run += mine[i];
+      if (run >= kq) bin = (uint32_t)(lane * 8 + i);
+    }
+  }
+  // wave minimum of the candidate bins (0xFFFFFFFF: fewer than k_q sums)
+  for (int o = 32; o >= 1; o >>= 1) {
+    const uint32_t y = __shfl_xor(bin, o, 64);
+    bin = y < bin ? y : bin;
+  }
+  return bin == 0xFFFFFFFFu ? 0ull : sum_bin_floor(bin);
+}
+
 __device__ inline uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline uint64_t uniform64(uint64_t v) {
+  return ((uint64_t)uniform((uint32_t)(v >> 32)) << 32) | uniform((uint32_t)v);
+}
 
 // Copy the survivors to the global buffer.
 template <bool kQuery>

@@ -75,7 +75,7 @@ struct Workspace {
   DevBuf cand_s, cand_a, cand_c;
   DevBuf tmp_s[2], tmp_a[2], tmp_c[2];
   DevBuf hist, sel_state, sort_tmp[4], sort_counts, scan_tmp;
-  DevBuf global_tab;
+  DevBuf global_tab, spa_meta;
   unsigned global_slabs = 0;  // accumulator slabs in global_tab
   // query
   DevBuf q_src, q_cnt, q_wedges, q_rows, q_out;

@@ -27,6 +27,8 @@
 #include <cmath>
 #include <cstring>
 
+#include <memory>
+
 #include "kernels.h"
 
 namespace lp {
@@ -409,7 +411,7 @@ __device__ inline void walk_chunk(const GView& g, const uint32_t* excl, const ui
 // groups per workgroup), one source per group at a time, up to SLOTS slots.
 // ---------------------------------------------------------------------------
 
-template <int WGS, int G, int SLOTS, bool kW, int STAGE>
+template <int WGS, int G, int SLOTS, bool kW, int STAGE, bool kQ = false>
 struct LdsTab {
   static constexpr int NG = WGS / G;
   static constexpr int NW = WGS / 64;
@@ -425,6 +427,9 @@ struct LdsTab {
   uint32_t rt_key[NW][64];
   uint32_t rt_h[NW][64];
   uint64_t rt_w[kW ? NW : 1][64];
+  // weighted queries: a histogram of the group's sums and its floor
+  uint32_t qhist[kQ ? NG : 1][kQ ? kSumBins : 1];
+  uint64_t qfloor[kQ ? NG : 1];
   uint32_t st_c[NW][STAGE];
   uint32_t st_h[NW][STAGE];
   uint32_t st_w2[kW ? NW : 1][kW ? STAGE : 1];
@@ -442,7 +447,7 @@ __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, WorkList 
   static_assert(G % 64 == 0 && (G == 64 || G == WGS), "groups are whole waves");
   static_assert(STAGE >= 64, "a stage holds at least one wave of entries");
   constexpr int NG = WGS / G;
-  __shared__ LdsTab<WGS, G, SLOTS, kW, STAGE> L;
+  __shared__ LdsTab<WGS, G, SLOTS, kW, STAGE, kW && kQuery> L;
   const int grp = (int)uniform(threadIdx.x / G);
   const int gl = threadIdx.x & (G - 1);
   const int wv = threadIdx.x >> 6;
@@ -570,6 +575,28 @@ __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, WorkList 
         handed = true;
         break;
       }
+      // a weighted query needs only the k_q best sums of the source: the
+      // floor of a histogram of this partition's sums bounds them below
+      uint64_t wmin_q = wmin;
+      if constexpr (kW && kQuery) {
+        if (E.kq > 0 && S > 4 * E.kq) {
+          uint32_t* qh = L.qhist[grp];
+          for (uint32_t b = gl; b < kSumBins; b += G) qh[b] = 0;
+          group_sync<G>();
+          for (uint32_t t = gl; t < S; t += G) {
+            const uint64_t v = vals[t];
+            if (keys[t] != kEmpty32 && v != 0 && (v >> 63) == 0) atomicAdd(&qh[sum_bin(v)], 1u);
+          }
+          group_sync<G>();
+          if (gl < 64) {
+            const uint64_t f = sum_floor_wave(qh, E.kq);
+            if (gl == 0) L.qfloor[grp] = f;
+          }
+          group_sync<G>();
+          const uint64_t f = uniform64(L.qfloor[grp]);
+          wmin_q = f > wmin ? f : wmin;
+        }
+      }
       // stage every key of this partition that can still reach tau, and
       // leave the table empty for the next source
       for (uint32_t t0 = 0; t0 < S; t0 += G) {
@@ -586,7 +613,7 @@ __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, WorkList 
             vals[t] = 0;
           }
           cand = t < S && c != kEmpty32 && (wsum >> 63) == 0;
-          ok = cand && wsum >= wmin;
+          ok = cand && wsum >= wmin_q;
         } else {
           const uint64_t v = tab[tc];
           if (t < S) tab[t] = kSlotEmpty;
@@ -1011,6 +1038,226 @@ __global__ __launch_bounds__(kSpaThreads) void acc_spa_kernel(GView g, Emit E, W
 }
 
 // ---------------------------------------------------------------------------
+// Dense accumulation split over workgroups, for the sources above the LDS
+// capacity: one workgroup per source made a hub with millions of wedges the
+// tail of the whole launch.  A round takes as many sources as there are
+// slabs; any workgroup takes any piece of 1024 arcs of them (atomics into the
+// source's slab, first touches appended to its key list, one atomic per wave
+// for the list), then the first-order entries are cleared, then pieces of
+// 1024 keys are scored and emitted, which leaves every slab zero again.
+// Kernel boundaries order the three steps.
+// ---------------------------------------------------------------------------
+
+struct SpaRound {
+  WorkList wl;       // the bucket's work list
+  uint32_t i0, n;    // the round's items: work-list positions [i0, i0 + n)
+  uint32_t* poff;    // n + 1 offsets of the arc pieces ...
+  uint32_t* koff;    // n + 1 offsets of the key pieces
+  uint32_t* nkeys;   // n distinct keys per source (zero before the round)
+  char* acc;         // slab j at acc + j * 8n
+  uint32_t* keys;    // key list j at keys + j * n
+  uint32_t* hist;    // query with sums: n x kSumBins bins of the sources' sums (zeroed) ...
+  unsigned long long* floor_sum;  // ... and n per-source floors: the k_q-th largest sum's bin
+};
+
+constexpr uint32_t kSpaPiece = kSpaThreads;  // arcs or keys per piece
+
+// piece offsets of a round: ceil(arcs / 1024) per source (mode 0) or
+// ceil(keys / 1024) (mode 1); one workgroup
+__global__ __launch_bounds__(1024) void spa_pieces_kernel(SpaRound R, int mode) {
+  __shared__ uint32_t tmp[16];
+  uint32_t* out = mode == 0 ? R.poff : R.koff;
+  uint32_t run = 0;
+  for (uint32_t j0 = 0; j0 < R.n; j0 += 1024) {
+    const uint32_t j = j0 + threadIdx.x;
+    uint32_t p = 0;
+    if (j < R.n) {
+      const uint32_t cnt = mode == 0 ? load_rec(R.wl, R.i0 + j).na : R.nkeys[j];
+      p = (cnt + kSpaPiece - 1) / kSpaPiece;
+    }
+    uint32_t tot;
+    const uint32_t ex = group_exclusive_scan<1024>(p, tmp, &tot);
+    if (j < R.n) out[j] = run + ex;
+    run += tot;
+  }
+  if (threadIdx.x == 0) out[R.n] = run;
+}
+
+// the source j of piece q: last j with off[j] <= q (off[0] = 0 <= q < off[n])
+__device__ inline uint32_t spa_piece_source(const uint32_t* off, uint32_t n, uint32_t q) {
+  uint32_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (off[mid] <= q) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <bool kW, bool kQuery, bool kSampled>
+__global__ __launch_bounds__(kSpaThreads) void spa_split_acc_kernel(GView g, Emit E, SpaRound R) {
+  constexpr int T = kSpaThreads;
+  constexpr int NW = T / 64;
+  __shared__ uint32_t s_excl[T], s_start[T], scan_tmp[NW];
+  __shared__ uint64_t s_w[kW ? T : 1];
+  __shared__ uint8_t s_mark[NW][64];
+  const int wv = threadIdx.x >> 6;
+  uint8_t* mark = s_mark[wv];
+  mark[lane_id()] = 0;
+  wave_fence();
+  const uint32_t total = uniform(R.poff[R.n]);
+  for (uint32_t q = blockIdx.x; q < total; q += gridDim.x) {
+    const uint32_t j = uniform(spa_piece_source(R.poff, R.n, q));
+    const SrcRec s = uniform_rec(load_rec(R.wl, R.i0 + j));
+    const uint32_t cb = (q - uniform(R.poff[j])) * kSpaPiece;
+    char* slab = R.acc + (uint64_t)j * g.n * 8;
+    uint32_t* H = reinterpret_cast<uint32_t*>(slab);
+    unsigned long long* HW = reinterpret_cast<unsigned long long*>(slab);
+    uint32_t* K = R.keys + (uint64_t)j * g.n;
+    uint32_t lo, hi;
+    __syncthreads();  // every wave is done with the previous piece
+    load_chunk<T, kQuery, kW>(g, E, s, cb, s_excl, s_start, s_w, scan_tmp, &lo, &hi);
+    __syncthreads();
+    const uint32_t narcs = s.na - cb < (uint32_t)T ? s.na - cb : (uint32_t)T;
+    walk_chunk<NW, T>(g, s_excl, s_start, narcs, lo, hi, (int)uniform(wv), mark,
+                      [&](const uint32_t (&c)[kWin], const uint32_t (&arc)[kWin],
+                          const bool (&v)[kWin]) {
+#pragma unroll
+      for (int u = 0; u < kWin; u++) {
+        bool first = false;
+        if (v[u] && !(kQuery && c[u] == s.a)) {
+          if (kW) first = atomicAdd(&HW[c[u]], (unsigned long long)s_w[arc[u]]) == 0ull;
+          else first = atomicAdd(&H[c[u]], 1u) == 0u;
+        }
+        // new keys of the wave go to the list with one atomic
+        const uint64_t m = __ballot(first);
+        if (m) {
+          uint32_t base = 0;
+          const int leader = __ffsll((unsigned long long)m) - 1;
+          if (lane_id() == leader) base = atomicAdd(&R.nkeys[j], (uint32_t)__popcll(m));
+          base = __shfl(base, leader);
+          if (first)
+            __hip_atomic_store(&K[base + (uint32_t)__popcll(m & lanemask_lt())], c[u], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+    });
+  }
+}
+
+// first-order neighbours are not candidates: clear their entries (one
+// workgroup per source; the source's work counters are taken here)
+template <bool kW, bool kQuery, bool kSampled>
+__global__ __launch_bounds__(kSpaThreads) void spa_split_excl_kernel(GView g, Emit E, SpaRound R) {
+  WorkAcc wk;
+  for (uint32_t j = blockIdx.x; j < R.n; j += gridDim.x) {
+    const SrcRec s = uniform_rec(load_rec(R.wl, R.i0 + j));
+    char* slab = R.acc + (uint64_t)j * g.n * 8;
+    for (uint32_t e = s.x0 + threadIdx.x; e < s.x1; e += kSpaThreads) {
+      const uint32_t b = g.adj[e];
+      if (kW)
+        __hip_atomic_store(reinterpret_cast<unsigned long long*>(slab) + b, 0ull, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      else
+        __hip_atomic_store(reinterpret_cast<uint32_t*>(slab) + b, 0u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (threadIdx.x == 0) wk.source(s.da, s.na, s.U);
+  }
+  flush_work(E, wk);
+}
+
+// Query with sums (AA, RA): each source needs only its k_q best candidates,
+// and the score grows with the sum.  A log-scale histogram of each source's
+// sums gives a floor at or below its k_q-th largest sum; the sweep keeps
+// only sums at or above it, so a hub no longer emits millions of candidates.
+template <bool kW, bool kQuery, bool kSampled>
+__global__ __launch_bounds__(kSpaThreads) void spa_split_hist_kernel(GView g, Emit E, SpaRound R) {
+  __shared__ uint32_t lh[kSumBins];
+  const uint32_t total = uniform(R.koff[R.n]);
+  for (uint32_t q = blockIdx.x; q < total; q += gridDim.x) {
+    const uint32_t j = uniform(spa_piece_source(R.koff, R.n, q));
+    for (uint32_t b = threadIdx.x; b < kSumBins; b += kSpaThreads) lh[b] = 0;
+    __syncthreads();
+    const unsigned long long* HW = reinterpret_cast<const unsigned long long*>(R.acc + (uint64_t)j * g.n * 8);
+    const uint32_t* K = R.keys + (uint64_t)j * g.n;
+    const uint32_t nk = uniform(R.nkeys[j]);
+    const uint32_t t = (q - uniform(R.koff[j])) * kSpaPiece + threadIdx.x;
+    if (t < nk) {
+      const unsigned long long v = HW[K[t]];
+      if (v != 0) atomicAdd(&lh[sum_bin(v)], 1u);
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < kSumBins; b += kSpaThreads)
+      if (lh[b]) atomicAdd(&R.hist[(uint64_t)j * kSumBins + b], lh[b]);
+    __syncthreads();
+  }
+}
+
+// one wave per source of the round
+__global__ __launch_bounds__(64) void spa_split_floor_kernel(SpaRound R, uint32_t kq) {
+  const uint32_t j = blockIdx.x;
+  if (j >= R.n) return;
+  const uint64_t f = sum_floor_wave(R.hist + (uint64_t)j * kSumBins, kq);
+  if (lane_id() == 0) R.floor_sum[j] = f;
+}
+
+// score and emit pieces of 1024 keys, clearing the slab behind them
+template <bool kW, bool kQuery, bool kSampled>
+__global__ __launch_bounds__(kSpaThreads) void spa_split_sweep_kernel(GView g, Emit E, SpaRound R) {
+  constexpr int NW = kSpaThreads / 64;
+  __shared__ uint32_t st_c[NW][kSpaStage], st_h[NW][kSpaStage], st_k[NW][kSpaStage],
+      st_d[NW][kSpaStage], st_w2[kW ? NW : 1][kW ? kSpaStage : 1];
+  __shared__ uint32_t so_s[NW][64], so_a[NW][64], so_c[NW][64];
+  const int wv = threadIdx.x >> 6;
+  Stage SG{st_c[wv], st_h[wv], kW ? st_w2[wv] : nullptr, st_k[wv], st_d[wv], (uint32_t)kSpaStage,
+           so_s[wv], so_a[wv], so_c[wv], 64u};
+  FpAcc fa;
+  WorkAcc wk;
+  const uint32_t total = uniform(R.koff[R.n]);
+  for (uint32_t q = blockIdx.x; q < total; q += gridDim.x) {
+    const uint32_t j = uniform(spa_piece_source(R.koff, R.n, q));
+    const SrcRec s = uniform_rec(load_rec(R.wl, R.i0 + j));
+    const uint32_t ts_bits = E.fp_mode ? 0u : uniform((kQuery ? E.tau : tau_of(E, s.key))[0]);
+    uint64_t wmin = kW ? min_wsum(E.measure, ts_bits, E.shift) : 1ull;
+    if (kQuery && kW && R.floor_sum) {
+      const uint64_t f = uniform64(R.floor_sum[j]);
+      wmin = f > wmin ? f : wmin;
+    }
+    const uint32_t hmin = kW ? 1u : min_count(E.measure, ts_bits, s.da, !kQuery);
+    char* slab = R.acc + (uint64_t)j * g.n * 8;
+    const uint32_t* K = R.keys + (uint64_t)j * g.n;
+    const uint32_t nk = uniform(R.nkeys[j]);
+    const uint32_t t = (q - uniform(R.koff[j])) * kSpaPiece + threadIdx.x;
+    uint32_t c = 0, h = 0;
+    uint64_t wsum = 0;
+    bool ok = false;
+    if (t < nk) {
+      // every key is listed once, and the accumulation is over (an earlier
+      // launch): a plain read and clear, no read-modify-write atomics
+      c = K[t];
+      if (kW) {
+        unsigned long long* p = reinterpret_cast<unsigned long long*>(slab) + c;
+        wsum = *p;
+        *p = 0ull;
+        wk.v[4] += wsum != 0 ? 1u : 0u;
+        ok = wsum != 0 && wsum >= wmin;
+      } else {
+        uint32_t* p = reinterpret_cast<uint32_t*>(slab) + c;
+        h = *p;
+        *p = 0u;
+        wk.v[4] += h != 0 ? 1u : 0u;
+        ok = h != 0 && h >= hmin;
+      }
+    }
+    stage_add<kQuery, kW>(E, g, SG, ok, c, h, wsum, s.key, s.da, fa);
+  }
+  stage_drain<kQuery, kW>(E, g, SG, fa);
+  flush_fp(E, fa);
+  flush_work(E, wk);
+}
+
+// ---------------------------------------------------------------------------
 // Radix select over the candidate buffer: the k largest keys
 // (score bits, ~a, ~c), 9 digit steps of 11 / 11 / 10 bits per key word.
 // ---------------------------------------------------------------------------
@@ -1414,10 +1661,45 @@ static lp_status launch_spa(lp_graph* g, Workspace& w, const GView& gv, const Em
   // the accumulators are left zeroed by every workgroup; the key lists need no init
   char* base = w.global_tab.as<char>();
   uint32_t* spa_keys = reinterpret_cast<uint32_t*>(base + (size_t)w.global_slabs * n * 8);
-  const unsigned wgs = slabs;
-  hipLaunchKernelGGL((acc_spa_kernel<kW, kQuery, kSampled>), dim3(wgs), dim3(kSpaThreads), 0, st, gv, E, wl,
-                     ov, base, spa_keys);
-  LP_HIP(hipGetLastError());
+  if (ov.ovf) {
+    // overflow records (partitions of sources that filled an LDS table): one
+    // workgroup per record
+    hipLaunchKernelGGL((acc_spa_kernel<kW, kQuery, kSampled>), dim3(slabs), dim3(kSpaThreads), 0, st, gv, E,
+                       wl, ov, base, spa_keys);
+    LP_HIP(hipGetLastError());
+    return LP_OK;
+  }
+  // the bucket's sources: rounds of up to `slabs` sources, split over all CUs
+  // meta: poff, koff, nkeys (u32, slabs + 1 each), then per-source floors
+  // (u64) and sum histograms (u32, kSumBins each)
+  const size_t u32_meta = ((size_t)slabs * 3 + 8 + 1) & ~(size_t)1;
+  const bool floors = kQuery && kW && E.kq > 0;
+  LP_TRY(w.spa_meta.ensure(u32_meta * 4 + (size_t)slabs * 8 + (floors ? (size_t)slabs * kSumBins * 4 : 0)));
+  uint32_t* meta = w.spa_meta.as<uint32_t>();
+  unsigned long long* floor_sum = reinterpret_cast<unsigned long long*>(meta + u32_meta);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(floor_sum + slabs);
+  const unsigned grid = (unsigned)num_cus() * 4;
+  for (uint64_t r0 = 0; r0 < nitems; r0 += slabs) {
+    const uint32_t nr = (uint32_t)std::min<uint64_t>(slabs, nitems - r0);
+    SpaRound R{wl,   (uint32_t)r0, nr,   meta, meta + slabs + 1, meta + 2 * (slabs + 1), base, spa_keys,
+               hist, floors ? floor_sum : nullptr};
+    LP_HIP(hipMemsetAsync(R.nkeys, 0, (size_t)nr * 4, st));
+    hipLaunchKernelGGL(spa_pieces_kernel, dim3(1), dim3(1024), 0, st, R, 0);
+    hipLaunchKernelGGL((spa_split_acc_kernel<kW, kQuery, kSampled>), dim3(grid), dim3(kSpaThreads), 0, st, gv,
+                       E, R);
+    hipLaunchKernelGGL((spa_split_excl_kernel<kW, kQuery, kSampled>), dim3(nr), dim3(kSpaThreads), 0, st, gv, E,
+                       R);
+    hipLaunchKernelGGL(spa_pieces_kernel, dim3(1), dim3(1024), 0, st, R, 1);
+    if (floors) {
+      LP_HIP(hipMemsetAsync(hist, 0, (size_t)nr * kSumBins * 4, st));
+      hipLaunchKernelGGL((spa_split_hist_kernel<kW, kQuery, kSampled>), dim3(grid), dim3(kSpaThreads), 0, st,
+                         gv, E, R);
+      hipLaunchKernelGGL(spa_split_floor_kernel, dim3(nr), dim3(64), 0, st, R, E.kq);
+    }
+    hipLaunchKernelGGL((spa_split_sweep_kernel<kW, kQuery, kSampled>), dim3(grid), dim3(kSpaThreads), 0, st, gv,
+                       E, R);
+    LP_HIP(hipGetLastError());
+  }
   return LP_OK;
 }
 
@@ -2583,6 +2865,7 @@ lp_status run_query(lp_graph* g, Workspace& w, const int32_t* sources, int64_t n
   E.out_count = count;
   E.cap = cap;
   E.q_count = seg_count;
+  E.kq = kq > 0 ? (uint32_t)kq : 0u;
   E.fp = fp;
   E.ovf = ovf;
   E.ovf_rec = ovf_rec;
@@ -2590,12 +2873,23 @@ lp_status run_query(lp_graph* g, Workspace& w, const int32_t* sources, int64_t n
   E.ovf_cap = ovf_cap;
   E.err = err;
   uint32_t ovf_host = 0;
+  // lp_query (not a server slot) keeps the call's statistics
+  const bool own_stats = &w == &g->ws;
+  if (own_stats) g->last = lp_stats{};
+  std::unique_ptr<LaunchClock> clk(own_stats ? new LaunchClock(&g->last) : nullptr);
   if (po.wedges)
-    LP_TRY(run_phase_any<true>(g, w, gv, E, qlists, Q, po.count, 1, 0, &ovf_host, nullptr, st));
+    LP_TRY(run_phase_any<true>(g, w, gv, E, qlists, Q, po.count, 1, 0, &ovf_host, clk.get(), st));
   unsigned long long n_total = 0;
   LP_HIP(hipMemcpyAsync(&n_total, count, 8, hipMemcpyDeviceToHost, st));
   LP_HIP(hipStreamSynchronize(st));
   if (n_total > cap) return set_error(LP_ERR_DEVICE, "query candidate overflow");
+  if (own_stats) {
+    LP_TRY(collect_work(w, &g->last, st));
+    g->last.wedges = po.wedges;
+    g->last.sources = po.sources;
+    for (int b = 0; b < kBuckets; b++) g->last.bucket_sources[b] = po.count[b];
+    g->last.appended = n_total;
+  }
   // sort by (query index asc, score desc, c asc)
   if (n_total > 1) {
     SortSpec sp{};
