@@ -948,6 +948,9 @@ __global__ __launch_bounds__(kSpaThreads) void acc_spa_kernel(GView g, Emit E, W
   __shared__ uint32_t st_c[NW][kSpaStage], st_h[NW][kSpaStage], st_k[NW][kSpaStage],
       st_d[NW][kSpaStage], st_w2[kW ? NW : 1][kW ? kSpaStage : 1];
   __shared__ uint32_t so_s[NW][64], so_a[NW][64], so_c[NW][64];
+  // weighted queries: a histogram of the source's sums and its floor
+  __shared__ uint32_t qh[kW && kQuery ? kSumBins : 1];
+  __shared__ unsigned long long qfloor;
   const int wv = threadIdx.x >> 6;
   uint8_t* mark = s_mark[wv];
   mark[lane_id()] = 0;
@@ -1009,6 +1012,28 @@ __global__ __launch_bounds__(kSpaThreads) void acc_spa_kernel(GView g, Emit E, W
     __threadfence();
     __syncthreads();
     const uint32_t nk = nkeys;
+    // a weighted query keeps only sums at or above the floor of its k_q-th
+    // largest sum's bin (reads through the atomics' coherence point)
+    uint64_t wmin_q = wmin;
+    if constexpr (kW && kQuery) {
+      if (E.kq > 0 && nk > 4 * E.kq) {
+        for (uint32_t b = threadIdx.x; b < kSumBins; b += T) qh[b] = 0;
+        __syncthreads();
+        for (uint32_t t = threadIdx.x; t < nk; t += T) {
+          const uint32_t c = __hip_atomic_load(&K[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const unsigned long long v = __hip_atomic_load(&HW[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (v != 0) atomicAdd(&qh[sum_bin(v)], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x < 64) {
+          const uint64_t f = sum_floor_wave(qh, E.kq);
+          if (threadIdx.x == 0) qfloor = f;
+        }
+        __syncthreads();
+        const uint64_t f = uniform64(qfloor);
+        wmin_q = f > wmin ? f : wmin;
+      }
+    }
     for (uint32_t t0 = 0; t0 < nk; t0 += T) {
       const uint32_t t = t0 + threadIdx.x;
       uint32_t c = 0, h = 0;
@@ -1019,7 +1044,7 @@ __global__ __launch_bounds__(kSpaThreads) void acc_spa_kernel(GView g, Emit E, W
         if (kW) {
           wsum = __hip_atomic_exchange(&HW[c], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           wk.v[4] += wsum != 0 ? 1u : 0u;
-          ok = wsum != 0 && wsum >= wmin;
+          ok = wsum != 0 && wsum >= wmin_q;
         } else {
           h = __hip_atomic_exchange(&H[c], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           wk.v[4] += h != 0 ? 1u : 0u;
@@ -1661,15 +1686,18 @@ static lp_status launch_spa(lp_graph* g, Workspace& w, const GView& gv, const Em
   // the accumulators are left zeroed by every workgroup; the key lists need no init
   char* base = w.global_tab.as<char>();
   uint32_t* spa_keys = reinterpret_cast<uint32_t*>(base + (size_t)w.global_slabs * n * 8);
-  if (ov.ovf) {
-    // overflow records (partitions of sources that filled an LDS table): one
-    // workgroup per record
+  if (ov.ovf || nitems > 2ull * slabs) {
+    // one workgroup per source (or overflow record), its own slab: with many
+    // sources (more than two rounds of slabs) every CU has one and no round
+    // waits for its slowest piece.  Overflow records (partitions of sources
+    // that filled an LDS table) always go here.
     hipLaunchKernelGGL((acc_spa_kernel<kW, kQuery, kSampled>), dim3(slabs), dim3(kSpaThreads), 0, st, gv, E,
                        wl, ov, base, spa_keys);
     LP_HIP(hipGetLastError());
     return LP_OK;
   }
-  // the bucket's sources: rounds of up to `slabs` sources, split over all CUs
+  // few sources (at most two rounds): one workgroup each would leave the GPU
+  // idle behind the largest, so each is split over all CUs
   // meta: poff, koff, nkeys (u32, slabs + 1 each), then per-source floors
   // (u64) and sum histograms (u32, kSumBins each)
   const size_t u32_meta = ((size_t)slabs * 3 + 8 + 1) & ~(size_t)1;

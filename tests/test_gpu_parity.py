@@ -677,3 +677,29 @@ def test_full_size_batch512(lp, batch512):
         a, c, s = got[i]
         ref = oracle.predict(gs[i], 256, "JC", ks[i])
         assert_same_list((a - vs[i], c - vs[i], s), ref, "JC", f"batch graph {i} n={gs[i].n}")
+
+
+@pytest.mark.parametrize("slots", [1, 3, 0, 1 << 20])
+def test_global_path_forms(lp, config1, slots):
+    """The global accumulator runs one workgroup per source when there are
+    more than two rounds of slabs and splits each source over all workgroups
+    otherwise; the workgroup count decides which.  Both forms, for predict
+    and for weighted queries (with their per-source floors), match the
+    oracle."""
+    gr, k = config1
+    src = synth.sample_sources(gr, 30, seed=23, top=6)
+    say(f"[gpu] global path, {slots} slabs")
+    with lp.Graph(gr.offsets, gr.indices) as g:
+        lp.set_tuning(g, lds_wedge_cap=40, global_slots=slots)
+        for m in ("JC", "RA"):
+            ref = oracle.predict(gr, 256, m, k)
+            got = run_predict(lp, g, m, 256, k)
+            assert_same_list(got, ref, m, f"slots={slots}/{m}")
+            assert lp.last_stats(g)["launches"]["global"]["sources"] > 0
+        assert lp.fingerprint(g, None) == oracle.fingerprint(gr, None)
+        for m, kq in (("AA", 5), ("RA", 40)):
+            refq = oracle.query(gr, None, m, src, kq)
+            c, s, cnt = (to_np(x) for x in lp.query(g, src, m, None, kq))
+            for i in range(src.shape[0]):
+                assert_same_query((c[i][: cnt[i]], s[i][: cnt[i]]), refq[i], m,
+                                  f"slots={slots} query {m} src={src[i]}")
