@@ -227,7 +227,7 @@ def test_query(lp, config1, m):
     src = np.concatenate([src, src[:3]])  # repeats are allowed
     say(f"[gpu] query {m} ns={src.shape[0]}")
     with lp.Graph(gr.offsets, gr.indices) as g:
-        for L, kq in ((256, 10), (None, 7), (256, 20000)):
+        for L, kq in ((256, 10), (None, 7), (256, 20000), (None, 1)):
             ref = oracle.query(gr, L, m, src, kq)
             c, s, cnt = lp.query(g, src, m, L, kq)
             c, s, cnt = to_np(c), to_np(s), to_np(cnt)
@@ -703,3 +703,26 @@ def test_global_path_forms(lp, config1, slots):
             for i in range(src.shape[0]):
                 assert_same_query((c[i][: cnt[i]], s[i][: cnt[i]]), refq[i], m,
                                   f"slots={slots} query {m} src={src[i]}")
+
+
+def test_predict_multi_empty_graphs(lp):
+    """Graphs without vertices or without edges inside a union: they return
+    no rows, and their neighbours in the union are unaffected."""
+    gs = synth.chung_lu_batch(3, 200, 2000, seed=31)
+    empty = synth.Graph(np.zeros(1, np.int64), np.zeros(0, np.int32))
+    isolated = synth.Graph(np.zeros(6, np.int64), np.zeros(0, np.int32))  # 5 vertices, no edges
+    parts = [empty, gs[0], isolated, empty, gs[1], gs[2], empty]
+    u, vs = synth.disjoint_union(parts)
+    ks = [0, gs[0].m // 10, 3, 5, gs[1].m // 10, 7, 0]
+    say(f"[gpu] predict_multi with empty graphs n={u.n}")
+    with lp.Graph(u.offsets, u.indices) as g:
+        for budget in (-1, 500):
+            lp.set_tuning(g, sample_budget=budget)
+            res = lp.predict_multi(g, vs, ks, "JC", 256)
+            for i, gr in enumerate(parts):
+                a, c, sc = (to_np(x) for x in res[i])
+                if gr.m == 0:
+                    assert a.shape[0] == 0
+                    continue
+                ref = oracle.predict(gr, 256, "JC", ks[i])
+                assert_same_list((a - vs[i], c - vs[i], sc), ref, "JC", f"graph {i} budget={budget}")
