@@ -726,3 +726,22 @@ def test_predict_multi_empty_graphs(lp):
                     continue
                 ref = oracle.predict(gr, 256, "JC", ks[i])
                 assert_same_list((a - vs[i], c - vs[i], sc), ref, "JC", f"graph {i} budget={budget}")
+
+
+def test_predict_multi_many_graphs(lp):
+    """More graphs than the per-graph histograms hold in LDS (2,500 small
+    graphs): the global-memory counters give the same lists."""
+    gs = synth.chung_lu_batch(2500, 12, 60, seed=41, d_min=3.0, d_max=8.0)
+    u, vs = synth.disjoint_union(gs)
+    ks = [max(1, gr.m // 4) for gr in gs]
+    say(f"[gpu] predict_multi {len(gs)} graphs n={u.n}")
+    rng = np.random.default_rng(43)
+    picks = rng.choice(len(gs), size=150, replace=False)
+    with lp.Graph(u.offsets, u.indices) as g:
+        for budget in (-1, 2000):
+            lp.set_tuning(g, sample_budget=budget)
+            res = lp.predict_multi(g, vs, ks, "JC", 256)
+            for i in picks:
+                a, c, sc = (to_np(x) for x in res[i])
+                ref = oracle.predict(gs[i], 256, "JC", ks[i])
+                assert_same_list((a - vs[i], c - vs[i], sc), ref, "JC", f"graph {i} budget={budget}")
