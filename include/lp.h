@@ -144,7 +144,8 @@ lp_status lp_fingerprint(lp_graph *g, int64_t hub_limit, uint64_t *out, void *hi
  *     (default 65536);
  *   global_slots: workgroups of the global-memory path, each holding a dense
  *     accumulator of 12 bytes per vertex (default: one per compute unit; the
- *     pool is also kept within a quarter of the device memory);
+ *     pool of each workspace is also kept within an eighth of the device
+ *     memory);
  *   sample_budget: wedge budget of the sampling pass that sets the top-k
  *     filter threshold (default: about 0.1% of the call's wedges, clamped to
  *     [2^20, 2^22]; a negative value disables sampling);

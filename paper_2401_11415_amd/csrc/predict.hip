@@ -1673,8 +1673,9 @@ static lp_status launch_spa(lp_graph* g, Workspace& w, const GView& gv, const Em
   const size_t n = (size_t)g->n;
   // pool: one slab of 8n accumulator bytes per workgroup, then as many key
   // lists of 4n; it grows to the launch's workgroup count (at most
-  // cfg.spa_wgs, and at most a quarter of the device memory) and never shrinks
-  const uint64_t mem_cap = std::max<uint64_t>(1, device_memory() / 4 / (n * 12 + 1));
+  // cfg.spa_wgs, and at most an eighth of the device memory, since every
+  // server slot has a workspace of its own) and never shrinks
+  const uint64_t mem_cap = std::max<uint64_t>(1, device_memory() / 8 / (n * 12 + 1));
   const unsigned slabs = (unsigned)std::min<uint64_t>(std::min<uint64_t>(cfg.spa_wgs, nitems), mem_cap);
   if (w.global_slabs < slabs) {
     w.global_tab.release();
