@@ -1797,12 +1797,26 @@ static lp_status collect_work(Workspace& w, lp_stats* S, hipStream_t st) {
   return LP_OK;
 }
 
+// Device values the caller reads after a phase, fetched in the phase's own
+// host round trip (after any overflow launch).
+struct Readback {
+  void* dst[2] = {nullptr, nullptr};
+  const void* src[2] = {nullptr, nullptr};
+  size_t bytes[2] = {0, 0};
+  lp_status issue(hipStream_t st) const {
+    for (int i = 0; i < 2; i++)
+      if (bytes[i]) LP_HIP(hipMemcpyAsync(dst[i], src[i], bytes[i], hipMemcpyDeviceToHost, st));
+    return LP_OK;
+  }
+};
+
 // The whole accumulation for one phase (all buckets, then overflow records).
 template <bool kW, bool kQuery>
 static lp_status run_phase(lp_graph* g, Workspace& w, const GView& gv, const Emit& E0,
                            const SrcRec* lists, uint64_t list_stride, const uint32_t* counts_host,
                            uint32_t stride, int phase, uint32_t* ovf_host_count, LaunchClock* clk,
-                           hipStream_t st, const uint32_t* first = nullptr) {
+                           hipStream_t st, const uint32_t* first = nullptr,
+                           const Readback* rb = nullptr) {
   unsigned long long* work = work_counters(w);
   // The sampling phase launches every bucket with a few sources each: those
   // launches are latency bound and independent, so they run concurrently on
@@ -1860,9 +1874,11 @@ static lp_status run_phase(lp_graph* g, Workspace& w, const GView& gv, const Emi
       LP_HIP(hipStreamWaitEvent(st, w.join[j], 0));
     }
   }
-  // overflow records written by this phase's LDS kernels
+  // overflow records written by this phase's LDS kernels (and, in the same
+  // round trip, the candidate count when the caller wants it)
   uint32_t ovf_total = 0;
   LP_HIP(hipMemcpyAsync(&ovf_total, E0.ovf_count, 4, hipMemcpyDeviceToHost, st));
+  if (rb) LP_TRY(rb->issue(st));
   LP_HIP(hipStreamSynchronize(st));
   if (ovf_total > E0.ovf_cap) return set_error(LP_ERR_OUT_OF_MEMORY, "overflow list exhausted");
   if (ovf_total > *ovf_host_count) {
@@ -1874,6 +1890,7 @@ static lp_status run_phase(lp_graph* g, Workspace& w, const GView& gv, const Emi
     LP_TRY((launch_spa<kW, kQuery, false>(g, w, gv, E, none, ov, ovf_total - *ovf_host_count, st)));
     if (clk) LP_TRY(clk->stop(kBuckets, st));
     *ovf_host_count = ovf_total;
+    if (rb) LP_TRY(rb->issue(st));
     LP_HIP(hipStreamSynchronize(st));
   }
   if (clk) clk->collect();
@@ -1885,12 +1902,12 @@ static lp_status run_phase_any(lp_graph* g, Workspace& w, const GView& gv, const
                                const SrcRec* lists, uint64_t list_stride,
                                const uint32_t* counts_host, uint32_t stride, int phase,
                                uint32_t* ovf_host_count, LaunchClock* clk, hipStream_t st,
-                               const uint32_t* first = nullptr) {
+                               const uint32_t* first = nullptr, const Readback* rb = nullptr) {
   if (E.measure == LP_AA || E.measure == LP_RA)
     return run_phase<true, kQuery>(g, w, gv, E, lists, list_stride, counts_host, stride, phase,
-                                   ovf_host_count, clk, st, first);
+                                   ovf_host_count, clk, st, first, rb);
   return run_phase<false, kQuery>(g, w, gv, E, lists, list_stride, counts_host, stride, phase,
-                                  ovf_host_count, clk, st, first);
+                                  ovf_host_count, clk, st, first, rb);
 }
 
 // Radix select of the k largest keys among entries [base, count) of the
@@ -2136,10 +2153,12 @@ lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int3
   unsigned long long n_sample = 0;
   LaunchClock clk(&S);
   if (sample) {
+    Readback rb;
+    rb.dst[0] = &n_sample;
+    rb.src[0] = count;
+    rb.bytes[0] = 8;
     LP_TRY(run_phase_any<false>(g, w, gv, E, lists, (uint64_t)g->n, pr.out.count,
-                                stride, 1, &ovf_host, &clk, st));
-    LP_HIP(hipMemcpyAsync(&n_sample, count, 8, hipMemcpyDeviceToHost, st));
-    LP_HIP(hipStreamSynchronize(st));
+                                stride, 1, &ovf_host, &clk, st, nullptr, &rb));
     if (n_sample > cap) return set_error(LP_ERR_OUT_OF_MEMORY, "sample exceeded its buffer");
   }
   unsigned long long r_target =
@@ -2154,18 +2173,23 @@ lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int3
         else
           LP_TRY(run_select(g, E.out_s, E.out_a, E.out_c, count, cap, 0, r_target, ts, ta, tc, tau, st));
       }
-      LP_TRY(run_phase_any<false>(g, w, gv, E, lists, (uint64_t)g->n, pr.out.count,
-                                  stride, 2, &ovf_host, &clk, st));
-    } else {
-      LP_TRY(run_phase_any<false>(g, w, gv, E, lists, (uint64_t)g->n, pr.out.count,
-                                  1, 0, &ovf_host, &clk, st));
     }
-    if (retries == 0) LP_HIP(hipEventRecord(tm.ev[2], st));
     unsigned long long n_total = 0;
     uint32_t tau_h[3] = {0, 0, 0};
-    LP_HIP(hipMemcpyAsync(&n_total, count, 8, hipMemcpyDeviceToHost, st));
-    LP_HIP(hipMemcpyAsync(tau_h, tau, 12, hipMemcpyDeviceToHost, st));
-    LP_HIP(hipStreamSynchronize(st));
+    Readback rb;
+    rb.dst[0] = &n_total;
+    rb.src[0] = count;
+    rb.bytes[0] = 8;
+    rb.dst[1] = tau_h;
+    rb.src[1] = tau;
+    rb.bytes[1] = 12;
+    if (sample)
+      LP_TRY(run_phase_any<false>(g, w, gv, E, lists, (uint64_t)g->n, pr.out.count,
+                                  stride, 2, &ovf_host, &clk, st, nullptr, &rb));
+    else
+      LP_TRY(run_phase_any<false>(g, w, gv, E, lists, (uint64_t)g->n, pr.out.count,
+                                  1, 0, &ovf_host, &clk, st, nullptr, &rb));
+    if (retries == 0) LP_HIP(hipEventRecord(tm.ev[2], st));
     if (n_total > cap) {
       if (!sample)
         return set_error(LP_ERR_OUT_OF_MEMORY, "candidate buffer overflow (%llu > %llu)",
@@ -2624,9 +2648,11 @@ lp_status run_predict_multi(lp_graph* g, int64_t ng, const int64_t* vstart, cons
   uint32_t* gid = w.m_gid.as<uint32_t>();
   if (sample) {
     // sampled sources without thresholds, then each graph's threshold
-    LP_TRY(run_phase_any<false>(g, w, gv, E, split_lists, nl, n_samp, 1, 1, &ovf_host, &clk, st, first));
-    LP_HIP(hipMemcpyAsync(&n_sample, count, 8, hipMemcpyDeviceToHost, st));
-    LP_HIP(hipStreamSynchronize(st));
+    Readback rb;
+    rb.dst[0] = &n_sample;
+    rb.src[0] = count;
+    rb.bytes[0] = 8;
+    LP_TRY(run_phase_any<false>(g, w, gv, E, split_lists, nl, n_samp, 1, 1, &ovf_host, &clk, st, first, &rb));
     if (n_sample > cap) return set_error(LP_ERR_OUT_OF_MEMORY, "sample exceeded its buffer");
     LP_HIP(hipMemsetAsync(gcount, 0, (size_t)NG * 4, st));
     uint32_t* ts = w.tmp_s[0].as<uint32_t>();
@@ -2654,15 +2680,18 @@ lp_status run_predict_multi(lp_graph* g, int64_t ng, const int64_t* vstart, cons
   unsigned long long n_total = 0;
   for (int attempt = 0;; attempt++) {
     if (attempt > 4) return set_error(LP_ERR_DEVICE, "per-graph thresholds did not converge");
+    Readback rb;
+    rb.dst[0] = &n_total;
+    rb.src[0] = count;
+    rb.bytes[0] = 8;
     if (sample) {
       LP_HIP(hipMemcpyAsync(count, &n_sample, 8, hipMemcpyHostToDevice, st));
-      LP_TRY(run_phase_any<false>(g, w, gv, E, split_lists, nl, n_rest, 1, 0, &ovf_host, &clk, st));
+      LP_TRY(run_phase_any<false>(g, w, gv, E, split_lists, nl, n_rest, 1, 0, &ovf_host, &clk, st, nullptr,
+                                  &rb));
     } else {
       LP_TRY(run_phase_any<false>(g, w, gv, E, lists, (uint64_t)g->n, pr.out.count, 1, 0, &ovf_host,
-                                  &clk, st));
+                                  &clk, st, nullptr, &rb));
     }
-    LP_HIP(hipMemcpyAsync(&n_total, count, 8, hipMemcpyDeviceToHost, st));
-    LP_HIP(hipStreamSynchronize(st));
     if (n_total > cap) {
       // graphs without a threshold kept more than the buffer holds: the pass
       // counted every entry, so grow to that and run it again
@@ -2906,11 +2935,13 @@ lp_status run_query(lp_graph* g, Workspace& w, const int32_t* sources, int64_t n
   const bool own_stats = &w == &g->ws;
   if (own_stats) g->last = lp_stats{};
   std::unique_ptr<LaunchClock> clk(own_stats ? new LaunchClock(&g->last) : nullptr);
-  if (po.wedges)
-    LP_TRY(run_phase_any<true>(g, w, gv, E, qlists, Q, po.count, 1, 0, &ovf_host, clk.get(), st));
   unsigned long long n_total = 0;
-  LP_HIP(hipMemcpyAsync(&n_total, count, 8, hipMemcpyDeviceToHost, st));
-  LP_HIP(hipStreamSynchronize(st));
+  Readback rb;
+  rb.dst[0] = &n_total;
+  rb.src[0] = count;
+  rb.bytes[0] = 8;
+  if (po.wedges)
+    LP_TRY(run_phase_any<true>(g, w, gv, E, qlists, Q, po.count, 1, 0, &ovf_host, clk.get(), st, nullptr, &rb));
   if (n_total > cap) return set_error(LP_ERR_DEVICE, "query candidate overflow");
   if (own_stats) {
     LP_TRY(collect_work(w, &g->last, st));

@@ -63,3 +63,21 @@ def test_measures_table_matches_header():
     text = open(HEADER).read()
     for i, m in enumerate(lp.MEASURES):
         assert re.search(rf"LP_{m}\s*=\s*{i}\b", text), m
+
+
+def test_tuning_struct_matches_header(lib):
+    """The binding's lp_tuning mirror has the header's fields, in order."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct \{([^}]*)\} lp_tuning;", text, re.S).group(1)
+    want = [(name, int(n) if n else 1) for name, n in re.findall(r"int64_t\s+(\w+)(?:\[(\d+)\])?;", body)]
+    got = [(name, getattr(t, "_length_", 1)) for name, t in lp._Tuning._fields_]
+    assert want == got
+    assert ctypes.sizeof(lp._Tuning) == 8 * sum(n for _, n in want)
+    assert lib.lp_set_tuning(None, None) == 1
+
+
+def test_bucket_defaults_match_header():
+    text = open(HEADER).read()
+    m = re.search(r"bucket_max\[b\].*?\(defaults ([\d, ]+),", text, re.S)
+    assert m is not None
+    assert tuple(int(x) for x in m.group(1).replace(" ", "").split(",")) == lp.BUCKET_MAX_DEFAULT
