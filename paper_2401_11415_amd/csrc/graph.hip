@@ -440,6 +440,14 @@ void release_workspace(Workspace& w) {
   }
   if (w.fork) (void)hipEventDestroy(w.fork);
   w.fork = nullptr;
+  for (auto& e : w.clock_ev) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
+  }
+  for (auto& e : w.timer_ev) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
+  }
 }
 
 void destroy_graph(lp_graph* g) {

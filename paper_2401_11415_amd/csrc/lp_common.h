@@ -90,6 +90,9 @@ struct Workspace {
   hipStream_t side[kSide] = {};
   hipEvent_t fork = nullptr;
   hipEvent_t join[kSide] = {};
+  // timing events of a call (per-launch clock, phase timer), created once
+  hipEvent_t clock_ev[4 * (kNumBuckets + 1)] = {};
+  hipEvent_t timer_ev[4] = {};
 };
 
 }  // namespace lp

@@ -1734,18 +1734,22 @@ static lp_status launch_spa(lp_graph* g, Workspace& w, const GView& gv, const Em
 
 // HIP events around every accumulation launch of a call, on the call's
 // stream; per-bucket device time and launch counts go to the call's stats.
+// The events belong to the workspace (created on its first call), so a call
+// records them and creates none.
+static hipEvent_t* workspace_events(hipEvent_t* ev, int n) {
+  for (int i = 0; i < n; i++)
+    if (!ev[i]) (void)hipEventCreate(&ev[i]);
+  return ev;
+}
+
 struct LaunchClock {
+  static_assert(kBuckets == kNumBuckets, "one clock slot pair per bucket");
   // slots [0, kBuckets]: main pass; [kBuckets + 1, 2 kBuckets + 1]: sampling pass
-  hipEvent_t ev[4 * (kBuckets + 1)] = {};
+  hipEvent_t* ev;
   bool used[2 * (kBuckets + 1)] = {};
   lp_stats* stats = nullptr;
-  explicit LaunchClock(lp_stats* s) : stats(s) {
-    for (auto& e : ev) (void)hipEventCreate(&e);
-  }
-  ~LaunchClock() {
-    for (auto& e : ev)
-      if (e) (void)hipEventDestroy(e);
-  }
+  LaunchClock(lp_stats* s, Workspace& w)
+      : ev(workspace_events(w.clock_ev, 4 * (kBuckets + 1))), stats(s) {}
   // slot kBuckets: the global-path launch for overflowing LDS tables
   lp_status start(int slot, hipStream_t st) {
     used[slot] = true;
@@ -2023,14 +2027,8 @@ static lp_status run_plan(lp_graph* g, int64_t L, PlanResult* pr, hipStream_t st
 }
 
 struct Timer {
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  Timer() {
-    for (auto& e : ev) (void)hipEventCreate(&e);
-  }
-  ~Timer() {
-    for (auto& e : ev)
-      if (e) (void)hipEventDestroy(e);
-  }
+  hipEvent_t* ev;
+  explicit Timer(Workspace& w) : ev(workspace_events(w.timer_ev, 4)) {}
   float ms(int a, int b) {
     float t = 0;
     if (hipEventElapsedTime(&t, ev[a], ev[b]) != hipSuccess) {
@@ -2082,7 +2080,7 @@ lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int3
   lp_stats& S = g->last;
   S = lp_stats{};
   *out_count = 0;
-  Timer tm;
+  Timer tm(w);
   LP_HIP(hipEventRecord(tm.ev[0], st));
   PlanResult pr;
   LP_TRY(run_plan(g, L, &pr, st));
@@ -2151,7 +2149,7 @@ lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int3
   const SrcRec* lists = w.lists.as<SrcRec>();
   uint32_t ovf_host = 0;
   unsigned long long n_sample = 0;
-  LaunchClock clk(&S);
+  LaunchClock clk(&S, w);
   if (sample) {
     Readback rb;
     rb.dst[0] = &n_sample;
@@ -2554,7 +2552,7 @@ lp_status run_predict_multi(lp_graph* g, int64_t ng, const int64_t* vstart, cons
     if (herr) return set_error(LP_ERR_INVALID_GRAPH, "an edge joins two of the graphs");
     w.m_checked = hstart;
   }
-  Timer tm;
+  Timer tm(w);
   LP_HIP(hipEventRecord(tm.ev[0], st));
   PlanResult pr;
   LP_TRY(run_plan(g, L, &pr, st));
@@ -2644,7 +2642,7 @@ lp_status run_predict_multi(lp_graph* g, int64_t ng, const int64_t* vstart, cons
   E.ngraphs = NG;
   uint32_t ovf_host = 0;
   unsigned long long n_sample = 0;
-  LaunchClock clk(&S);
+  LaunchClock clk(&S, w);
   uint32_t* gid = w.m_gid.as<uint32_t>();
   if (sample) {
     // sampled sources without thresholds, then each graph's threshold
@@ -2854,7 +2852,7 @@ lp_status run_fingerprint(lp_graph* g, int64_t L, uint64_t* out, hipStream_t st)
   E.err = err;
   uint32_t ovf_host = 0;
   if (pr.out.wedges) {
-    LaunchClock clk(&S);
+    LaunchClock clk(&S, w);
     LP_TRY(run_phase_any<false>(g, w, view_of(g), E, w.lists.as<SrcRec>(), (uint64_t)g->n,
                                 pr.out.count, 1, 0, &ovf_host, &clk, st));
     LP_TRY(collect_work(w, &S, st));
@@ -2934,7 +2932,7 @@ lp_status run_query(lp_graph* g, Workspace& w, const int32_t* sources, int64_t n
   // lp_query (not a server slot) keeps the call's statistics
   const bool own_stats = &w == &g->ws;
   if (own_stats) g->last = lp_stats{};
-  std::unique_ptr<LaunchClock> clk(own_stats ? new LaunchClock(&g->last) : nullptr);
+  std::unique_ptr<LaunchClock> clk(own_stats ? new LaunchClock(&g->last, w) : nullptr);
   unsigned long long n_total = 0;
   Readback rb;
   rb.dst[0] = &n_total;
