@@ -32,7 +32,7 @@ PAPER_DLH_EDGES_PER_S = 38.1e6  # sk-2005, 2x Xeon Gold 6226R (context only)
 BUCKET_KERNELS = {
     False: {"tiny": "acc_batch_kernel<256, 48, 3072, false, 64, false>",
             "small": "acc_batch_kernel<256, 8, 3072, false, 64, false>",
-            "mid1": "acc_batch_kernel<256, 2, 3072, false, 64, false>",
+            "mid1": "acc_batch_kernel<512, 4, 6144, false, 64, false>",
             "mid2": "acc_lds_kernel<256, 256, 3072, false, false, 64, false>",
             "mid3": "acc_lds_kernel<512, 512, 6144, false, false, 64, false>",
             "large": "acc_lds_kernel<1024, 1024, 14336, false, false, 64, false>",

@@ -1606,7 +1606,8 @@ static lp_status launch_bucket(lp_graph* g, int bucket, const GView& gv, const E
   const uint64_t n = (uint64_t)g->n;
   if (!kQuery && bucket <= kBucketMid1) {
     // batches: Tiny 48 sources (<= 1536 wedges; 32 above 2^26 vertices),
-    // Small 8 (<= 2048), Mid1 2 (<= 2048)
+    // Small 8 (<= 2048), Mid1 4 per 512 lanes for count tables (<= 4096), 2
+    // per 256 lanes for weighted ones (<= 2048)
     // (the tuning may ask for 32 tiny or 4 small sources per workgroup)
     const bool tiny32 = g->tuning.batch_sources[0] == 32;
     const bool small4 = g->tuning.batch_sources[1] == 4;
@@ -1623,6 +1624,9 @@ static lp_status launch_bucket(lp_graph* g, int bucket, const GView& gv, const E
     else if (bucket == kBucketSmall && n <= BatchKey<4>::kMaxN)
       hipLaunchKernelGGL((acc_batch_kernel<256, 4, 3072, kW, 64, kSampled>),
                          dim3(grid_for((nitems + 3) / 4, 1, cus * 8)), dim3(256), 0, st, gv, E, wl);
+    else if (bucket == kBucketMid1 && !kW && n <= BatchKey<4>::kMaxN)
+      hipLaunchKernelGGL((acc_batch_kernel<512, 4, 6144, kW, 64, kSampled>),
+                         dim3(grid_for((nitems + 3) / 4, 1, cus * 4)), dim3(512), 0, st, gv, E, wl);
     else if (bucket == kBucketMid1 && n <= BatchKey<2>::kMaxN)
       hipLaunchKernelGGL((acc_batch_kernel<256, 2, 3072, kW, 64, kSampled>),
                          dim3(grid_for((nitems + 1) / 2, 1, cus * 8)), dim3(256), 0, st, gv, E, wl);
