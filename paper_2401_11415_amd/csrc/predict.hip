@@ -1297,6 +1297,9 @@ struct SelState {
   uint32_t done;
   uint32_t prefix[3];  // boundary key digits found so far (key words, bits above the step)
   uint32_t pad;
+  // this step's reservations: entries emitted in the high half, entries of
+  // the next working set in the low half (each < 2^32: n_cur < 2^32)
+  unsigned long long step_pack;
 };
 
 __device__ inline void step_geom(int step, int* word, int* shift, int* bits) {
@@ -1367,6 +1370,7 @@ __global__ __launch_bounds__(64) void sel_pick_kernel(SelState* st, int step, ui
     st->k_rem = k - above;
     st->prefix[word] |= ((uint32_t)d) << shift;
     st->n_next = 0;
+    st->step_pack = 0;
   }
   __syncthreads();
   for (int i = t; i < 2048; i += 64) hist[i] = 0;
@@ -1375,8 +1379,12 @@ __global__ __launch_bounds__(64) void sel_pick_kernel(SelState* st, int step, ui
 constexpr int kSelItems = 16;  // elements per thread per tile of the partition
 
 // Partition the working set around the chosen digit: larger digits go to the
-// output, the boundary digit to the next working set.  One global atomic per
-// counter per tile of 256 * kSelItems elements.
+// output, the boundary digit to the next working set.  Each block owns a
+// contiguous chunk of tiles of 256 * kSelItems entries: it counts both
+// classes over the chunk (key word only), reserves its two ranges with one
+// 64-bit atomic on step_pack, then classifies again and writes the chunk tile
+// by tile.  Same-address atomics serialise, so there is one per block, not
+// one per tile.
 __global__ __launch_bounds__(256) void sel_partition_kernel(
     const uint32_t* __restrict__ ks, const uint32_t* __restrict__ ka, const uint32_t* __restrict__ kc,
     SelState* st, int step, uint32_t* __restrict__ ns, uint32_t* __restrict__ na,
@@ -1393,67 +1401,88 @@ __global__ __launch_bounds__(256) void sel_partition_kernel(
   const bool take_all = st->take_all != 0;
   const int lane = lane_id(), wid = threadIdx.x >> 6;
   constexpr unsigned long long kTile = 256ull * kSelItems;
-  for (unsigned long long t0 = (unsigned long long)blockIdx.x * kTile; t0 < n;
-       t0 += (unsigned long long)gridDim.x * kTile) {
+  const unsigned long long ntiles = (n + kTile - 1) / kTile;
+  const unsigned long long per = (ntiles + gridDim.x - 1) / gridDim.x;
+  const unsigned long long c_begin = (unsigned long long)blockIdx.x * per * kTile;
+  const unsigned long long c_end = c_begin + per * kTile < n ? c_begin + per * kTile : n;
+  if (c_begin >= c_end) return;  // uniform over the block
+  const uint32_t* kp = word == 0 ? ks : (word == 1 ? ka : kc);
+  const uint32_t kinv = word == 0 ? 0u : ~0u;  // key words 1 and 2 are ~a and ~c
+  // pass 1: the chunk's class counts
+  uint32_t n_o = 0, n_n = 0;
+  for (unsigned long long i = c_begin + threadIdx.x; i < c_end; i += 256) {
+    const uint32_t d = ((kp[i] ^ kinv) >> shift) & mask;
+    n_o += (d > dsel || (take_all && d == dsel)) ? 1u : 0u;
+    n_n += (!take_all && d == dsel) ? 1u : 0u;
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    n_o += __shfl_xor(n_o, o);
+    n_n += __shfl_xor(n_n, o);
+  }
+  if (lane == 0) {
+    w_out[wid] = n_o;
+    w_next[wid] = n_n;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long to = (unsigned long long)w_out[0] + w_out[1] + w_out[2] + w_out[3];
+    const unsigned long long tn = (unsigned long long)w_next[0] + w_next[1] + w_next[2] + w_next[3];
+    const unsigned long long old = (to | tn) ? atomicAdd(&st->step_pack, (to << 32) | tn) : 0ull;
+    b_out = st->n_out + (old >> 32);
+    b_next = old & 0xFFFFFFFFull;
+  }
+  __syncthreads();
+  unsigned long long run_out = b_out, run_next = b_next;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  // pass 2: classify and write, tile by tile.  Entries are ranked in (wave,
+  // item, lane) order, so the lanes of one store write a contiguous run.
+  for (unsigned long long t0 = c_begin; t0 < c_end; t0 += kTile) {
     uint32_t cls = 0;  // 2 bits per item: 1 = out, 2 = next
-    uint32_t c_out = 0, c_next = 0;
+    uint32_t c_out = 0, c_next = 0;  // this wave's totals (uniform)
 #pragma unroll
     for (int j = 0; j < kSelItems; j++) {
       const unsigned long long i = t0 + (unsigned long long)j * 256 + threadIdx.x;
-      if (i < n) {
-        const uint32_t d = (key_word(ks[i], ka[i], kc[i], word) >> shift) & mask;
-        if (d > dsel || (take_all && d == dsel)) {
-          cls |= 1u << (2 * j);
-          c_out++;
-        } else if (d == dsel) {
-          cls |= 2u << (2 * j);
-          c_next++;
-        }
+      uint32_t cl = 0;
+      if (i < c_end) {
+        const uint32_t d = ((kp[i] ^ kinv) >> shift) & mask;
+        cl = (d > dsel || (take_all && d == dsel)) ? 1u : (d == dsel ? 2u : 0u);
       }
+      cls |= cl << (2 * j);
+      c_out += (uint32_t)__popcll(__ballot(cl == 1u));
+      c_next += (uint32_t)__popcll(__ballot(cl == 2u));
     }
-    // offsets: exclusive scans within the wave, then across the 4 waves
-    uint32_t x_out = c_out, x_next = c_next;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t yo = __shfl_up(x_out, o, 64), yn = __shfl_up(x_next, o, 64);
-      if (lane >= o) {
-        x_out += yo;
-        x_next += yn;
-      }
-    }
-    if (lane == 63) {
-      w_out[wid] = x_out;
-      w_next[wid] = x_next;
+    if (lane == 0) {
+      w_out[wid] = c_out;
+      w_next[wid] = c_next;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      const uint32_t to = w_out[0] + w_out[1] + w_out[2] + w_out[3];
-      const uint32_t tn = w_next[0] + w_next[1] + w_next[2] + w_next[3];
-      b_out = to ? atomicAdd(&st->n_out, (unsigned long long)to) : 0ull;
-      b_next = tn ? atomicAdd(&st->n_next, (unsigned long long)tn) : 0ull;
-    }
-    __syncthreads();
-    unsigned long long po = b_out + x_out - c_out, pn = b_next + x_next - c_next;
-    for (int w = 0; w < wid; w++) {
-      po += w_out[w];
-      pn += w_next[w];
+    unsigned long long po = run_out, pn = run_next;
+    for (int w = 0; w < 4; w++) {
+      if (w < wid) {
+        po += w_out[w];
+        pn += w_next[w];
+      }
+      run_out += w_out[w];
+      run_next += w_next[w];
     }
 #pragma unroll
     for (int j = 0; j < kSelItems; j++) {
       const uint32_t cl = (cls >> (2 * j)) & 3u;
-      if (cl == 0) continue;
+      const uint64_t bo = __ballot(cl == 1u), bn = __ballot(cl == 2u);
       const unsigned long long i = t0 + (unsigned long long)j * 256 + threadIdx.x;
-      if (cl == 1) {
-        os[po] = ks[i];
-        oa[po] = ka[i];
-        oc[po] = kc[i];
-        po++;
-      } else {
-        ns[pn] = ks[i];
-        na[pn] = ka[i];
-        nc[pn] = kc[i];
-        pn++;
+      if (cl == 1u) {
+        const unsigned long long q = po + (unsigned long long)__popcll(bo & lt);
+        os[q] = ks[i];
+        oa[q] = ka[i];
+        oc[q] = kc[i];
+      } else if (cl == 2u) {
+        const unsigned long long q = pn + (unsigned long long)__popcll(bn & lt);
+        ns[q] = ks[i];
+        na[q] = ka[i];
+        nc[q] = kc[i];
       }
+      po += (unsigned long long)__popcll(bo);
+      pn += (unsigned long long)__popcll(bn);
     }
     __syncthreads();
   }
@@ -1461,6 +1490,8 @@ __global__ __launch_bounds__(256) void sel_partition_kernel(
 
 __global__ void sel_advance_kernel(SelState* st, int last_step) {
   if (st->done) return;
+  st->n_out += st->step_pack >> 32;
+  st->n_next = st->step_pack & 0xFFFFFFFFull;
   if (st->take_all || last_step) {
     st->done = 1;
     return;
@@ -2062,20 +2093,53 @@ static lp_status ensure_ovf(Workspace& w, uint32_t** ovf, void** ovf_rec, uint32
 }
 
 // number of buffer entries whose key is >= tau
+constexpr int kGeItems = 8;  // keys per thread per round of count_ge_kernel
+
+// Number of keys >= tau.  Each round a block takes a contiguous tile of
+// 256 * kGeItems keys with all of a thread's score loads in flight; the
+// block's count reaches the global counter with one atomic (same-address
+// atomics serialise, so their number is kept to the grid size).
 __global__ __launch_bounds__(256) void count_ge_kernel(const uint32_t* __restrict__ ks,
                                                        const uint32_t* __restrict__ ka,
                                                        const uint32_t* __restrict__ kc,
                                                        unsigned long long n, const uint32_t* tau,
                                                        unsigned long long* out) {
+  __shared__ unsigned long long part[4];
   const uint32_t t0 = tau[0], t1 = tau[1], t2 = tau[2];
+  // a threshold (s, 0, 0) is met by every key of score >= s: the id words
+  // are then never read
+  const bool score_only = (t1 | t2) == 0;
   unsigned long long c = 0;
-  for (unsigned long long i = (unsigned long long)blockIdx.x * 256 + threadIdx.x; i < n;
-       i += (unsigned long long)gridDim.x * 256) {
-    const uint32_t s = ks[i], a = ~ka[i], x = ~kc[i];
-    c += (s > t0 || (s == t0 && (a > t1 || (a == t1 && x >= t2)))) ? 1ull : 0ull;
+  for (unsigned long long base = (unsigned long long)blockIdx.x * (256 * kGeItems) + threadIdx.x;
+       base < n; base += (unsigned long long)gridDim.x * (256 * kGeItems)) {
+    uint32_t s[kGeItems];
+#pragma unroll
+    for (int j = 0; j < kGeItems; j++) {
+      const unsigned long long i = base + (unsigned long long)j * 256;
+      s[j] = i < n ? ks[i] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kGeItems; j++) {
+      const unsigned long long i = base + (unsigned long long)j * 256;
+      if (i >= n) continue;
+      bool ge = s[j] > t0;
+      if (s[j] == t0) {
+        if (score_only) ge = true;
+        else {
+          const uint32_t a = ~ka[i], x = ~kc[i];
+          ge = a > t1 || (a == t1 && x >= t2);
+        }
+      }
+      c += ge ? 1ull : 0ull;
+    }
   }
   for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o);
-  if (lane_id() == 0 && c) atomicAdd(out, c);
+  if (lane_id() == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long t = part[0] + part[1] + part[2] + part[3];
+    if (t) atomicAdd(out, t);
+  }
 }
 
 lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int32_t* out_a,
@@ -2209,8 +2273,9 @@ lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int3
       // at least k of them are
       unsigned long long* ge = fp;  // scratch counter
       LP_HIP(hipMemsetAsync(ge, 0, 8, st));
-      hipLaunchKernelGGL(count_ge_kernel, dim3(grid_for(n_total, 256, num_cus() * 4)), dim3(256), 0,
-                         st, E.out_s, E.out_a, E.out_c, n_total, (const uint32_t*)tau, ge);
+      hipLaunchKernelGGL(count_ge_kernel, dim3(grid_for(n_total, 256 * kGeItems, num_cus() * 2)),
+                         dim3(256), 0, st, E.out_s, E.out_a, E.out_c, n_total,
+                         (const uint32_t*)tau, ge);
       LP_HIP(hipGetLastError());
       unsigned long long nge = 0;
       LP_HIP(hipMemcpyAsync(&nge, ge, 8, hipMemcpyDeviceToHost, st));
