@@ -227,13 +227,15 @@ lp_status scan_inclusive_u32_u64(const uint32_t* in, uint64_t* out, int64_t n, D
 }
 
 // ---------------------------------------------------------------------------
-// Stable LSD radix sort: 8-bit digits, tiles of 4096 records per workgroup.
+// Stable LSD radix sort: 8-bit digits, tiles of 2048 records per workgroup
+// (the scatter stages a tile in LDS, 8 KB per record word, so small tiles
+// let five workgroups share a CU for three-word records).
 // Pass = per-tile digit histogram -> digit-major exclusive scan -> stable
 // scatter through LDS.
 // ---------------------------------------------------------------------------
 
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;
+constexpr int kSortItems = 8;
 constexpr int kSortTile = kSortThreads * kSortItems;
 
 struct PassArgs {
@@ -250,23 +252,33 @@ __device__ inline uint32_t digit_of(const PassArgs& p, int64_t i) {
   return (k >> p.shift) & 255u;
 }
 
+// Per-tile digit histogram.  Lanes add into kCountCopies histograms by lane
+// number (rows padded to spread them over the LDS banks), so a run of equal
+// digits (equal scores are common) serialises over 64 / kCountCopies lanes
+// instead of the whole wave.
+constexpr int kCountCopies = 16;
+
 __global__ __launch_bounds__(kSortThreads) void radix_count_kernel(PassArgs p, int64_t n,
                                                                    uint32_t* __restrict__ counts,
                                                                    int64_t ntiles) {
-  __shared__ uint32_t hist[256];
-  hist[threadIdx.x] = 0;
+  __shared__ uint32_t hist[kCountCopies][257];
+  for (int j = 0; j < kCountCopies; j++) hist[j][threadIdx.x] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  uint32_t* mine = hist[threadIdx.x % kCountCopies];
 #pragma unroll 4
   for (int r = 0; r < kSortItems; r++) {
     int64_t i = base + (int64_t)r * kSortThreads + threadIdx.x;
-    if (i < n) atomicAdd(&hist[digit_of(p, i)], 1u);
+    if (i < n) atomicAdd(&mine[digit_of(p, i)], 1u);
   }
   __syncthreads();
-  counts[(int64_t)threadIdx.x * ntiles + blockIdx.x] = hist[threadIdx.x];
+  uint32_t tot = 0;
+#pragma unroll
+  for (int j = 0; j < kCountCopies; j++) tot += hist[j][threadIdx.x];
+  counts[(int64_t)threadIdx.x * ntiles + blockIdx.x] = tot;
 }
 
-// Stable scatter of one tile: every wave ranks its 1024 records by digit
+// Stable scatter of one tile: every wave ranks its quarter of the tile by digit
 // (ballot match per round of 64, running per-digit counts in LDS), the tile
 // is staged in LDS in digit order, and the staged records leave in runs of
 // equal digits, so that neighbouring lanes write neighbouring addresses.
@@ -286,7 +298,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(PassArgs p,
                                                                      int64_t ntiles) {
   __shared__ ScatterLds<NW> L;
   constexpr int kWaves = kSortThreads / 64;
-  constexpr int kRounds = kSortTile / kWaves / 64;  // 16 rounds of 64 records per wave
+  constexpr int kRounds = kSortTile / kWaves / 64;  // rounds of 64 records per wave
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int w = 0; w < kWaves; w++) L.wcnt[w][threadIdx.x] = 0;
