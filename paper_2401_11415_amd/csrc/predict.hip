@@ -1818,10 +1818,7 @@ static unsigned long long* work_counters(Workspace& w) {
 }
 constexpr int kSampledWork = 8 * 8;  // offset of the sampling pass's counters
 
-static lp_status collect_work(Workspace& w, lp_stats* S, hipStream_t st) {
-  unsigned long long h[2 * kSampledWork];
-  LP_HIP(hipMemcpyAsync(h, work_counters(w), sizeof(h), hipMemcpyDeviceToHost, st));
-  LP_HIP(hipStreamSynchronize(st));
+static void fill_work(const unsigned long long* h, lp_stats* S) {
   for (int p = 0; p < 2; p++) {
     lp_bucket_stats* arr = p ? S->sampled : S->bucket;
     const unsigned long long* x = h + p * kSampledWork;
@@ -1833,21 +1830,67 @@ static lp_status collect_work(Workspace& w, lp_stats* S, hipStream_t st) {
       arr[b].candidates = x[b * 8 + 4];
     }
   }
-  return LP_OK;
 }
 
 // Device values the caller reads after a phase, fetched in the phase's own
 // host round trip (after any overflow launch).
+// Small device -> host reads of one host round trip.  A copy into pageable
+// memory blocks the host by itself, so the values land in the workspace's
+// pinned buffer (after the plan summary) and reach the caller's variables
+// when finish() has synchronised the stream.
+constexpr size_t kHostStatsBytes = 4096;
+constexpr size_t kStageBase = 256;  // the plan summary sits below
+static_assert(sizeof(PlanOut) <= kStageBase, "plan summary overlaps the readback staging");
+
+struct PinnedReads {
+  static constexpr int kMax = 8;
+  Workspace& w;
+  int n = 0;
+  size_t used = 0;
+  void* dst[kMax];
+  size_t off[kMax], bytes[kMax];
+  explicit PinnedReads(Workspace& ws) : w(ws) {}
+  lp_status add(void* d, const void* src, size_t b, hipStream_t st) {
+    LP_TRY(w.host_stats.ensure(kHostStatsBytes));
+    if (n == kMax || kStageBase + used + b > kHostStatsBytes)
+      return set_error(LP_ERR_DEVICE, "readback staging full");
+    LP_HIP(hipMemcpyAsync(w.host_stats.as<char>() + kStageBase + used, src, b,
+                          hipMemcpyDeviceToHost, st));
+    dst[n] = d;
+    off[n] = kStageBase + used;
+    bytes[n] = b;
+    n++;
+    used = (used + b + 15) & ~(size_t)15;
+    return LP_OK;
+  }
+  lp_status finish(hipStream_t st) {
+    LP_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < n; i++) std::memcpy(dst[i], w.host_stats.as<char>() + off[i], bytes[i]);
+    n = 0;
+    used = 0;
+    return LP_OK;
+  }
+};
+
 struct Readback {
   void* dst[2] = {nullptr, nullptr};
   const void* src[2] = {nullptr, nullptr};
   size_t bytes[2] = {0, 0};
-  lp_status issue(hipStream_t st) const {
+  lp_status issue(PinnedReads& pr, hipStream_t st) const {
     for (int i = 0; i < 2; i++)
-      if (bytes[i]) LP_HIP(hipMemcpyAsync(dst[i], src[i], bytes[i], hipMemcpyDeviceToHost, st));
+      if (bytes[i]) LP_TRY(pr.add(dst[i], src[i], bytes[i], st));
     return LP_OK;
   }
 };
+
+static lp_status collect_work(Workspace& w, lp_stats* S, hipStream_t st) {
+  unsigned long long h[2 * kSampledWork];
+  PinnedReads reads(w);
+  LP_TRY(reads.add(h, work_counters(w), sizeof(h), st));
+  LP_TRY(reads.finish(st));
+  fill_work(h, S);
+  return LP_OK;
+}
 
 // The whole accumulation for one phase (all buckets, then overflow records).
 template <bool kW, bool kQuery>
@@ -1916,9 +1959,10 @@ static lp_status run_phase(lp_graph* g, Workspace& w, const GView& gv, const Emi
   // overflow records written by this phase's LDS kernels (and, in the same
   // round trip, the candidate count when the caller wants it)
   uint32_t ovf_total = 0;
-  LP_HIP(hipMemcpyAsync(&ovf_total, E0.ovf_count, 4, hipMemcpyDeviceToHost, st));
-  if (rb) LP_TRY(rb->issue(st));
-  LP_HIP(hipStreamSynchronize(st));
+  PinnedReads reads(w);
+  LP_TRY(reads.add(&ovf_total, E0.ovf_count, 4, st));
+  if (rb) LP_TRY(rb->issue(reads, st));
+  LP_TRY(reads.finish(st));
   if (ovf_total > E0.ovf_cap) return set_error(LP_ERR_OUT_OF_MEMORY, "overflow list exhausted");
   if (ovf_total > *ovf_host_count) {
     WorkList none{nullptr, 0, 1, 0};
@@ -1929,8 +1973,8 @@ static lp_status run_phase(lp_graph* g, Workspace& w, const GView& gv, const Emi
     LP_TRY((launch_spa<kW, kQuery, false>(g, w, gv, E, none, ov, ovf_total - *ovf_host_count, st)));
     if (clk) LP_TRY(clk->stop(kBuckets, st));
     *ovf_host_count = ovf_total;
-    if (rb) LP_TRY(rb->issue(st));
-    LP_HIP(hipStreamSynchronize(st));
+    if (rb) LP_TRY(rb->issue(reads, st));
+    LP_TRY(reads.finish(st));
   }
   if (clk) clk->collect();
   return LP_OK;
@@ -2044,7 +2088,7 @@ static lp_status run_plan(lp_graph* g, int64_t L, PlanResult* pr, hipStream_t st
   const uint64_t n = (uint64_t)g->n;
   LP_TRY(w.lists.ensure(std::max<uint64_t>(n, 1) * sizeof(SrcRec) * kBuckets));
   LP_TRY(w.stats.ensure(sizeof(PlanOut) + 64));
-  LP_TRY(w.host_stats.ensure(4096));
+  LP_TRY(w.host_stats.ensure(kHostStatsBytes));
   pr->hub = hub_start(g, L);
   PlanOut* d_out = w.stats.as<PlanOut>();
   LP_HIP(hipMemsetAsync(d_out, 0, sizeof(PlanOut), st));
@@ -2290,13 +2334,9 @@ lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int3
     S.retries = retries;
     LP_TRY(run_select(g, E.out_s, E.out_a, E.out_c, count, cap, 0, (unsigned long long)k, os, oa, oc,
                       nullptr, st));
-    SelState hs;
-    LP_HIP(hipMemcpyAsync(&hs, w.sel_state.p, sizeof(SelState), hipMemcpyDeviceToHost, st));
-    LP_HIP(hipStreamSynchronize(st));
-    const uint64_t kout = hs.n_out;
-    if (kout != std::min<uint64_t>((uint64_t)k, n_total))
-      return set_error(LP_ERR_DEVICE, "selection returned %llu of %llu keys",
-                       (unsigned long long)kout, (unsigned long long)std::min<uint64_t>(k, n_total));
+    // the select emits min(k, n_total) keys; its own count is checked in the
+    // call's last round trip
+    const uint64_t kout = std::min<uint64_t>((uint64_t)k, n_total);
     LP_TRY(sort_keys(g, os, oa, oc, kout, id_bits((uint64_t)g->n), id_bits((uint64_t)g->n), st));
     LP_HIP(hipEventRecord(tm.ev[3], st));
     hipPointerAttribute_t at;
@@ -2322,12 +2362,20 @@ lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int3
         LP_HIP(hipMemcpyAsync(out_score, xs, kout * 4, hipMemcpyDefault, st));
       }
     }
+    SelState hs;
     uint32_t herr = 0;
-    LP_HIP(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, st));
-    LP_HIP(hipStreamSynchronize(st));
+    unsigned long long wk[2 * kSampledWork];
+    PinnedReads reads(w);
+    LP_TRY(reads.add(&hs, w.sel_state.p, sizeof(SelState), st));
+    LP_TRY(reads.add(&herr, err, 4, st));
+    LP_TRY(reads.add(wk, work_counters(w), sizeof(wk), st));
+    LP_TRY(reads.finish(st));
+    if (hs.n_out != kout)
+      return set_error(LP_ERR_DEVICE, "selection returned %llu of %llu keys", hs.n_out,
+                       (unsigned long long)kout);
     if (herr) return set_error(LP_ERR_DEVICE, "device error flags 0x%x", herr);
     *out_count = (int64_t)kout;
-    LP_TRY(collect_work(w, &S, st));
+    fill_work(wk, &S);
     S.ms_plan = tm.ms(0, 1);
     S.ms_accumulate = tm.ms(1, 2);
     S.ms_select = tm.ms(2, 3);
@@ -2951,7 +2999,7 @@ lp_status run_query(lp_graph* g, Workspace& w, const int32_t* sources, int64_t n
   LP_TRY(w.q_rows.ensure(Q * sizeof(SrcRec) * kBuckets + 256));
   SrcRec* qlists = w.q_rows.as<SrcRec>();
   LP_TRY(w.stats.ensure(sizeof(PlanOut) + 64));
-  LP_TRY(w.host_stats.ensure(4096));
+  LP_TRY(w.host_stats.ensure(kHostStatsBytes));
   PlanOut* d_out = w.stats.as<PlanOut>();
   LP_HIP(hipMemsetAsync(d_out, 0, sizeof(PlanOut), st));
   const uint32_t hub = hub_start(g, L);
