@@ -2277,7 +2277,9 @@ lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int3
   for (uint64_t retries = 0;; retries++) {
     if (retries > 40) return set_error(LP_ERR_DEVICE, "top-k threshold did not converge");
     if (sample) {
-      LP_HIP(hipMemcpyAsync(count, &n_sample, 8, hipMemcpyHostToDevice, st));
+      // drop the previous pass's appends (the count is n_sample already on
+      // the first pass: it was read back from there)
+      if (retries > 0) LP_HIP(hipMemcpyAsync(count, &n_sample, 8, hipMemcpyHostToDevice, st));
       if (need_tau) {
         if (r_target >= n_sample) LP_HIP(hipMemsetAsync(tau, 0, 12, st));
         else
@@ -2322,8 +2324,9 @@ lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int3
                          (const uint32_t*)tau, ge);
       LP_HIP(hipGetLastError());
       unsigned long long nge = 0;
-      LP_HIP(hipMemcpyAsync(&nge, ge, 8, hipMemcpyDeviceToHost, st));
-      LP_HIP(hipStreamSynchronize(st));
+      PinnedReads reads(w);
+      LP_TRY(reads.add(&nge, ge, 8, st));
+      LP_TRY(reads.finish(st));
       if (nge < (unsigned long long)k) {
         r_target = r_target >= n_sample / 4 ? n_sample : r_target * 4;
         need_tau = true;
