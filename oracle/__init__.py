@@ -59,6 +59,8 @@ def _load():
     lib.oracle_score.argtypes = [ctypes.c_int, i64, dbl, i64, i64]
     lib.oracle_pair.restype = ctypes.c_int
     lib.oracle_pair.argtypes = [i64, vp, vp, i64, ctypes.c_int, i64, i64, vp, vp]
+    lib.oracle_pairs.restype = None
+    lib.oracle_pairs.argtypes = [i64, vp, vp, i64, ctypes.c_int, vp, vp, i64, ctypes.c_int, vp, vp, vp]
     lib.oracle_bruteforce.restype = i64
     lib.oracle_bruteforce.argtypes = [i64, vp, vp, i64, ctypes.c_int, vp, vp, vp, vp, i64]
     lib.oracle_source.restype = i64
@@ -112,6 +114,23 @@ def pair(g, L, m, a: int, c: int):
     ok = _load().oracle_pair(g.n, off.ctypes.data, idx.ctypes.data, _hub(L), measure_id(m),
                              a, c, ctypes.addressof(h), ctypes.addressof(s))
     return bool(ok), h.value, s.value
+
+
+def pairs(g, L, m, a, c, threads: int = 0):
+    """``pair`` for many unordered pairs: (is_candidate bool[], h int64[], fp64 score[])."""
+    off, idx = _arrays(g)
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    c = np.ascontiguousarray(c, dtype=np.int32)
+    assert a.shape == c.shape
+    npairs = a.shape[0]
+    ok = np.zeros(max(npairs, 1), np.int8)
+    h = np.zeros(max(npairs, 1), np.int64)
+    s = np.zeros(max(npairs, 1), np.float64)
+    if npairs:
+        _load().oracle_pairs(g.n, off.ctypes.data, idx.ctypes.data, _hub(L), measure_id(m),
+                             a.ctypes.data, c.ctypes.data, npairs, int(threads), ok.ctypes.data,
+                             h.ctypes.data, s.ctypes.data)
+    return ok[:npairs].astype(bool), h[:npairs], s[:npairs]
 
 
 def bruteforce(g, L, m):

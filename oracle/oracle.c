@@ -106,6 +106,15 @@ static void pair_counts(const int64_t *off, const int32_t *idx, int64_t L, int m
   *w = sum;
 }
 
+static int get_threads(int nthreads) {
+#ifdef _OPENMP
+  return nthreads > 0 ? nthreads : omp_get_max_threads();
+#else
+  (void)nthreads;
+  return 1;
+#endif
+}
+
 /* One pair: returns 1 and fills h / score if (a, c) is a candidate. */
 int oracle_pair(int64_t n, const int64_t *off, const int32_t *idx, int64_t L, int m,
                 int64_t a, int64_t c, int64_t *h_out, double *s_out) {
@@ -120,6 +129,22 @@ int oracle_pair(int64_t n, const int64_t *off, const int32_t *idx, int64_t L, in
   if (h == 0) return 0;
   *s_out = oracle_score(m, h, w, deg_of(off, a), deg_of(off, c));
   return 1;
+}
+
+/* oracle_pair over a list of unordered pairs (a[i], c[i]); ok[i] = 1 for a
+ * candidate, with its h and FP64 score.  Used to check a listed pair that
+ * another route reported without re-running a whole prediction. */
+void oracle_pairs(int64_t n, const int64_t *off, const int32_t *idx, int64_t L, int m,
+                  const int32_t *a, const int32_t *c, int64_t np, int nthreads,
+                  int8_t *ok, int64_t *h_out, double *s_out) {
+  int T = get_threads(nthreads);
+#pragma omp parallel for num_threads(T) schedule(dynamic, 64)
+  for (int64_t i = 0; i < np; i++) {
+    int valid = a[i] >= 0 && a[i] < n && c[i] >= 0 && c[i] < n;
+    h_out[i] = 0;
+    s_out[i] = 0.0;
+    ok[i] = valid ? (int8_t)oracle_pair(n, off, idx, L, m, a[i], c[i], &h_out[i], &s_out[i]) : 0;
+  }
 }
 
 /* Every candidate pair a < c; returns the total count, writes up to cap. */
@@ -286,15 +311,6 @@ static int cmp_pred_desc(const void *x, const void *y) {
   if (better(a, b)) return -1;
   if (better(b, a)) return 1;
   return 0;
-}
-
-static int get_threads(int nthreads) {
-#ifdef _OPENMP
-  return nthreads > 0 ? nthreads : omp_get_max_threads();
-#else
-  (void)nthreads;
-  return 1;
-#endif
 }
 
 /*

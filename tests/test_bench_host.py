@@ -63,3 +63,20 @@ def test_algorithmic_bytes_on_a_path():
     full = 8 * 4 + 8 * 6 + 4 * 6 + 4 * 2 + 12 * 2
     assert bench.algorithmic_bytes(deg, None, wedges=2, candidates=2, k_out=2) == full + 4 * 2
     assert bench.algorithmic_bytes(deg, None, 2, 2, 2, normalised=False) == full
+
+
+def test_observed_graph_cache(tmp_path):
+    """The cached observed graph equals a fresh one (same holdout, same k)."""
+    import synth
+    make = lambda: synth.chung_lu(3000, 8.0, 2.3, 3)  # noqa: E731
+    fresh, k = bench.observed_graph(synth, "cl3k", "", make)
+    first, k1 = bench.observed_graph(synth, "cl3k", str(tmp_path), make)
+    assert (tmp_path / "cl3k_obs.npz").exists()
+    again, k2 = bench.observed_graph(synth, "cl3k", str(tmp_path), lambda: None)
+    for g in (first, again):
+        assert np.array_equal(g.offsets, fresh.offsets) and np.array_equal(g.indices, fresh.indices)
+    assert k == k1 == k2 > 0
+
+
+def test_cpu_model_is_a_name():
+    assert isinstance(bench.cpu_model(), str) and bench.cpu_model()

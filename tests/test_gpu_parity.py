@@ -10,8 +10,8 @@ import pytest
 
 import oracle
 import synth
-from lpcheck import (EXACT_MEASURES, assert_same_candidates, assert_same_list, assert_same_query,
-                     assert_sorted_unique, assert_topk_acceptance, say, to_np)
+from lpcheck import (assert_query_rows, assert_same_candidates, assert_same_list, assert_same_query,
+                     say, to_np)
 
 pytestmark = pytest.mark.gpu
 
@@ -98,7 +98,7 @@ def test_random_graphs_all_candidates(lp, seed, kind):
             for m in MEAS:
                 ref = oracle.predict(gr, L, m, tot + 5)
                 got = run_predict(lp, g, m, L, tot + 5)
-                assert_same_list(got, ref, m, f"{kind}{seed}/{m}/L={L}")
+                assert_same_list(got, ref, m, f"{kind}{seed}/{m}/L={L}", graph=gr, L=L)
 
 
 @pytest.fixture(scope="module")
@@ -115,7 +115,7 @@ def test_config1_jaccard_topk(lp, config1, L):
     ref = oracle.predict(gr, L, "JC", k)
     with lp.Graph(gr.offsets, gr.indices) as g:
         got = run_predict(lp, g, "JC", L, k)
-        assert_same_list(got, ref, "JC", f"config1/JC/L={L}")
+        assert_same_list(got, ref, "JC", f"config1/JC/L={L}", graph=gr, L=L)
         st = lp.last_stats(g)
         assert st["wedges"] == oracle.wedges(gr, L)
 
@@ -128,7 +128,7 @@ def test_config1_measures(lp, config1, m):
         for L in (32, 256):
             ref = oracle.predict(gr, L, m, k)
             got = run_predict(lp, g, m, L, k)
-            assert_same_list(got, ref, m, f"config1/{m}/L={L}")
+            assert_same_list(got, ref, m, f"config1/{m}/L={L}", graph=gr, L=L)
 
 
 @pytest.mark.parametrize("L", [0, 1, 2, 16, 256, None])
@@ -151,7 +151,7 @@ def test_global_path_and_partitions(lp, config1):
             for m in ("JC", "RA"):
                 ref = oracle.predict(gr, 256, m, k)
                 got = run_predict(lp, g, m, 256, k)
-                assert_same_list(got, ref, m, f"cap={cap}/{m}")
+                assert_same_list(got, ref, m, f"cap={cap}/{m}", graph=gr, L=256)
             assert lp.fingerprint(g, None) == oracle.fingerprint(gr, None)
             st = lp.last_stats(g)
             assert st["buckets"]["global"] > 0
@@ -161,7 +161,7 @@ def test_global_path_and_partitions(lp, config1):
         for m in ("JC", "AA", "CN"):
             ref = oracle.predict(kb, None, m, 3000)
             got = run_predict(lp, g, m, None, 3000)
-            assert_same_list(got, ref, m, f"K4,12000/{m}")
+            assert_same_list(got, ref, m, f"K4,12000/{m}", graph=kb, L=None)
         assert lp.fingerprint(g, None) == oracle.fingerprint(kb, None)
         st = lp.last_stats(g)
         assert st["buckets"]["large"] > 0
@@ -217,7 +217,7 @@ def test_sampled_threshold_path(lp, config1):
                 for kk in (50, k, 3 * k):
                     ref = oracle.predict(gr, 256, m, kk)
                     got = run_predict(lp, g, m, 256, kk)
-                    assert_same_list(got, ref, m, f"budget={budget}/{m}/k={kk}")
+                    assert_same_list(got, ref, m, f"budget={budget}/{m}/k={kk}", graph=gr, L=256)
 
 
 @pytest.mark.parametrize("m", ["JC", "SC", "AA", "RA", "HP"])
@@ -233,7 +233,8 @@ def test_query(lp, config1, m):
             c, s, cnt = to_np(c), to_np(s), to_np(cnt)
             for i in range(src.shape[0]):
                 row = (c[i][: cnt[i]], s[i][: cnt[i]])
-                assert_same_query(row, ref[i], m, f"query {m} L={L} src={src[i]}")
+                assert_same_query(row, ref[i], m, f"query {m} L={L} src={src[i]}", graph=gr, L=L,
+                                  src=src[i])
 
 
 def test_query_global_path(lp, config1):
@@ -246,8 +247,7 @@ def test_query_global_path(lp, config1):
             ref = oracle.query(gr, None, m, src, 50)
             c, s, cnt = lp.query(g, src, m, None, 50)
             c, s, cnt = to_np(c), to_np(s), to_np(cnt)
-            for i in range(src.shape[0]):
-                assert_same_query((c[i][: cnt[i]], s[i][: cnt[i]]), ref[i], m, f"q-global {m}")
+            assert_query_rows(c, s, cnt, src, ref, m, f"q-global {m}", graph=gr, L=None)
 
 
 def test_determinism(lp, config1):
@@ -273,7 +273,7 @@ def test_edge_cases(lp, config1):
         # threshold: strictly above
         ref = oracle.predict(gr, 256, "JC", k, 0.25)
         got = run_predict(lp, g, "JC", 256, k, 0.25)
-        assert_same_list(got, ref, "JC", "s_th=0.25")
+        assert_same_list(got, ref, "JC", "s_th=0.25", graph=gr, L=256, s_th=0.25)
         assert np.all(got[2] > 0.25)
         # host output pointers
         ref = oracle.predict(gr, 256, "SC", 500)
@@ -358,6 +358,43 @@ def test_full_size_rmat22_topk(lp, rmat22):
     assert_same_list(got, ref, "JC", "R-MAT-22/JC/L=256")
 
 
+def test_full_size_rmat22_digest_l64(lp, rmat22):
+    """The R-MAT-22 candidate-set digest at the smallest hub limit of the
+    sweep's main range (L = 64)."""
+    gr, _ = rmat22
+    say(f"[gpu] R-MAT-22 fingerprint L=64 n={gr.n}")
+    with lp.Graph(gr.offsets, gr.indices) as g:
+        assert lp.fingerprint(g, 64) == oracle.fingerprint(gr, 64)
+
+
+@pytest.mark.parametrize("m", ["AA", "RA", "CN"])
+def test_full_size_rmat22_topk_measures(lp, rmat22, m):
+    """The benchmark graph with the unnormalised measures (DLH, L = 256,
+    k = |held out|): CN exact, AA / RA by the acceptance rule, every pair
+    outside the oracle's list checked by definition."""
+    gr, k = rmat22
+    say(f"[gpu] R-MAT-22 predict {m} L=256 k={k}")
+    with lp.Graph(gr.offsets, gr.indices) as g:
+        got = run_predict(lp, g, m, 256, k)
+    ref = oracle.predict(gr, 256, m, k)
+    assert_same_list(got, ref, m, f"R-MAT-22/{m}/L=256", graph=gr, L=256)
+
+
+@pytest.mark.parametrize("L", [1024, None])
+@pytest.mark.parametrize("m", ["JC", "AA"])
+def test_full_size_rmat22_query_wide(lp, rmat22, m, L):
+    """Ranked lists on R-MAT-22 at L = 1024 and IBase (every intermediate,
+    hubs included) for seeded sources plus the 4 of highest degree: the
+    sources whose wedges go through the global accumulator."""
+    gr, _ = rmat22
+    src = synth.sample_sources(gr, 128, seed=29, top=4)
+    say(f"[gpu] R-MAT-22 query {m} L={L} ns={src.shape[0]}")
+    with lp.Graph(gr.offsets, gr.indices) as g:
+        c, s, cnt = (to_np(x) for x in lp.query(g, src, m, L, 10))
+    refq = oracle.query(gr, L, m, src, 10)
+    assert_query_rows(c, s, cnt, src, refq, m, f"R-MAT-22 query {m} L={L}", graph=gr, L=L)
+
+
 @pytest.mark.parametrize("m", ["JC", "RA"])
 def test_full_size_rmat22_query(lp, rmat22, m):
     """Per-source ranked lists on R-MAT-22 for a seeded sample of sources,
@@ -369,9 +406,7 @@ def test_full_size_rmat22_query(lp, rmat22, m):
         c, s, cnt = lp.query(g, src, m, 256, 10)
         c, s, cnt = to_np(c), to_np(s), to_np(cnt)
     refq = oracle.query(gr, 256, m, src, 10)
-    for i in range(src.shape[0]):
-        assert_same_query((c[i][: cnt[i]], s[i][: cnt[i]]), refq[i], m,
-                          f"R-MAT-22 query {m} src={src[i]}")
+    assert_query_rows(c, s, cnt, src, refq, m, f"R-MAT-22 query {m}", graph=gr, L=256)
 
 
 def test_server_mix_equals_alone(lp, config1):
@@ -409,9 +444,7 @@ def test_server_mix_equals_alone(lp, config1):
                 assert np.array_equal(out[1][i][:n], to_np(s)[i][:n])
         for (src, (m, L, kq)), (out, rec) in list(zip(reqs, results))[:6]:
             ref = oracle.query(gr, L, m, src, kq)
-            for i in range(src.shape[0]):
-                assert_same_query((out[0][i][: out[2][i]], out[1][i][: out[2][i]]), ref[i], m,
-                                  f"server {m} src={src[i]}")
+            assert_query_rows(out[0], out[1], out[2], src, ref, m, f"server {m}", graph=gr, L=L)
 
 
 def test_server_invalid_requests(lp, config1):
@@ -457,7 +490,25 @@ def test_full_size_chung_lu_8m_aa_topk(lp, chung_lu_8m):
     with lp.Graph(gr.offsets, gr.indices) as g:
         got = run_predict(lp, g, "AA", 32, k)
     ref = oracle.predict(gr, 32, "AA", k)
-    assert_same_list(got, ref, "AA", "Chung-Lu 8M/AA/L=32")
+    assert_same_list(got, ref, "AA", "Chung-Lu 8M/AA/L=32", graph=gr, L=32)
+
+
+def test_full_size_chung_lu_8m_digest_l256(lp, chung_lu_8m):
+    gr, _ = chung_lu_8m
+    say(f"[gpu] Chung-Lu 8M fingerprint L=256 n={gr.n}")
+    with lp.Graph(gr.offsets, gr.indices) as g:
+        assert lp.fingerprint(g, 256) == oracle.fingerprint(gr, 256)
+
+
+def test_full_size_chung_lu_8m_ra_topk(lp, chung_lu_8m):
+    """DLH resource allocation at L = 256 (the paper's choice for RA),
+    k = |held out|, as bench.py times it."""
+    gr, k = chung_lu_8m
+    say(f"[gpu] Chung-Lu 8M predict RA L=256 k={k}")
+    with lp.Graph(gr.offsets, gr.indices) as g:
+        got = run_predict(lp, g, "RA", 256, k)
+    ref = oracle.predict(gr, 256, "RA", k)
+    assert_same_list(got, ref, "RA", "Chung-Lu 8M/RA/L=256", graph=gr, L=256)
 
 
 @pytest.mark.parametrize("m", ["RA", "AA", "JC"])
@@ -471,9 +522,7 @@ def test_full_size_chung_lu_8m_query(lp, chung_lu_8m, m):
         c, s, cnt = lp.query(g, src, m, 256, 10)
         c, s, cnt = to_np(c), to_np(s), to_np(cnt)
     ref = oracle.query(gr, 256, m, src, 10)
-    for i in range(src.shape[0]):
-        assert_same_query((c[i][: cnt[i]], s[i][: cnt[i]]), ref[i], m,
-                          f"Chung-Lu 8M query {m} src={src[i]}")
+    assert_query_rows(c, s, cnt, src, ref, m, f"Chung-Lu 8M query {m}", graph=gr, L=256)
 
 
 def test_full_size_rmat24_server(lp):
@@ -493,9 +542,7 @@ def test_full_size_rmat24_server(lp):
             outs = [srv.wait(t)[0] for t in tickets]
     for r, out in zip(reqs, outs):
         ref = oracle.query(gr, 32, "AA", r, 10)
-        for i in range(r.shape[0]):
-            assert_same_query((out[0][i][: out[2][i]], out[1][i][: out[2][i]]), ref[i], "AA",
-                              f"R-MAT-24 server src={r[i]}")
+        assert_query_rows(out[0], out[1], out[2], r, ref, "AA", "R-MAT-24 server", graph=gr, L=32)
 
 
 @pytest.mark.parametrize("budget", [-1, 3000])
@@ -518,7 +565,7 @@ def test_predict_multi_equals_alone(lp, budget):
                 a, c, s = (to_np(x) for x in res[i])
                 got = (a - vs[i], c - vs[i], s)
                 ref = oracle.predict(gr, L, m, ks[i])
-                assert_same_list(got, ref, m, f"multi graph {i} {m} L={L}")
+                assert_same_list(got, ref, m, f"multi graph {i} {m} L={L}", graph=gr, L=L)
                 if m != "AA":
                     with lp.Graph(gr.offsets, gr.indices) as gi:
                         alone = run_predict(lp, gi, m, L, ks[i])
@@ -694,15 +741,13 @@ def test_global_path_forms(lp, config1, slots):
         for m in ("JC", "RA"):
             ref = oracle.predict(gr, 256, m, k)
             got = run_predict(lp, g, m, 256, k)
-            assert_same_list(got, ref, m, f"slots={slots}/{m}")
+            assert_same_list(got, ref, m, f"slots={slots}/{m}", graph=gr, L=256)
             assert lp.last_stats(g)["launches"]["global"]["sources"] > 0
         assert lp.fingerprint(g, None) == oracle.fingerprint(gr, None)
         for m, kq in (("AA", 5), ("RA", 40)):
             refq = oracle.query(gr, None, m, src, kq)
             c, s, cnt = (to_np(x) for x in lp.query(g, src, m, None, kq))
-            for i in range(src.shape[0]):
-                assert_same_query((c[i][: cnt[i]], s[i][: cnt[i]]), refq[i], m,
-                                  f"slots={slots} query {m} src={src[i]}")
+            assert_query_rows(c, s, cnt, src, refq, m, f"slots={slots} query {m}", graph=gr, L=None)
 
 
 def test_predict_multi_empty_graphs(lp):
