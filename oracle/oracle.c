@@ -26,13 +26,13 @@
  *       intersection of two sorted neighbour lists, for every pair (Section
  *       3.3, the baseline approach).
  *   O1  oracle_source / oracle_predict / oracle_query / oracle_fingerprint:
- *       the paper's algorithm (Section 4.1, Algorithm 1): per source a, a
- *       depth-2 traversal that accumulates into a collision-free per-thread
- *       table (a values vector of size |V|, a keys vector and a key count),
- *       skipping c <= a and hub intermediates, then clearing first-order
- *       neighbours, then scoring; per-thread bounded min-heaps of size N_P
- *       followed by a sort and max-heap merge.  Ties are broken by the total
- *       order above so the result is deterministic.
+ *       the same sums gathered by intermediate (Sections 4.1 and 4.2): for a
+ *       source a, every explored neighbour b adds one (or its AA / RA weight)
+ *       to each neighbour c of b, into dense per-thread arrays over the
+ *       vertices; neighbours of a are flagged and never candidates.  The k
+ *       best under the total order above are kept per thread by sorting and
+ *       cutting a bounded buffer, then the threads' sorted lists are merged,
+ *       so the result is deterministic.
  */
 #include <math.h>
 #include <stdint.h>
@@ -170,95 +170,96 @@ int64_t oracle_bruteforce(int64_t n, const int64_t *off, const int32_t *idx, int
 }
 
 /* ---------------------------------------------------------------------- */
-/* O1: the paper's two-hop algorithm                                       */
+/* O1: accumulation by intermediate (Sections 4.1 and 4.2)                 */
 /* ---------------------------------------------------------------------- */
 
-/* collision-free per-thread table: a values vector of size |V| (count and
- * weight), a keys vector and a key count (Section 4.1.3). */
+/* h(a, c) counts the explored vertices adjacent to both a and c.  Summed the
+ * other way round, each explored neighbour b of a adds one to h(a, c) for
+ * every neighbour c of b, so one pass over the explored neighbours of a gives
+ * h(a, c), and the AA / RA sum of the weights of those b, for all c at once.
+ * The sums of the current source live in dense per-thread arrays indexed by
+ * c (a vector of |V| values, as Section 4.1.3 keeps), with a list of the
+ * entries touched so that reading and clearing them costs the work done; a
+ * flag array marks the neighbours of a, which are never candidates (Section
+ * 4.1.4). */
 typedef struct {
-  int64_t *cnt;
-  double *w;
-  int32_t *keys;
-  int64_t nkeys;
-  uint8_t *seen; /* seen[c] != 0 when c is already a key of the current source */
-} table_t;
+  int64_t *h;       /* explored common neighbours with the source */
+  double *w;        /* sum of their AA / RA weights */
+  int32_t *touched; /* entries with h > 0, in order of first touch */
+  int64_t ntouched;
+  uint8_t *adj_a;   /* 1 at the neighbours of the source */
+} sums_t;
 
-static int table_init(table_t *t, int64_t n) {
+static int sums_init(sums_t *t, int64_t n) {
   size_t N = (size_t)(n > 0 ? n : 1);
-  t->cnt = (int64_t *)calloc(N, sizeof(int64_t));
+  t->h = (int64_t *)calloc(N, sizeof(int64_t));
   t->w = (double *)calloc(N, sizeof(double));
-  t->keys = (int32_t *)malloc(N * sizeof(int32_t));
-  t->seen = (uint8_t *)calloc(N, sizeof(uint8_t));
-  t->nkeys = 0;
-  return t->cnt && t->w && t->keys && t->seen;
+  t->touched = (int32_t *)malloc(N * sizeof(int32_t));
+  t->adj_a = (uint8_t *)calloc(N, sizeof(uint8_t));
+  t->ntouched = 0;
+  return t->h && t->w && t->touched && t->adj_a;
 }
-static void table_free(table_t *t) {
-  free(t->cnt); free(t->w); free(t->keys); free(t->seen);
-}
-
-/* mode 0: prediction orientation (skip c <= a, Algorithm 1 scanEdges);
- * mode 1: recommendation for one vertex (skip only c == a). */
-static void scan_edges(table_t *t, const int64_t *off, const int32_t *idx, int m,
-                       int64_t a, int64_t b, int mode) {
-  double wb = oracle_weight(m, deg_of(off, b));
-  for (int64_t e = off[b]; e < off[b + 1]; e++) {
-    int64_t c = idx[e];
-    if (mode == 0 ? c <= a : c == a) continue;
-    if (!t->seen[c]) { t->seen[c] = 1; t->keys[t->nkeys++] = (int32_t)c; }
-    t->cnt[c] += 1;
-    t->w[c] += wb;
-  }
+static void sums_free(sums_t *t) {
+  free(t->h); free(t->w); free(t->touched); free(t->adj_a);
 }
 
-/* Fill the table for source a: traversal, hub filter, first-order clearing. */
-static void fill_source(table_t *t, const int64_t *off, const int32_t *idx, int64_t L, int m,
-                        int64_t a, int mode) {
-  t->nkeys = 0;
+/* The sums of source a.  mode 0 (prediction): every unordered pair is formed
+ * once, by its smaller endpoint, so only c > a is counted (Section 4.1.1);
+ * mode 1 (the recommendations of one vertex): every c != a. */
+static void sums_of(sums_t *t, const int64_t *off, const int32_t *idx, int64_t L, int m, int64_t a,
+                    int mode) {
+  t->ntouched = 0;
   for (int64_t e = off[a]; e < off[a + 1]; e++) {
-    int64_t b = idx[e];
-    if (explored(off, b, L)) scan_edges(t, off, idx, m, a, b, mode);
+    const int64_t b = idx[e];
+    if (!explored(off, b, L)) continue;
+    const double wb = oracle_weight(m, deg_of(off, b));
+    for (int64_t f = off[b]; f < off[b + 1]; f++) {
+      const int64_t c = idx[f];
+      if (c == a || (mode == 0 && c < a)) continue;
+      if (t->h[c] == 0) t->touched[t->ntouched++] = (int32_t)c;
+      t->h[c] += 1;
+      t->w[c] += wb;
+    }
   }
-  /* first-order neighbours are never candidates (Section 4.1.4) */
-  for (int64_t e = off[a]; e < off[a + 1]; e++) {
-    int64_t b = idx[e];
-    t->cnt[b] = 0;
-    t->w[b] = 0.0;
-  }
+  for (int64_t e = off[a]; e < off[a + 1]; e++) t->adj_a[idx[e]] = 1;
 }
 
-static void reset_keys(table_t *t) {
-  for (int64_t i = 0; i < t->nkeys; i++) {
-    int32_t c = t->keys[i];
-    t->cnt[c] = 0;
+/* c is a candidate of the current source: a common explored neighbour and no edge */
+static inline int is_candidate(const sums_t *t, int64_t c) { return t->h[c] > 0 && !t->adj_a[c]; }
+
+static void sums_clear(sums_t *t, const int64_t *off, const int32_t *idx, int64_t a) {
+  for (int64_t i = 0; i < t->ntouched; i++) {
+    const int32_t c = t->touched[i];
+    t->h[c] = 0;
     t->w[c] = 0.0;
-    t->seen[c] = 0;
   }
-  t->nkeys = 0;
+  t->ntouched = 0;
+  for (int64_t e = off[a]; e < off[a + 1]; e++) t->adj_a[idx[e]] = 0;
 }
 
-/* Per-source candidate list (c, h, score), in key-insertion order. */
+/* Per-source candidate list (c, h, score), in order of first touch. */
 int64_t oracle_source(int64_t n, const int64_t *off, const int32_t *idx, int64_t L, int m,
                       int64_t a, int mode, int32_t *out_c, int64_t *out_h, double *out_s,
                       int64_t cap) {
-  table_t t;
-  if (!table_init(&t, n)) { table_free(&t); return -1; }
-  fill_source(&t, off, idx, L, m, a, mode);
+  sums_t t;
+  if (!sums_init(&t, n)) { sums_free(&t); return -1; }
+  sums_of(&t, off, idx, L, m, a, mode);
   int64_t r = 0;
-  for (int64_t i = 0; i < t.nkeys; i++) {
-    int64_t c = t.keys[i];
-    if (t.cnt[c] == 0) continue;
+  for (int64_t i = 0; i < t.ntouched; i++) {
+    const int64_t c = t.touched[i];
+    if (!is_candidate(&t, c)) continue;
     if (r < cap) {
       out_c[r] = (int32_t)c;
-      out_h[r] = t.cnt[c];
-      out_s[r] = oracle_score(m, t.cnt[c], t.w[c], deg_of(off, a), deg_of(off, c));
+      out_h[r] = t.h[c];
+      out_s[r] = oracle_score(m, t.h[c], t.w[c], deg_of(off, a), deg_of(off, c));
     }
     r++;
   }
-  table_free(&t);
+  sums_free(&t);
   return r;
 }
 
-/* ----- prediction lists: bounded min-heaps under the total order ------- */
+/* ----- the k best predictions under the total order --------------------- */
 
 typedef struct {
   float s32;
@@ -266,44 +267,11 @@ typedef struct {
   double s64;
 } pred_t;
 
-/* x ranks before y */
+/* x ranks before y: FP32 score descending, then a, then c ascending */
 static inline int better(const pred_t *x, const pred_t *y) {
   if (x->s32 != y->s32) return x->s32 > y->s32;
   if (x->a != y->a) return x->a < y->a;
   return x->c < y->c;
-}
-
-static void sift_down_min(pred_t *h, int64_t n, int64_t i) {
-  for (;;) {
-    int64_t l = 2 * i + 1, r = l + 1, w = i;
-    if (l < n && better(&h[w], &h[l])) w = l;
-    if (r < n && better(&h[w], &h[r])) w = r;
-    if (w == i) return;
-    pred_t t = h[i]; h[i] = h[w]; h[w] = t;
-    i = w;
-  }
-}
-
-typedef struct {
-  pred_t *v;
-  int64_t size, cap;
-  int heaped;
-} plist_t;
-
-/* Algorithm 1: push until N_P entries, then keep a min-heap and replace the
- * worst entry when a better one arrives. */
-static void plist_add(plist_t *p, pred_t x) {
-  if (p->cap == 0) return;
-  if (p->size < p->cap) {
-    p->v[p->size++] = x;
-    if (p->size == p->cap) {
-      for (int64_t i = p->size / 2 - 1; i >= 0; i--) sift_down_min(p->v, p->size, i);
-      p->heaped = 1;
-    }
-  } else if (better(&x, &p->v[0])) {
-    p->v[0] = x;
-    sift_down_min(p->v, p->size, 0);
-  }
 }
 
 static int cmp_pred_desc(const void *x, const void *y) {
@@ -311,6 +279,44 @@ static int cmp_pred_desc(const void *x, const void *y) {
   if (better(a, b)) return -1;
   if (better(b, a)) return 1;
   return 0;
+}
+
+/* The k best entries offered so far: a buffer of up to 2k entries that is
+ * sorted and cut to its first k whenever it fills.  After a cut, the k-th
+ * entry is a floor: an entry not better than it cannot be among the final k,
+ * so it is not kept. */
+typedef struct {
+  pred_t *v;
+  int64_t n, k;
+  int has_floor;
+  pred_t floor;
+} best_t;
+
+static void best_cut(best_t *b) {
+  qsort(b->v, (size_t)b->n, sizeof(pred_t), cmp_pred_desc);
+  if (b->n > b->k) b->n = b->k;
+  if (b->k > 0 && b->n == b->k) {
+    b->floor = b->v[b->k - 1];
+    b->has_floor = 1;
+  }
+}
+
+static void best_offer(best_t *b, pred_t x) {
+  if (b->k == 0) return;
+  if (b->has_floor && !better(&x, &b->floor)) return;
+  if (b->n == 2 * b->k) {
+    best_cut(b);
+    if (!better(&x, &b->floor)) return;
+  }
+  b->v[b->n++] = x;
+}
+
+static int best_init(best_t *b, int64_t k) {
+  b->k = k > 0 ? k : 0;
+  b->n = 0;
+  b->has_floor = 0;
+  b->v = (pred_t *)malloc((size_t)(2 * b->k > 0 ? 2 * b->k : 1) * sizeof(pred_t));
+  return b->v != NULL;
 }
 
 /*
@@ -331,21 +337,19 @@ int64_t oracle_predict(int64_t n, const int64_t *off, const int32_t *idx, int64_
 }
 
 /* The same restricted to the sources listed (all vertices when sources is
- * NULL): the candidates owned by those sources, top k of them. */
+ * NULL): the candidates owned by those sources, top k of them.  Sources are
+ * shared among threads; each thread keeps the k best of its own, and the
+ * final list is the k best of the threads' sorted lists, merged. */
 int64_t oracle_predict_sources(int64_t n, const int64_t *off, const int32_t *idx, int64_t L,
                                int m, int64_t k, float s_th, int nthreads, const int32_t *sources,
                                int64_t ns, int32_t *out_a, int32_t *out_c, float *out_s32,
                                double *out_s64) {
   int T = get_threads(nthreads);
-  plist_t *P = (plist_t *)calloc((size_t)T, sizeof(plist_t));
-  int failed = 0;
-  for (int t = 0; t < T; t++) {
-    P[t].cap = k;
-    P[t].v = (pred_t *)malloc((size_t)(k > 0 ? k : 1) * sizeof(pred_t));
-    if (!P[t].v) failed = 1;
-  }
+  best_t *B = (best_t *)calloc((size_t)T, sizeof(best_t));
+  int failed = B == NULL;
+  for (int t = 0; !failed && t < T; t++)
+    if (!best_init(&B[t], k)) failed = 1;
   if (!failed) {
-    /* scoring phase: vertices in parallel, dynamic schedule of 2048 (Section 4.1.7) */
 #pragma omp parallel num_threads(T)
     {
 #ifdef _OPENMP
@@ -353,53 +357,55 @@ int64_t oracle_predict_sources(int64_t n, const int64_t *off, const int32_t *idx
 #else
       int tid = 0;
 #endif
-      table_t tb;
-      if (!table_init(&tb, n)) {
+      sums_t sm;
+      if (!sums_init(&sm, n)) {
 #pragma omp atomic write
         failed = 1;
       } else {
 #pragma omp for schedule(dynamic, 2048)
         for (int64_t i = 0; i < ns; i++) {
           const int64_t a = sources ? sources[i] : i;
-          fill_source(&tb, off, idx, L, m, a, 0);
-          for (int64_t i = 0; i < tb.nkeys; i++) {
-            int64_t c = tb.keys[i];
-            if (tb.cnt[c] == 0) continue;
-            double s = oracle_score(m, tb.cnt[c], tb.w[c], deg_of(off, a), deg_of(off, c));
-            float s32 = (float)s;
-            if (!(s32 > s_th)) continue;
+          sums_of(&sm, off, idx, L, m, a, 0);
+          for (int64_t j = 0; j < sm.ntouched; j++) {
+            const int64_t c = sm.touched[j];
+            if (!is_candidate(&sm, c)) continue;
+            const double s = oracle_score(m, sm.h[c], sm.w[c], deg_of(off, a), deg_of(off, c));
+            const float s32 = (float)s;
+            if (!(s32 > s_th)) continue; /* strictly above the score threshold */
             pred_t x = {s32, (int32_t)a, (int32_t)c, s};
-            plist_add(&P[tid], x);
+            best_offer(&B[tid], x);
           }
-          reset_keys(&tb);
+          sums_clear(&sm, off, idx, a);
         }
       }
-      table_free(&tb);
+      sums_free(&sm);
     }
   }
   int64_t r = 0;
   if (!failed) {
-    /* merging phase: sort every per-thread list, then a max-heap merge */
-    for (int t = 0; t < T; t++) qsort(P[t].v, (size_t)P[t].size, sizeof(pred_t), cmp_pred_desc);
+#pragma omp parallel for num_threads(T) schedule(dynamic, 1)
+    for (int t = 0; t < T; t++) best_cut(&B[t]);
+    /* merge the sorted per-thread lists: repeatedly take the best head */
     int64_t *head = (int64_t *)calloc((size_t)T, sizeof(int64_t));
-    while (r < k) {
-      int best = -1;
+    while (head && r < k) {
+      int pick = -1;
       for (int t = 0; t < T; t++) {
-        if (head[t] >= P[t].size) continue;
-        if (best < 0 || better(&P[t].v[head[t]], &P[best].v[head[best]])) best = t;
+        if (head[t] >= B[t].n) continue;
+        if (pick < 0 || better(&B[t].v[head[t]], &B[pick].v[head[pick]])) pick = t;
       }
-      if (best < 0) break;
-      pred_t x = P[best].v[head[best]++];
+      if (pick < 0) break;
+      const pred_t x = B[pick].v[head[pick]++];
       out_a[r] = x.a;
       out_c[r] = x.c;
       out_s32[r] = x.s32;
       out_s64[r] = x.s64;
       r++;
     }
+    if (!head) failed = 1;
     free(head);
   }
-  for (int t = 0; t < T; t++) free(P[t].v);
-  free(P);
+  for (int t = 0; B && t < T; t++) free(B[t].v);
+  free(B);
   return failed ? -1 : r;
 }
 
@@ -415,41 +421,40 @@ int oracle_query(int64_t n, const int64_t *off, const int32_t *idx, int64_t L, i
   int failed = 0;
 #pragma omp parallel num_threads(T)
   {
-    table_t tb;
-    plist_t pl;
-    pl.cap = kq;
-    pl.v = (pred_t *)malloc((size_t)(kq > 0 ? kq : 1) * sizeof(pred_t));
-    if (!table_init(&tb, n) || !pl.v) {
+    sums_t sm;
+    best_t bs;
+    const int ok_b = best_init(&bs, kq);
+    if (!sums_init(&sm, n) || !ok_b) {
 #pragma omp atomic write
       failed = 1;
     } else {
 #pragma omp for schedule(dynamic, 1)
       for (int64_t i = 0; i < ns; i++) {
-        int64_t s = src[i];
-        pl.size = 0;
-        pl.heaped = 0;
-        fill_source(&tb, off, idx, L, m, s, 1);
-        for (int64_t j = 0; j < tb.nkeys; j++) {
-          int64_t c = tb.keys[j];
-          if (tb.cnt[c] == 0) continue;
-          double sc = oracle_score(m, tb.cnt[c], tb.w[c], deg_of(off, s), deg_of(off, c));
-          float s32 = (float)sc;
+        const int64_t s = src[i];
+        bs.n = 0;
+        bs.has_floor = 0;
+        sums_of(&sm, off, idx, L, m, s, 1);
+        for (int64_t j = 0; j < sm.ntouched; j++) {
+          const int64_t c = sm.touched[j];
+          if (!is_candidate(&sm, c)) continue;
+          const double sc = oracle_score(m, sm.h[c], sm.w[c], deg_of(off, s), deg_of(off, c));
+          const float s32 = (float)sc;
           if (!(s32 > s_th)) continue;
-          pred_t x = {s32, 0, (int32_t)c, sc};
-          plist_add(&pl, x);
+          pred_t x = {s32, 0, (int32_t)c, sc}; /* a is the same for all: ties go by c */
+          best_offer(&bs, x);
         }
-        reset_keys(&tb);
-        qsort(pl.v, (size_t)pl.size, sizeof(pred_t), cmp_pred_desc);
-        for (int64_t j = 0; j < pl.size; j++) {
-          out_c[i * kq + j] = pl.v[j].c;
-          out_s32[i * kq + j] = pl.v[j].s32;
-          out_s64[i * kq + j] = pl.v[j].s64;
+        sums_clear(&sm, off, idx, s);
+        best_cut(&bs);
+        for (int64_t j = 0; j < bs.n; j++) {
+          out_c[i * kq + j] = bs.v[j].c;
+          out_s32[i * kq + j] = bs.v[j].s32;
+          out_s64[i * kq + j] = bs.v[j].s64;
         }
-        out_cnt[i] = (int32_t)pl.size;
+        out_cnt[i] = (int32_t)bs.n;
       }
     }
-    table_free(&tb);
-    free(pl.v);
+    sums_free(&sm);
+    if (ok_b) free(bs.v);
   }
   return failed ? -1 : 0;
 }
@@ -475,30 +480,30 @@ int oracle_fingerprint(int64_t n, const int64_t *off, const int32_t *idx, int64_
   int failed = 0;
 #pragma omp parallel num_threads(T) reduction(+ : cnt, sh, sm, wed)
   {
-    table_t tb;
-    if (!table_init(&tb, n)) {
+    sums_t t;
+    if (!sums_init(&t, n)) {
 #pragma omp atomic write
       failed = 1;
     } else {
 #pragma omp for schedule(dynamic, 2048)
       for (int64_t a = 0; a < n; a++) {
-        fill_source(&tb, off, idx, L, M_CN, a, 0);
-        for (int64_t i = 0; i < tb.nkeys; i++) {
-          int64_t c = tb.keys[i];
-          if (tb.cnt[c] == 0) continue;
+        sums_of(&t, off, idx, L, M_CN, a, 0);
+        for (int64_t i = 0; i < t.ntouched; i++) {
+          const int64_t c = t.touched[i];
+          if (!is_candidate(&t, c)) continue;
           cnt += 1;
-          sh += (uint64_t)tb.cnt[c];
-          sm += fp_mix((uint64_t)a, (uint64_t)c, (uint64_t)tb.cnt[c]);
+          sh += (uint64_t)t.h[c];
+          sm += fp_mix((uint64_t)a, (uint64_t)c, (uint64_t)t.h[c]);
         }
         for (int64_t e = off[a]; e < off[a + 1]; e++) {
           int64_t b = idx[e];
           if (!explored(off, b, L)) continue;
           for (int64_t f = off[b]; f < off[b + 1]; f++) wed += (idx[f] > a);
         }
-        reset_keys(&tb);
+        sums_clear(&t, off, idx, a);
       }
     }
-    table_free(&tb);
+    sums_free(&t);
   }
   out[0] = cnt;
   out[1] = sh;

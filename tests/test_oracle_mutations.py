@@ -18,11 +18,11 @@ MUTATIONS = {
     "aa_log10": ("1.0 / log((double)db)", "1.0 / log10((double)db)"),
     "ra_off_by_one": ("1.0 / (double)db", "1.0 / (double)(db + 1)"),
     "hub_strict": ("return deg_of(off, b) <= L;", "return deg_of(off, b) < L;"),
-    "skip_rule": ("if (mode == 0 ? c <= a : c == a) continue;", "if (mode == 0 ? c < a : c == a) continue;"),
-    "no_first_order_clear": ("    t->cnt[b] = 0;\n    t->w[b] = 0.0;\n", "    (void)b;\n"),
+    "skip_rule": ("if (c == a || (mode == 0 && c < a)) continue;", "if (mode == 0 && c < a) continue;"),
+    "no_first_order_clear": ("for (int64_t e = off[a]; e < off[a + 1]; e++) t->adj_a[idx[e]] = 1;", ""),
     "tie_order": ("if (x->a != y->a) return x->a < y->a;", "if (x->a != y->a) return x->a > y->a;"),
-    "threshold_inclusive": ("if (!(s32 > s_th)) continue;\n            pred_t x = {s32, (int32_t)a",
-                            "if (!(s32 >= s_th)) continue;\n            pred_t x = {s32, (int32_t)a"),
+    "threshold_inclusive": ("if (!(s32 > s_th)) continue; /* strictly above the score threshold */",
+                            "if (!(s32 >= s_th)) continue;"),
 }
 
 
