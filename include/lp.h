@@ -68,7 +68,9 @@ typedef enum {
 
 /*
  * Copy a CSR graph to the device and build the resident structures
- * (degree-ordered relabelling and per-arc two-hop bookkeeping).
+ * (degree-ordered relabelling and per-arc two-hop bookkeeping).  The input is
+ * the observed graph of Section 5.1: simple and undirected (self-loops
+ * removed, each edge present in both directions) with 32-bit vertex ids.
  *   n        number of vertices, 0 <= n <= INT32_MAX.
  *   offsets  n+1 int64, offsets[0] == 0, non-decreasing, offsets[n] = arcs
  *            (twice the undirected edge count, < 2^32).  Device or host pointer.
@@ -156,17 +158,27 @@ lp_status lp_fingerprint(lp_graph *g, int64_t hub_limit, uint64_t *out, void *hi
  *   batch_sources[2]: sources sharing one 256-lane workgroup in the tiny
  *     bucket (48 or 32; 48 needs fewer than 2^26 vertices, else 32 is used)
  *     and in the small bucket (8 or 4).
+ *   kernel_shape[2]: the kernel of the small and mid1 buckets in the
+ *     prediction orientation: 1 batches (several sources share a workgroup
+ *     and one LDS table), 2 one source per 64-lane wave (small only), 3 one
+ *     source per 128-lane workgroup, 4 one source per 256-lane workgroup;
+ *     0 keeps the default (batches).
+ *   scratch_limit: largest single device scratch allocation a call on g may
+ *     make, in bytes (0: none); a call that needs more returns
+ *     LP_ERR_OUT_OF_MEMORY, as when the device runs out, and g stays usable.
  * Results do not depend on the knobs.  Errors: LP_ERR_INVALID_ARGUMENT for
  * NULL arguments, negative lds_wedge_cap or global_slots, a bucket_max
- * outside [0, its default] or another batch_sources value; g then keeps its
- * previous knobs. */
+ * outside [0, its default], another batch_sources value, a kernel_shape
+ * outside [0, 4] (2 for the mid1 bucket) or a negative scratch_limit; g then
+ * keeps its previous knobs. */
 typedef struct {
   int64_t lds_wedge_cap;
   int64_t global_slots;
   int64_t sample_budget;
   int64_t bucket_max[5];
   int64_t batch_sources[2];
-  int64_t reserved[2];
+  int64_t kernel_shape[2];
+  int64_t scratch_limit;
 } lp_tuning;
 lp_status lp_set_tuning(lp_graph *g, const lp_tuning *t);
 
@@ -199,7 +211,9 @@ typedef struct {
   uint64_t appended;          /* candidates written to the selection buffer */
   uint64_t retries;           /* extra passes after a threshold estimate missed */
   double ms_plan, ms_accumulate, ms_select, ms_total; /* device time per phase */
-  lp_bucket_stats bucket[8];  /* per bucket (tiny, small, mid1, mid2, mid3, large, global):
+  lp_bucket_stats bucket[8];  /* per bucket (tiny, small, mid1, mid2, mid3, large, global),
+                                 then "split": AA / RA sources whose sums do not fit a
+                                 packed 64-bit slot, run afterwards with 12-byte tables;
                                  the main pass, or the only pass without sampling */
   lp_bucket_stats sampled[8]; /* the sampling pass that estimates the top-k threshold */
 } lp_stats;
@@ -226,12 +240,14 @@ lp_status lp_predict_multi(lp_graph *g, int64_t ngraphs, const int64_t *vstart, 
  * stream with its own device scratch (candidate buffers, tables, sort space).
  * Requests queue until a slot is free; a free slot takes the oldest request
  * and every other queued request with the same measure, hub limit, k_q and
- * threshold, up to max_batch_sources sources and max_batch_paths two-hop
- * paths, and runs them as one query.  The path count of a source s under hub
- * limit L is
- * min(sum over b in Gamma(s) of d_b, d_s * L), an upper bound of its wedges;
- * it bounds the batch's candidate buffer.  A request above either cap
- * runs alone.  Each request's result equals lp_query on that request alone.
+ * threshold whose sources, two-hop paths and device scratch still fit the
+ * caps below, and runs them as one query.  The path count of a source s under
+ * hub limit L is min(sum over b in Gamma(s) of d_b, d_s * L), an upper bound
+ * of its wedges; it bounds the batch's candidate buffer.  A batch's device
+ * scratch is 24 bytes per path (candidates and sort space), the per-source
+ * records and outputs, and 12 bytes per vertex for each source whose paths
+ * plus degree exceed the LDS capacity (a dense global accumulator; at most as
+ * many as a workspace holds).  A request above any cap runs alone.  Each request's result equals lp_query on that request alone.
  * Requests that arrive while batches run join the next batch of the slot that
  * frees first, so work of several requests overlaps on the device.
  * ------------------------------------------------------------------------- */
@@ -241,6 +257,8 @@ typedef struct {
   int32_t slots;             /* concurrent batches, 1..8 (0: 2) */
   int64_t max_batch_sources; /* sources per batch (0: 16384) */
   int64_t max_batch_paths;   /* two-hop paths per batch (0: 2^27) */
+  int64_t max_batch_bytes;   /* device scratch per batch (0: an eighth of the device
+                                memory divided among the slots) */
 } lp_server_config;
 
 typedef struct {
@@ -248,6 +266,7 @@ typedef struct {
   uint64_t batch;          /* batch id (in launch order, from 1) */
   uint32_t batch_requests; /* requests served by that batch */
   uint64_t batch_sources;  /* sources in that batch */
+  uint64_t batch_bytes;    /* that batch's device scratch bound (bytes) */
   double queue_ms;         /* submit -> batch start (host clock) */
   double run_ms;           /* batch start -> results written */
   double total_ms;         /* submit -> results written */

@@ -24,8 +24,10 @@ __all__ = ["MEASURES", "HUB_NONE", "LpError", "Graph", "predict", "predict_multi
 
 MEASURES = ("CN", "JC", "SI", "SC", "HP", "HD", "LHN", "AA", "RA")
 HUB_NONE = (1 << 63) - 1  # L_H = infinity: IBase
-# scheduling buckets of the accumulation, by wedges per source (lp_stats order)
-BUCKETS = ("tiny", "small", "mid1", "mid2", "mid3", "large", "global")
+# scheduling buckets of the accumulation, by wedges per source (lp_stats order),
+# then the row of the 12-byte-table launch for AA / RA sources whose sums do
+# not fit a packed slot
+BUCKETS = ("tiny", "small", "mid1", "mid2", "mid3", "large", "global", "split")
 LP_VALIDATE = 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -44,7 +46,8 @@ class LpError(RuntimeError):
 class _Tuning(ctypes.Structure):
     _fields_ = [("lds_wedge_cap", ctypes.c_int64), ("global_slots", ctypes.c_int64),
                 ("sample_budget", ctypes.c_int64), ("bucket_max", ctypes.c_int64 * 5),
-                ("batch_sources", ctypes.c_int64 * 2), ("reserved", ctypes.c_int64 * 2)]
+                ("batch_sources", ctypes.c_int64 * 2), ("kernel_shape", ctypes.c_int64 * 2),
+                ("scratch_limit", ctypes.c_int64)]
 
 
 class _BucketStats(ctypes.Structure):
@@ -65,12 +68,13 @@ class _Stats(ctypes.Structure):
 
 class _ServerConfig(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_int32), ("max_batch_sources", ctypes.c_int64),
-                ("max_batch_paths", ctypes.c_int64)]
+                ("max_batch_paths", ctypes.c_int64), ("max_batch_bytes", ctypes.c_int64)]
 
 
 class _RequestInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("batch", ctypes.c_uint64),
                 ("batch_requests", ctypes.c_uint32), ("batch_sources", ctypes.c_uint64),
+                ("batch_bytes", ctypes.c_uint64),
                 ("queue_ms", ctypes.c_double), ("run_ms", ctypes.c_double),
                 ("total_ms", ctypes.c_double)]
 
@@ -283,18 +287,29 @@ def fingerprint(g: Graph, hub_limit, stream=None):
 BUCKET_MAX_DEFAULT = (32, 256, 1024, 2048, 4096)
 
 
+# kernel shapes of the small and mid1 buckets (lp_tuning.kernel_shape)
+SHAPES = {"batch": 1, "wave": 2, "workgroup128": 3, "workgroup256": 4}
+
+
 def set_tuning(g: Graph, lds_wedge_cap: int = 0, global_slots: int = 0, sample_budget: int = 0,
-               bucket_max=None, tiny_batch: int = 0, small_batch: int = 0):
+               bucket_max=None, tiny_batch: int = 0, small_batch: int = 0, small_shape=0,
+               mid1_shape=0, scratch_limit: int = 0):
     """Scheduler knobs of g (lp_set_tuning); 0 keeps a knob's default.
     bucket_max: up to five T bounds for tiny .. mid3, each at most its
     default (BUCKET_MAX_DEFAULT); tiny_batch / small_batch: sources per
-    workgroup in the tiny (48 or 32) and small (8 or 4) buckets."""
+    workgroup in the tiny (48 or 32) and small (8 or 4) buckets;
+    small_shape / mid1_shape: the kernel of those buckets, a key of SHAPES
+    or its number ("wave" is for the small bucket only); scratch_limit:
+    largest single scratch allocation of a call, in bytes (forces
+    LP_ERR_OUT_OF_MEMORY above it)."""
     bm = list(bucket_max or [])
     if len(bm) > 5:
         raise ValueError("bucket_max holds at most 5 bounds")
     bm += [0] * (5 - len(bm))
+    shape = [SHAPES[x] if isinstance(x, str) else int(x) for x in (small_shape, mid1_shape)]
     t = _Tuning(lds_wedge_cap, global_slots, sample_budget, (ctypes.c_int64 * 5)(*bm),
-                (ctypes.c_int64 * 2)(tiny_batch, small_batch))
+                (ctypes.c_int64 * 2)(tiny_batch, small_batch), (ctypes.c_int64 * 2)(*shape),
+                scratch_limit)
     _check(load().lp_set_tuning(g.handle, ctypes.byref(t)))
 
 
@@ -318,9 +333,9 @@ class Server:
     count [n]) numpy arrays and the request's timing / batch record."""
 
     def __init__(self, g: Graph, slots: int = 0, max_batch_sources: int = 0,
-                 max_batch_paths: int = 0):
+                 max_batch_paths: int = 0, max_batch_bytes: int = 0):
         lib = load()
-        cfg = _ServerConfig(slots, max_batch_sources, max_batch_paths)
+        cfg = _ServerConfig(slots, max_batch_sources, max_batch_paths, max_batch_bytes)
         h = ctypes.c_void_p()
         _check(lib.lp_server_create(g.handle, ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

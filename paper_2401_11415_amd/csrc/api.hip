@@ -134,6 +134,7 @@ lp_status lp_predict(lp_graph* g, lp_measure m, int64_t hub_limit, int64_t k, fl
     BusyGuard busy(g);
     if (!busy.ok) return set_error(LP_ERR_BUSY, "graph is in use by another thread");
     LP_TRY(select_device(g));
+    ScratchLimit limit(g->tuning.scratch_limit);
     return run_predict(g, (int)m, hub_limit, k, score_threshold, out_a, out_c, out_score, out_count,
                        (hipStream_t)hip_stream);
   });
@@ -162,6 +163,7 @@ lp_status lp_predict_multi(lp_graph* g, int64_t ngraphs, const int64_t* vstart, 
     BusyGuard busy(g);
     if (!busy.ok) return set_error(LP_ERR_BUSY, "graph is in use by another thread");
     LP_TRY(select_device(g));
+    ScratchLimit limit(g->tuning.scratch_limit);
     return run_predict_multi(g, ngraphs, vstart, k, (int)m, hub_limit, score_threshold, out_a, out_c,
                              out_score, out_count, (hipStream_t)hip_stream);
   });
@@ -183,6 +185,7 @@ lp_status lp_query(lp_graph* g, const int32_t* sources, int64_t n_sources, lp_me
     BusyGuard busy(g);
     if (!busy.ok) return set_error(LP_ERR_BUSY, "graph is in use by another thread");
     LP_TRY(select_device(g));
+    ScratchLimit limit(g->tuning.scratch_limit);
     return run_query(g, g->ws, sources, n_sources, (int)m, hub_limit, k_q, score_threshold, out_c,
                      out_score, out_count, (hipStream_t)hip_stream);
   });
@@ -196,6 +199,7 @@ lp_status lp_fingerprint(lp_graph* g, int64_t hub_limit, uint64_t* out, void* hi
     BusyGuard busy(g);
     if (!busy.ok) return set_error(LP_ERR_BUSY, "graph is in use by another thread");
     LP_TRY(select_device(g));
+    ScratchLimit limit(g->tuning.scratch_limit);
     return run_fingerprint(g, hub_limit, out, (hipStream_t)hip_stream);
   });
 }
@@ -203,7 +207,7 @@ lp_status lp_fingerprint(lp_graph* g, int64_t hub_limit, uint64_t* out, void* hi
 lp_status lp_set_tuning(lp_graph* g, const lp_tuning* t) {
   clear_error();
   if (!g || !t) return set_error(LP_ERR_INVALID_ARGUMENT, "NULL argument");
-  if (t->lds_wedge_cap < 0 || t->global_slots < 0)
+  if (t->lds_wedge_cap < 0 || t->global_slots < 0 || t->scratch_limit < 0)
     return set_error(LP_ERR_INVALID_ARGUMENT, "tuning values must be >= 0");
   for (int b = 0; b < 5; b++)
     if (t->bucket_max[b] < 0 || t->bucket_max[b] > lp::kBucketMaxDefault[b])
@@ -211,6 +215,9 @@ lp_status lp_set_tuning(lp_graph* g, const lp_tuning* t) {
   if ((t->batch_sources[0] != 0 && t->batch_sources[0] != 48 && t->batch_sources[0] != 32) ||
       (t->batch_sources[1] != 0 && t->batch_sources[1] != 8 && t->batch_sources[1] != 4))
     return set_error(LP_ERR_INVALID_ARGUMENT, "batch_sources: tiny 48 or 32, small 8 or 4");
+  if (t->kernel_shape[0] < 0 || t->kernel_shape[0] > 4 || t->kernel_shape[1] < 0 || t->kernel_shape[1] > 4 ||
+      t->kernel_shape[1] == 2)
+    return set_error(LP_ERR_INVALID_ARGUMENT, "kernel_shape: small 0-4, mid1 0, 1, 3 or 4");
   g->tuning = *t;
   return LP_OK;
 }

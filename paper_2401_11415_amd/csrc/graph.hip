@@ -171,14 +171,14 @@ __global__ void nz_flag_kernel(const uint32_t* __restrict__ suflen, int64_t arcs
 
 __global__ void nz_compact_kernel(const uint32_t* __restrict__ pos, const uint32_t* __restrict__ suflen,
                                   const uint32_t* __restrict__ adj, const uint32_t* __restrict__ sufstart,
-                                  const uint32_t* __restrict__ psum, int64_t arcs,
-                                  uint32_t* __restrict__ hb, uint32_t* __restrict__ hstart,
-                                  uint32_t* __restrict__ hpsum) {
+                                  const uint32_t* __restrict__ psum, const uint32_t* __restrict__ deg,
+                                  int64_t arcs, uint32_t* __restrict__ hdeg,
+                                  uint32_t* __restrict__ hstart, uint32_t* __restrict__ hpsum) {
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < arcs;
        p += (int64_t)gridDim.x * blockDim.x) {
     if (suflen[p] == 0) continue;
     const uint32_t q = pos[p];
-    hb[q] = adj[p];
+    hdeg[q] = deg[adj[p]];
     hstart[q] = sufstart[p];
     hpsum[q] = psum[p];
   }
@@ -211,7 +211,7 @@ uint32_t hub_start(const lp_graph* g, int64_t L) {
 }
 
 static void free_graph_arrays(lp_graph* g) {
-  uint32_t** arrs[] = {&g->off, &g->adj, &g->hoff, &g->hb, &g->hstart, &g->hpsum,
+  uint32_t** arrs[] = {&g->off, &g->adj, &g->hoff, &g->hdeg, &g->hstart, &g->hpsum,
                        &g->deg, &g->below, &g->perm, &g->rank, &g->deg_first};
   for (auto p : arrs) {
     if (*p) (void)hipFree(*p);
@@ -366,21 +366,21 @@ lp_status build_graph(int64_t n, const int64_t* offsets, const int32_t* indices,
     LP_HIP(hipMemcpyAsync(&H, pos + arcs, 4, hipMemcpyDeviceToHost, st));
     LP_HIP(hipStreamSynchronize(st));
     size_t hbytes = (size_t)std::max<uint32_t>(H, 1) * 4;
-    LP_HIP(hipMalloc((void**)&g->hb, hbytes));
+    LP_HIP(hipMalloc((void**)&g->hdeg, hbytes));
     LP_HIP(hipMalloc((void**)&g->hstart, hbytes));
     LP_HIP(hipMalloc((void**)&g->hpsum, hbytes));
     g->device_bytes += (int64_t)(3 * hbytes);
     g->harcs = H;
     hipLaunchKernelGGL(nz_compact_kernel, dim3(gb), dim3(kThreads), 0, st, pos,
                        d_suflen.as<uint32_t>(), g->adj, d_sufstart.as<uint32_t>(),
-                       d_psum.as<uint32_t>(), arcs, g->hb, g->hstart, g->hpsum);
+                       d_psum.as<uint32_t>(), g->deg, arcs, g->hdeg, g->hstart, g->hpsum);
     LP_HIP(hipGetLastError());
     hipLaunchKernelGGL(nz_offsets_kernel, dim3(blocks_for(n + 1)), dim3(kThreads), 0, st, g->off, pos,
                        n, g->hoff);
     LP_HIP(hipGetLastError());
   } else {
     LP_HIP(hipMemsetAsync(g->hoff, 0, nb, st));
-    LP_HIP(hipMalloc((void**)&g->hb, 4));
+    LP_HIP(hipMalloc((void**)&g->hdeg, 4));
     LP_HIP(hipMalloc((void**)&g->hstart, 4));
     LP_HIP(hipMalloc((void**)&g->hpsum, 4));
   }
@@ -426,7 +426,7 @@ void release_workspace(Workspace& w) {
   DevBuf* all[] = {&w.cnt, &w.wedges, &w.lists, &w.counters, &w.stats, &w.cand_s, &w.cand_a,
                    &w.cand_c, &w.tmp_s[0], &w.tmp_s[1], &w.tmp_a[0], &w.tmp_a[1], &w.tmp_c[0],
                    &w.tmp_c[1], &w.hist, &w.sel_state, &w.sort_tmp[0], &w.sort_tmp[1],
-                   &w.sort_tmp[2], &w.sort_tmp[3], &w.sort_counts, &w.scan_tmp, &w.global_tab, &w.q_src,
+                   &w.sort_tmp[2], &w.sort_tmp[3], &w.sort_counts, &w.scan_tmp, &w.global_tab, &w.unfit, &w.q_src,
                    &w.q_cnt, &w.q_wedges, &w.q_rows, &w.q_out, &w.m_graph, &w.m_gid,
                    &w.m_lists, &w.spa_meta};
   for (auto b : all) b->release();

@@ -14,7 +14,7 @@ struct GView {
   const uint32_t* off;
   const uint32_t* adj;
   const uint32_t* hoff;    // two-hop arc list (arcs with wedges c > a)
-  const uint32_t* hb;
+  const uint32_t* hdeg;    // degree of each arc's intermediate
   const uint32_t* hstart;
   const uint32_t* hpsum;
   const uint32_t* deg;
@@ -51,7 +51,15 @@ struct Emit {
   const uint32_t* gstart;
   uint32_t ngraphs;
   uint32_t kq;  // query: results wanted per source (0: keep every candidate)
+  // packed AA / RA tables (key and fixed-point sum in one 64-bit slot): id
+  // bits of a key (0: 12-byte tables); a source whose sums do not fit is
+  // listed in unfit_rec and accumulated afterwards with 12-byte tables
+  int pk_idbits;
+  void* unfit_rec;  // SrcRec[unfit_cap]
+  uint32_t* unfit_count;
+  uint32_t unfit_cap;
 };
+
 
 // Log-scale bins of a positive fixed-point sum: values below 8 have a bin
 // each, then eight bins per octave (bin order = value order), 496 in all.
@@ -106,6 +114,25 @@ __device__ inline void flush_work(const Emit& E, WorkAcc& wa) {
 }
 
 enum : uint32_t { kErrProbe = 1, kErrOvfList = 2 };
+
+// Hand a whole source to the 12-byte-table launch that follows a packed
+// phase (or, without one, to the global path as an overflow record).
+template <class Rec>
+__device__ inline void hand_unfit(const Emit& E, const Rec& r) {
+  if (E.unfit_rec) {
+    const uint32_t slot = atomicAdd(E.unfit_count, 1u);
+    if (slot < E.unfit_cap) static_cast<Rec*>(E.unfit_rec)[slot] = r;
+    else atomicOr(E.err, kErrOvfList);
+    return;
+  }
+  const uint32_t slot = atomicAdd(E.ovf_count, 1u);
+  if (slot < E.ovf_cap) {
+    static_cast<Rec*>(E.ovf_rec)[slot] = r;
+    E.ovf[slot] = 0u | (1u << 8);
+  } else {
+    atomicOr(E.err, kErrOvfList);
+  }
+}
 
 __device__ inline int lane_id() { return threadIdx.x & 63; }
 
@@ -512,6 +539,37 @@ __device__ inline bool probe_weight(uint32_t* keys, uint64_t* vals, uint32_t S, 
   return !__any(key != kEmpty32);
 }
 
+// Packed weighted table (AA / RA in prediction orientation): one 64-bit slot
+// per key, bit 63 the first-order flag, bits [kb, 63) a fixed-point sum with a
+// per-source number of fraction bits, bits [0, kb) the key; an empty slot
+// holds the key mask kmask = 2^kb - 1 (no key reaches it).  A new key costs
+// one compare-and-swap, like a count table (which is this layout with kb = 32
+// and a sum that counts wedges).
+__device__ inline bool probe_packed(uint64_t* tab, uint32_t S, uint32_t key, uint32_t h, uint64_t inc,
+                                    uint32_t kmask) {
+  const uint64_t empty = kmask;
+  for (uint32_t probe = 0; probe < S; probe++) {
+    if (!__any(key != kEmpty32)) return true;
+    uint64_t old = empty;
+    if (key != kEmpty32)
+      old = atomicCAS((unsigned long long*)&tab[h], (unsigned long long)empty,
+                      (unsigned long long)(inc | key));
+    // lanes without a live key saw old == empty and stay dead
+    const bool same = (key != kEmpty32) & (((uint32_t)old & kmask) == key);
+    if (same) atomicAdd((unsigned long long*)&tab[h], (unsigned long long)inc);
+    key = (same | (old == empty)) ? kEmpty32 : key;
+    h = next_slot(h, S);
+  }
+  return !__any(key != kEmpty32);
+}
+
+// Table modes of the LDS accumulation kernels.
+enum : int {
+  kTabCount = 0,   // (count << 32) | key per 64-bit slot
+  kTabSplit = 1,   // weighted: 32-bit keys and 64-bit fixed-point sums (12 bytes per slot)
+  kTabPacked = 2   // weighted: key and fixed-point sum in one 64-bit slot
+};
+
 // Per-wave list of insertions whose home slot held another key.  Every key
 // gets one probe where it falls; the few that need more wait here and are
 // probed on in batches of up to 64, so that one long probe sequence does not
@@ -526,9 +584,10 @@ struct Retry {
   uint32_t n = 0;
 };
 
-template <bool kW>
+template <int TM>
 __device__ inline bool retry_drain(uint64_t* tab, uint32_t* keys, uint64_t* vals, uint32_t S,
-                                   Retry<kW>& R) {
+                                   Retry<TM != kTabCount>& R, uint32_t kmask = kEmpty32) {
+  constexpr bool kW = TM != kTabCount;
   if (R.n == 0) return true;
   wave_fence();
   const uint32_t l = (uint32_t)lane_id();
@@ -538,22 +597,34 @@ __device__ inline bool retry_drain(uint64_t* tab, uint32_t* keys, uint64_t* vals
   const uint64_t w = (kW && in) ? R.w[l] : 0ull;
   wave_fence();
   R.n = 0;
-  if (kW) return probe_weight(keys, vals, S, key, hv, w);
+  if (TM == kTabSplit) return probe_weight(keys, vals, S, key, hv, w);
+  if (TM == kTabPacked) return probe_packed(tab, S, key, hv, w, kmask);
   return probe_count(tab, S, key, hv & ~kBlocked, (hv & kBlocked) ? kBlocked64 : kSlotOne);
 }
 
 // Add inc to key's entry, inserting the key if absent (key == kEmpty32: no
-// update on this lane).  False if the table is full for some key.
-template <bool kW>
+// update on this lane).  False if the table is full for some key.  kmask:
+// key mask of a packed table.
+template <int TM>
 __device__ inline bool tab_insert(uint64_t* tab, uint32_t* keys, uint64_t* vals, uint32_t S, uint32_t key,
-                                  uint32_t h, uint64_t inc, Retry<kW>& R) {
+                                  uint32_t h, uint64_t inc, Retry<TM != kTabCount>& R,
+                                  uint32_t kmask = kEmpty32) {
   const bool live = key != kEmpty32;
   bool done;
-  if (kW) {
+  if (TM == kTabSplit) {
     uint32_t old = 0;
     if (live) old = atomicCAS(&keys[h], kEmpty32, key);
     done = (old == kEmpty32) | (old == key);
     if (live & done) atomicAdd((unsigned long long*)&vals[h], (unsigned long long)inc);
+  } else if (TM == kTabPacked) {
+    const uint64_t empty = kmask;
+    uint64_t old = empty;
+    if (live)
+      old = atomicCAS((unsigned long long*)&tab[h], (unsigned long long)empty,
+                      (unsigned long long)(inc | key));
+    const bool same = live & (((uint32_t)old & kmask) == key);
+    if (same) atomicAdd((unsigned long long*)&tab[h], (unsigned long long)inc);
+    done = same | (old == empty);
   } else {
     uint64_t old = kSlotEmpty;
     if (live)
@@ -568,12 +639,12 @@ __device__ inline bool tab_insert(uint64_t* tab, uint32_t* keys, uint64_t* vals,
   if (M == 0) return true;
   const uint32_t nf = (uint32_t)__popcll(M);
   bool ok = true;
-  if (R.n + nf > 64) ok = retry_drain<kW>(tab, keys, vals, S, R);
+  if (R.n + nf > 64) ok = retry_drain<TM>(tab, keys, vals, S, R, kmask);
   if (fail) {
     const uint32_t p = R.n + rank_lt(M);
     R.key[p] = key;
     const uint32_t hn = next_slot(h, S);
-    if (kW) {
+    if (TM != kTabCount) {
       R.h[p] = hn;
       R.w[p] = inc;
     } else {
@@ -584,64 +655,73 @@ __device__ inline bool tab_insert(uint64_t* tab, uint32_t* keys, uint64_t* vals,
   return ok;
 }
 
-// Flag the entry of key (kEmpty32: none on this lane) as a first-order
-// neighbour if the key is present.  Runs after every insertion into the table
-// has completed; no two lanes look for the same key, so a plain
-// read-modify-write suffices.  Lookups that meet another key at their home
-// slot continue through the retry list, which must be empty on entry and is
-// emptied by mark_drain.
-template <bool kW>
-__device__ inline void mark_probe(uint64_t* tab, uint32_t* keys, uint64_t* vals, uint32_t S,
-                                  uint32_t key, uint32_t h) {
-  for (uint32_t probe = 0; probe < S; probe++) {
-    if (!__any(key != kEmpty32)) return;
-    uint32_t k = kEmpty32;
-    if (key != kEmpty32) k = kW ? keys[h] : (uint32_t)tab[h];
-    const bool found = (key != kEmpty32) & (k == key);
-    if (found) {
-      if (kW) vals[h] |= kBlocked64W;
-      else tab[h] |= kBlocked64;
+// Key c's home slot in a table of S slots (a mix of the bits, then range
+// reduction to [0, S)).
+__device__ inline uint32_t key_slot(uint32_t c, uint32_t S) {
+  const uint32_t x = (c ^ (c >> 15)) * 0x2C1B3C6Du;
+  return (uint32_t)(((uint64_t)(x ^ (x >> 12)) * S) >> 32);
+}
+
+// K keys per lane at once into a count or packed table: every
+// compare-and-swap is issued before any result is used, so the K LDS round
+// trips overlap; then hits add their increments and misses join the retry
+// list.  Adds commute and a compare-and-swap looks only at the key bits, so
+// the order of the K updates does not matter.  key[u] == kEmpty32: none.
+template <int TM, int K>
+__device__ inline bool tab_insert_k(uint64_t* tab, uint32_t S, const uint32_t (&key)[K],
+                                    const uint64_t (&inc)[K], Retry<TM != kTabCount>& R, uint32_t kmask) {
+  static_assert(TM != kTabSplit, "one 64-bit slot per key");
+  const uint64_t empty = TM == kTabPacked ? (uint64_t)kmask : kSlotEmpty;
+  const uint32_t km = TM == kTabPacked ? kmask : 0xFFFFFFFFu;
+  uint32_t h[K];
+  uint64_t old[K];
+#pragma unroll
+  for (int u = 0; u < K; u++) {
+    h[u] = key_slot(key[u], S);
+    old[u] = empty;
+    if (key[u] != kEmpty32)
+      old[u] = atomicCAS((unsigned long long*)&tab[h[u]], (unsigned long long)empty,
+                         (unsigned long long)(inc[u] | key[u]));
+  }
+  bool ok = true;
+#pragma unroll
+  for (int u = 0; u < K; u++) {
+    const bool live = key[u] != kEmpty32;
+    const bool same = live & (((uint32_t)old[u] & km) == key[u]);
+    if (same) atomicAdd((unsigned long long*)&tab[h[u]], (unsigned long long)inc[u]);
+    const bool fail = live & !same & (old[u] != empty);
+    const uint64_t M = __ballot(fail);
+    if (M == 0) continue;
+    const uint32_t nf = (uint32_t)__popcll(M);
+    if (R.n + nf > 64) ok = retry_drain<TM>(tab, nullptr, nullptr, S, R, kmask) & ok;
+    if (fail) {
+      const uint32_t p = R.n + rank_lt(M);
+      R.key[p] = key[u];
+      const uint32_t hn = next_slot(h[u], S);
+      if (TM == kTabPacked) {
+        R.h[p] = hn;
+        R.w[p] = inc[u];
+      } else {
+        R.h[p] = inc[u] == kSlotOne ? hn : (hn | kBlocked);
+      }
     }
-    key = (found | (k == kEmpty32)) ? kEmpty32 : key;
-    h = next_slot(h, S);
+    R.n += nf;
   }
+  return ok;
 }
 
-template <bool kW>
-__device__ inline void mark_drain(uint64_t* tab, uint32_t* keys, uint64_t* vals, uint32_t S, Retry<kW>& R) {
-  if (R.n == 0) return;
-  wave_fence();
-  const uint32_t l = (uint32_t)lane_id();
-  const uint32_t key = l < R.n ? R.key[l] : kEmpty32;
-  const uint32_t h = l < R.n ? R.h[l] : 0u;
-  wave_fence();
-  R.n = 0;
-  mark_probe<kW>(tab, keys, vals, S, key, h);
+// Whether a source's packed sums fit: a key's sum has at most na terms (one
+// per explored arc), each below 2^e (RA: 1/d_b <= 1/2, e = -1; AA: 1/ln d_b
+// <= 1/ln 2 < 2, e = 1); with F fraction bits and each term rounded to
+// nearest, the sum stays below 2^(ceil(log2 na) + e + F + 1), which must fit
+// the 63 - kb bits above the key.
+__device__ inline bool packed_fits(int m, uint32_t na, int kb, int F) {
+  const int lg = na <= 1 ? 0 : 32 - __clz((int)(na - 1));  // ceil(log2 na)
+  return lg + (m == LP_RA ? -1 : 1) + F + 1 <= 63 - kb;
 }
 
-template <bool kW>
-__device__ inline void tab_mark(uint64_t* tab, uint32_t* keys, uint64_t* vals, uint32_t S, uint32_t key,
-                                uint32_t h, Retry<kW>& R) {
-  const bool live = key != kEmpty32;
-  uint32_t k = kEmpty32;
-  if (live) k = kW ? keys[h] : (uint32_t)tab[h];
-  const bool found = live & (k == key);
-  if (found) {
-    if (kW) vals[h] |= kBlocked64W;
-    else tab[h] |= kBlocked64;
-  }
-  const bool cont = live & !found & (k != kEmpty32);
-  const uint64_t M = __ballot(cont);
-  if (M == 0) return;
-  const uint32_t nf = (uint32_t)__popcll(M);
-  if (R.n + nf > 64) mark_drain<kW>(tab, keys, vals, S, R);
-  if (cont) {
-    const uint32_t p = R.n + rank_lt(M);
-    R.key[p] = key;
-    R.h[p] = next_slot(h, S);
-  }
-  R.n += nf;
-}
+// The fixed-point sum of a packed slot.
+__device__ inline uint64_t packed_sum(uint64_t v, int kb) { return (v << 1) >> (kb + 1); }
 
 // ---------------------------------------------------------------------------
 // Run-length decoding of a chunk of arcs into wedges, one wave at a time.

@@ -58,6 +58,16 @@ struct HostBuf {
   template <class T> T* as() const { return static_cast<T*>(p); }
 };
 
+// Largest single scratch allocation the calling thread's current call may
+// make (0: no limit); a call sets it from its graph's tuning, so that running
+// out of device memory can be forced from the host.
+struct ScratchLimit {
+  static thread_local size_t bytes;
+  size_t saved;
+  explicit ScratchLimit(int64_t limit) : saved(bytes) { bytes = limit > 0 ? (size_t)limit : 0; }
+  ~ScratchLimit() { bytes = saved; }
+};
+
 // ---------------------------------------------------------------------------
 // Resident graph.  Vertices are relabelled by ascending (degree, original id);
 // "new" ids below are ranks in that order.  Ownership of an unordered pair by
@@ -67,6 +77,7 @@ struct HostBuf {
 // ---------------------------------------------------------------------------
 
 constexpr int kNumBuckets = 7;  // scheduling buckets of the accumulation
+constexpr int kStatRows = 8;    // per-launch statistics rows: the buckets, then "split"
 
 struct Workspace {
   // plan
@@ -76,6 +87,7 @@ struct Workspace {
   DevBuf tmp_s[2], tmp_a[2], tmp_c[2];
   DevBuf hist, sel_state, sort_tmp[4], sort_counts, scan_tmp;
   DevBuf global_tab, spa_meta;
+  DevBuf unfit;  // packed AA / RA calls: sources whose sums do not fit a packed slot
   unsigned global_slabs = 0;  // accumulator slabs in global_tab
   // query
   DevBuf q_src, q_cnt, q_wedges, q_rows, q_out;
@@ -91,7 +103,7 @@ struct Workspace {
   hipEvent_t fork = nullptr;
   hipEvent_t join[kSide] = {};
   // timing events of a call (per-launch clock, phase timer), created once
-  hipEvent_t clock_ev[4 * (kNumBuckets + 1)] = {};
+  hipEvent_t clock_ev[4 * (kNumBuckets + 2)] = {};
   hipEvent_t timer_ev[4] = {};
 };
 
@@ -109,7 +121,7 @@ struct lp_graph {
   // two-hop arc list: for every source a, the arcs a->b (b ascending) whose row
   // b holds at least one id > a, i.e. that contribute wedges a-b-c with c > a
   uint32_t* hoff = nullptr;    // n+1 offsets into the list
-  uint32_t* hb = nullptr;      // b
+  uint32_t* hdeg = nullptr;    // degree of b (non-decreasing within a source: ids follow degree)
   uint32_t* hstart = nullptr;  // first position in adj (row b) holding an id > a
   uint32_t* hpsum = nullptr;   // inclusive running total of those suffix lengths within the row
   int64_t harcs = 0;

@@ -8,16 +8,24 @@
 // each remaining key; keep the best N_P pairs overall.
 //
 // GPU design (gfx950, wave64):
-//  * plan: for each source the number of explored arcs (a prefix of its row,
-//    since rows are sorted by degree rank) and its exact wedge count U(a);
-//    sources are bucketed by U(a).
-//  * accumulation: one group of G lanes per source with an open-addressing
-//    hash table in LDS sized 2*U(a) (G = 16, 64, 256 for growing U).  The
-//    wedges of a chunk of G arcs are enumerated as one flat index space so
-//    that lanes read consecutive ids of the same neighbour list (coalesced).
-//    Sources whose table would not fit are split into hash partitions
-//    processed one after the other; the largest sources use a dense
-//    accumulator in global memory.
+//  * plan: for each source its explored arcs (a prefix of its two-hop arc
+//    list, since intermediates are ordered by degree) and its exact wedge
+//    count U(a); sources go to seven buckets by T = U + (first-order
+//    neighbours after a).
+//  * accumulation: small sources run in batches (48, 8 or 4 per workgroup)
+//    that share one LDS hash table keyed by (position in the batch, c);
+//    larger ones get a whole workgroup (256, 512 or 1024 lanes) and a table
+//    sized by a bound on their distinct keys, split into hash partitions when
+//    it exceeds the LDS; sources above the LDS capacity use a dense
+//    accumulator in global memory.  A window decoder turns 64 consecutive
+//    flat wedge indices into (arc, position) pairs with one ballot, so lanes
+//    read consecutive ids of the same neighbour list (coalesced).
+//  * count tables (CN ... LHN) hold (count << 32 | key) per 64-bit slot; AA /
+//    RA tables hold key and fixed-point sum in one 64-bit slot when the
+//    per-source precision bound allows, else 12-byte slots.
+//  * with a top-k threshold, the normalised measures bound the degree (hence
+//    the id) of any candidate that can still pass; rows ascend, so only the
+//    part of each row below that id is read.
 //  * scoring is fused into the table sweep; survivors of S_th and of a key
 //    threshold tau are appended with one atomic per wave.
 //  * top-k: MSD radix select over the 96-bit key (score bits, ~a, ~c), then a
@@ -99,7 +107,10 @@ constexpr int kPlanItems = 16;  // sources per thread of the plan kernel
 
 // Bucket a tile of 256 * kPlanItems sources with one global atomic per
 // (workgroup, bucket); records land in lists[bucket * stride + position].
-__global__ __launch_bounds__(256) void plan_kernel(GView g, uint32_t hub_start, BucketCuts cuts,
+// A source's explored arcs are the prefix of its two-hop arcs whose
+// intermediate has degree < hub_deg (= L + 1, clamped); the list ascends by
+// intermediate, hence by degree.
+__global__ __launch_bounds__(256) void plan_kernel(GView g, uint32_t hub_deg, BucketCuts cuts,
                                                    SrcRec* __restrict__ lists,
                                                    PlanOut* __restrict__ out) {
   __shared__ uint32_t wtot[kBuckets][4];
@@ -118,7 +129,7 @@ __global__ __launch_bounds__(256) void plan_kernel(GView g, uint32_t hub_start, 
       const uint32_t h0 = g.hoff[a], h1 = g.hoff[a + 1];
       uint32_t U = 0, T = 0;
       if (h1 > h0) {
-        const uint32_t k = lower_bound_dev(g.hb, h0, h1, hub_start) - h0;
+        const uint32_t k = lower_bound_dev(g.hdeg, h0, h1, hub_deg) - h0;
         U = k ? g.hpsum[h0 + k - 1] : 0u;
         // the bucket follows the work (wedges), not the key bound: a source
         // with many wedges but few reachable keys still needs many lanes
@@ -181,7 +192,7 @@ __global__ __launch_bounds__(256) void plan_kernel(GView g, uint32_t hub_start, 
     const uint32_t a = (uint32_t)(tile + (uint64_t)j * 256 + threadIdx.x);
     // second read of the row bounds: cheap (cached) and keeps registers low
     const uint32_t h0 = g.hoff[a], h1 = g.hoff[a + 1];
-    const uint32_t k = lower_bound_dev(g.hb, h0, h1, hub_start) - h0;
+    const uint32_t k = lower_bound_dev(g.hdeg, h0, h1, hub_deg) - h0;
     SrcRec r;
     r.a = a;
     r.key = g.perm[a];
@@ -254,9 +265,11 @@ struct WorkList {
   uint32_t count;
   uint32_t stride;
   int phase;
+  const uint32_t* count_dev = nullptr;  // if set: phase 0, count read on the device
 };
 
 __device__ inline uint32_t work_count(const WorkList& w) {
+  if (w.count_dev) return *w.count_dev;
   if (w.phase == 0 || w.stride <= 1) return w.phase == 2 ? 0u : w.count;
   const uint32_t ns = (w.count + w.stride - 1) / w.stride;
   return w.phase == 1 ? ns : w.count - ns;
@@ -280,10 +293,13 @@ __device__ inline SrcRec uniform_rec(const SrcRec& r) {
 // Load the chunk of explored arcs [cb, cb + G) of source s into the group
 // scratch: flat index of its first wedge (excl), position in adj of its first
 // c (start), weight; the chunk covers flat wedges [*lo, *hi).
+// Weights are fixed point with wshift fraction bits, lifted by wlift bits
+// (packed tables keep the key below the sum).
 template <int G, bool kQuery, bool kW>
 __device__ inline void load_chunk(const GView& g, const Emit& E, const SrcRec& s, uint32_t cb,
                                   uint32_t* s_excl, uint32_t* s_start, uint64_t* s_w,
-                                  uint32_t* scan_tmp, uint32_t* lo, uint32_t* hi) {
+                                  uint32_t* scan_tmp, uint32_t* lo, uint32_t* hi, int wshift,
+                                  int wlift = 0) {
   const int gl = threadIdx.x & (G - 1);
   const uint32_t j = cb + gl;
   const bool valid = j < s.na;
@@ -295,7 +311,7 @@ __device__ inline void load_chunk(const GView& g, const Emit& E, const SrcRec& s
       const uint32_t b = g.adj[e];
       start = g.off[b];
       len = g.off[b + 1] - start;
-      if (kW) w = weight_of(E.measure, len, E.shift);
+      if (kW) w = weight_of(E.measure, len, wshift) << wlift;
     }
     uint32_t total;
     const uint32_t ex = group_exclusive_scan<G>(len, scan_tmp, &total);
@@ -307,7 +323,7 @@ __device__ inline void load_chunk(const GView& g, const Emit& E, const SrcRec& s
     if (valid) {
       start = g.hstart[e];
       ex = j == 0 ? 0u : g.hpsum[e - 1];
-      if (kW) w = weight_of(E.measure, g.deg[g.hb[e]], E.shift);
+      if (kW) w = weight_of(E.measure, g.hdeg[e], wshift) << wlift;
     }
     s_excl[gl] = ex;
     const uint32_t last = (cb + G < s.na ? cb + G : s.na) - 1;
@@ -336,13 +352,9 @@ __device__ inline void table_geometry(uint32_t U, uint32_t slots, uint32_t* P, u
   *S = (uint32_t)s;
 }
 
-// partition of a key (range reduction of its Fibonacci hash) and its home slot
+// partition of a key (range reduction of its Fibonacci hash)
 __device__ inline uint32_t key_part(uint32_t c, uint32_t P) {
   return (uint32_t)(((uint64_t)(c * kHashMul) * P) >> 32);
-}
-__device__ inline uint32_t key_slot(uint32_t c, uint32_t S) {
-  const uint32_t x = (c ^ (c >> 15)) * 0x2C1B3C6Du;
-  return (uint32_t)(((uint64_t)(x ^ (x >> 12)) * S) >> 32);
 }
 
 // ---------------------------------------------------------------------------
@@ -379,8 +391,12 @@ struct WalkRound {
         if (v[u]) idx[u] = start_of[arc[u]] + (b + lane - excl[arc[u]]);
       }
     }
+    // every lane loads (idx 0 where the lane has no wedge), so the loads need
+    // no branches
 #pragma unroll
-    for (int u = 0; u < kWin; u++) c[u] = v[u] ? g.adj[idx[u]] : kEmpty32;
+    for (int u = 0; u < kWin; u++) c[u] = g.adj[idx[u]];
+#pragma unroll
+    for (int u = 0; u < kWin; u++) c[u] = v[u] ? c[u] : kEmpty32;
   }
 };
 
@@ -411,13 +427,15 @@ __device__ inline void walk_chunk(const GView& g, const uint32_t* excl, const ui
 // groups per workgroup), one source per group at a time, up to SLOTS slots.
 // ---------------------------------------------------------------------------
 
-template <int WGS, int G, int SLOTS, bool kW, int STAGE, bool kQ = false>
+template <int WGS, int G, int SLOTS, int TM, int STAGE, bool kQ = false>
 struct LdsTab {
   static constexpr int NG = WGS / G;
   static constexpr int NW = WGS / 64;
-  uint64_t tab[kW ? 1 : NG * SLOTS];
-  uint32_t keys[kW ? NG * SLOTS : 1];
-  uint64_t vals[kW ? NG * SLOTS : 1];
+  static constexpr bool kW = TM != kTabCount;
+  static constexpr bool kSplit = TM == kTabSplit;
+  uint64_t tab[kSplit ? 1 : NG * SLOTS];
+  uint32_t keys[kSplit ? NG * SLOTS : 1];
+  uint64_t vals[kSplit ? NG * SLOTS : 1];
   uint32_t excl[NG][G];
   uint32_t start[NG][G];
   uint64_t w[kW ? NG : 1][kW ? G : 1];
@@ -442,18 +460,30 @@ struct LdsTab {
 
 // kSampled: the same kernel instantiated separately for the sampling pass,
 // so that profiles and per-launch statistics keep the two passes apart
-template <int WGS, int G, int SLOTS, bool kW, bool kQuery, int STAGE, bool kSampled>
-__global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, WorkList wl) {
+// Packed tables ask for at most 128 VGPRs (four waves per SIMD): without the
+// bound the compiler gives their kernels 130-150, and then a 512-lane
+// workgroup, or four 256-lane ones, no longer share a CU with another.  (The
+// count kernels stay below 128 by themselves and run slower under the bound.)
+template <int WGS, int G, int SLOTS, int TM, bool kQuery, int STAGE, bool kSampled>
+__global__ __launch_bounds__(WGS, TM == kTabPacked ? 4 : 1) void acc_lds_kernel(GView g, Emit E, WorkList wl) {
   static_assert(G % 64 == 0 && (G == 64 || G == WGS), "groups are whole waves");
   static_assert(STAGE >= 64, "a stage holds at least one wave of entries");
+  static_assert(!(TM == kTabPacked && kQuery), "packed sums are for the prediction orientation");
   constexpr int NG = WGS / G;
-  __shared__ LdsTab<WGS, G, SLOTS, kW, STAGE, kW && kQuery> L;
+  constexpr bool kW = TM != kTabCount;
+  constexpr bool kSplit = TM == kTabSplit;
+  constexpr bool kPacked = TM == kTabPacked;
+  __shared__ LdsTab<WGS, G, SLOTS, TM, STAGE, kW && kQuery> L;
   const int grp = (int)uniform(threadIdx.x / G);
   const int gl = threadIdx.x & (G - 1);
   const int wv = threadIdx.x >> 6;
-  uint64_t* tab = L.tab + (kW ? 0 : grp * SLOTS);
-  uint32_t* keys = L.keys + (kW ? grp * SLOTS : 0);
-  uint64_t* vals = L.vals + (kW ? grp * SLOTS : 0);
+  uint64_t* tab = L.tab + (kSplit ? 0 : grp * SLOTS);
+  uint32_t* keys = L.keys + (kSplit ? grp * SLOTS : 0);
+  uint64_t* vals = L.vals + (kSplit ? grp * SLOTS : 0);
+  // packed tables: the key is the id itself
+  const int kb = kPacked ? E.pk_idbits : 32;
+  const uint32_t kmask = kPacked ? (uint32_t)((1ull << kb) - 1) : kEmpty32;
+  const uint64_t empty = kPacked ? (uint64_t)kmask : kSlotEmpty;
   uint32_t* s_excl = L.excl[grp];
   uint32_t* s_start = L.start[grp];
   uint64_t* s_w = kW ? L.w[grp] : nullptr;
@@ -509,15 +539,20 @@ __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, WorkList 
     }
     uint32_t P, S;
     table_geometry(keys_max, SLOTS, &P, &S);
+    // packed sums: a source whose sums may not fit is handed over whole
+    if (kPacked && !packed_fits(E.measure, s.na, kb, E.shift)) {
+      if (gl == 0) hand_unfit(E, s);
+      continue;
+    }
     bool handed = false;
     for (uint32_t pass = 0; pass < P; pass++) {
       if (S > clean) {
         for (uint32_t t = clean + gl; t < S; t += G) {
-          if (kW) {
+          if (kSplit) {
             keys[t] = kEmpty32;
             vals[t] = 0;
           } else {
-            tab[t] = kSlotEmpty;
+            tab[t] = empty;
           }
         }
         clean = S;
@@ -528,21 +563,29 @@ __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, WorkList 
       for (uint32_t cb = 0; cb < s.na; cb += G) {
         uint32_t lo, hi;
         if (cb > 0) group_sync<G>();  // every wave is done with the previous chunk
-        load_chunk<G, kQuery, kW>(g, E, s, cb, s_excl, s_start, s_w, L.scan_tmp, &lo, &hi);
+        load_chunk<G, kQuery, kW>(g, E, s, cb, s_excl, s_start, s_w, L.scan_tmp, &lo, &hi, E.shift,
+                                  kPacked ? kb : 0);
         group_sync<G>();
         const uint32_t narcs = s.na - cb < (uint32_t)G ? s.na - cb : (uint32_t)G;
         walk_chunk<G / 64, G>(g, s_excl, s_start, narcs, lo, hi, (int)uniform(gl >> 6), mark,
                               [&](const uint32_t (&c)[kWin], const uint32_t (&arc)[kWin],
                                   const bool (&v)[kWin]) {
+          uint32_t key[kWin];
+          uint64_t inc[kWin];
 #pragma unroll
           for (int u = 0; u < kWin; u++) {
             bool live = v[u] & (c[u] < cut_all);
             if (kQuery) live = live & (c[u] != s.a);
             if (P > 1) live = live & (key_part(c[u], P) == pass);
-            const uint64_t inc = kW ? s_w[arc[u]] : kSlotOne;
-            const bool ok = tab_insert<kW>(tab, keys, vals, S, live ? c[u] : kEmpty32,
-                                           key_slot(c[u], S), inc, RT);
-            full = full | !ok;
+            key[u] = live ? c[u] : kEmpty32;
+            inc[u] = kW ? s_w[arc[u]] : kSlotOne;
+          }
+          if constexpr (kSplit) {
+#pragma unroll
+            for (int u = 0; u < kWin; u++)
+              full = full | !tab_insert<TM>(tab, keys, vals, S, key[u], key_slot(key[u], S), inc[u], RT, kmask);
+          } else {
+            full = full | !tab_insert_k<TM, kWin>(tab, S, key, inc, RT, kmask);
           }
         });
       }
@@ -552,11 +595,11 @@ __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, WorkList 
         uint32_t b = e0 == s.x0 ? xb : (e < s.x1 ? g.adj[e] : kEmpty32);
         if (b >= cut_all) b = kEmpty32;  // no wedge key at or above the cutoff exists
         if (P > 1 && b != kEmpty32 && key_part(b, P) != pass) b = kEmpty32;
-        const bool ok = tab_insert<kW>(tab, keys, vals, S, b, key_slot(b, S),
-                                       kW ? kBlocked64W : kBlocked64, RT);
+        const bool ok = tab_insert<TM>(tab, keys, vals, S, b, key_slot(b, S),
+                                       kW ? kBlocked64W : kBlocked64, RT, kmask);
         full = full | !ok;
       }
-      full = full | !retry_drain<kW>(tab, keys, vals, S, RT);
+      full = full | !retry_drain<TM>(tab, keys, vals, S, RT, kmask);
       if (full) L.ovf[grp][par] = 1;
       group_sync<G>();
       if (L.ovf[grp][par]) {
@@ -605,7 +648,7 @@ __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, WorkList 
         uint32_t c, h = 0;
         uint64_t wsum = 0;
         bool cand, ok;
-        if (kW) {
+        if (kSplit) {
           c = keys[tc];
           wsum = vals[tc];
           if (t < S) {
@@ -613,6 +656,13 @@ __global__ __launch_bounds__(WGS) void acc_lds_kernel(GView g, Emit E, WorkList 
             vals[t] = 0;
           }
           cand = t < S && c != kEmpty32 && (wsum >> 63) == 0;
+          ok = cand && wsum >= wmin_q;
+        } else if (kPacked) {
+          const uint64_t v = tab[tc];
+          if (t < S) tab[t] = empty;
+          c = (uint32_t)v & kmask;
+          cand = t < S && c != kmask && (v >> 63) == 0;
+          wsum = cand ? packed_sum(v, kb) : 0ull;
           ok = cand && wsum >= wmin_q;
         } else {
           const uint64_t v = tab[tc];
@@ -658,12 +708,14 @@ static_assert(BatchKey<48>::kMaxN == (1ull << 26) && BatchKey<32>::kMaxN == (1ul
                   BatchKey<2>::kMaxN == (1ull << 31) - 1,
               "batch key ranges");
 
-template <int WGS, int B, int SLOTS, bool kW, int STAGE>
+template <int WGS, int B, int SLOTS, int TM, int STAGE>
 struct BatchTab {
   static constexpr int NW = WGS / 64;
-  uint64_t tab[kW ? 1 : SLOTS];
-  uint32_t keys[kW ? SLOTS : 1];
-  uint64_t vals[kW ? SLOTS : 1];
+  static constexpr bool kW = TM != kTabCount;
+  static constexpr bool kSplit = TM == kTabSplit;
+  uint64_t tab[kSplit ? 1 : SLOTS];
+  uint32_t keys[kSplit ? SLOTS : 1];
+  uint64_t vals[kSplit ? SLOTS : 1];
   uint32_t excl[WGS];
   uint32_t start[WGS];
   uint32_t srcof[WGS];
@@ -675,6 +727,7 @@ struct BatchTab {
   uint32_t keys_max;       // bound of the batch's distinct keys
   uint32_t hmin[B];
   uint64_t wmin[kW ? B : 1];
+  uint8_t fits[TM == kTabPacked ? B : 1];  // packed sums: the source's sums fit its slots
   uint32_t cut[B][2];
   uint32_t cut_all[B];
   int ovf;
@@ -702,11 +755,21 @@ __device__ inline int batch_search(const uint32_t* off, uint32_t q) {
   return lo;
 }
 
-template <int WGS, int B, int SLOTS, bool kW, int STAGE, bool kSampled>
-__global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkList wl) {
+template <int WGS, int B, int SLOTS, int TM, int STAGE, bool kSampled>
+__global__ __launch_bounds__(WGS, TM == kTabPacked ? 4 : 1) void acc_batch_kernel(GView g, Emit E, WorkList wl) {
   using KB = BatchKey<B>;
   constexpr int NW = WGS / 64;
-  __shared__ BatchTab<WGS, B, SLOTS, kW, STAGE> L;
+  constexpr bool kW = TM != kTabCount;
+  constexpr bool kSplit = TM == kTabSplit;
+  constexpr bool kPacked = TM == kTabPacked;
+  __shared__ BatchTab<WGS, B, SLOTS, TM, STAGE> L;
+  // a key is (position in the batch, id): count and split tables keep the
+  // position in the top bits of 32; packed tables right above the id bits
+  const int ib = kPacked ? E.pk_idbits : KB::kIdBits;
+  const uint32_t imask = kPacked ? (uint32_t)((1ull << ib) - 1) : KB::kIdMask;
+  const int kb = kPacked ? ib + KB::kSrcBits : 32;
+  const uint32_t kmask = kPacked ? (uint32_t)((1ull << kb) - 1) : kEmpty32;
+  const uint64_t empty = kPacked ? (uint64_t)kmask : kSlotEmpty;
   const int tid = threadIdx.x;
   const int wv = tid >> 6;
   uint8_t* mark = L.mark[wv];
@@ -737,9 +800,16 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
         na = r.na;
         U = r.U;
         nx = r.x1 - r.x0;
-        // keys lie in (a, n)
-        const uint32_t room = g.n - 1 - r.a;
-        km = U + nx < room ? U + nx : room;
+        if (kPacked) {
+          // packed sums: a source whose sums may not fit is handed over
+          // whole and takes no part in the batch
+          const bool fits = packed_fits(E.measure, na, kb, E.shift);
+          L.fits[tid] = fits ? 1 : 0;
+          if (!fits) {
+            hand_unfit(E, r);
+            na = U = nx = 0;
+          }
+        }
         L.rec[tid] = r;
         // the source's threshold (its graph's, when several graphs run at once)
         const uint32_t ts_bits = E.fp_mode ? 0u : tau_of(E, r.key)[0];
@@ -752,7 +822,12 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
           // no count exceeds the explored arcs: wedges to ids at or above the
           // cutoff for that count are not accumulated
           cutv = id_cutoff(E.measure, r.na < r.da ? r.na : r.da, r.da, lo, g, true);
+          L.cut_all[tid] = cutv;
         }
+        // keys lie in (a, min(n, cutoff))
+        const uint32_t top = cutv < g.n ? cutv : g.n;
+        const uint32_t room = top > r.a + 1 ? top - r.a - 1 : 0u;
+        km = U + nx < room ? U + nx : room;
       }
       const uint32_t inext = i0 + gridDim.x * B + tid;
       if (tid < B && inext < total) nrec = load_rec(wl, inext);
@@ -790,15 +865,15 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
     if ((uint32_t)(WGS - 1 - tid) < NX) {
       const uint32_t xq = (uint32_t)(WGS - 1 - tid);
       const uint32_t xi = (uint32_t)batch_search<B>(L.xoff, xq);
-      xkey = (xi << KB::kIdBits) | g.adj[L.rec[xi].x0 + (xq - L.xoff[xi])];
+      xkey = (xi << ib) | g.adj[L.rec[xi].x0 + (xq - L.xoff[xi])];
     }
     if (S > clean) {
       for (uint32_t t = clean + tid; t < S; t += WGS) {
-        if (kW) {
+        if (kSplit) {
           L.keys[t] = kEmpty32;
           L.vals[t] = 0;
         } else {
-          L.tab[t] = kSlotEmpty;
+          L.tab[t] = empty;
         }
       }
       clean = S;
@@ -815,12 +890,12 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
       const uint32_t start = g.hstart[e];
       const uint32_t prev = local == 0 ? 0u : g.hpsum[e - 1];
       uint64_t w = 0;
-      if (kW) w = weight_of(E.measure, g.deg[g.hb[e]], E.shift);
+      if (kSplit) w = weight_of(E.measure, g.hdeg[e], E.shift);
+      if (kPacked && qin) w = weight_of(E.measure, g.hdeg[e], E.shift) << kb;
       L.excl[tid] = qin ? L.wedoff[si] + prev : kEmpty32;
       L.start[tid] = start;
       L.srcof[tid] = si;
       if (kW) L.w[tid] = w;
-      if (!kW && cb == 0 && tid < B) L.cut_all[tid] = cutv;
       // flat wedge range of this chunk
       const uint32_t qlast = (cb + WGS < NA ? cb + WGS : NA) - 1;
       const uint32_t sl = (uint32_t)batch_search<B>(L.arcoff, qlast);
@@ -831,14 +906,23 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
       walk_chunk<NW, WGS>(g, L.excl, L.start, narcs, lo, hi, (int)uniform(wv), mark,
                           [&](const uint32_t (&c)[kWin], const uint32_t (&arc)[kWin],
                               const bool (&v)[kWin]) {
+        uint32_t key[kWin];
+        uint64_t inc[kWin];
 #pragma unroll
         for (int u = 0; u < kWin; u++) {
           const uint32_t si = L.srcof[arc[u]];
-          const uint32_t k = (si << KB::kIdBits) | (c[u] & KB::kIdMask);
-          const uint64_t w = kW ? L.w[arc[u]] : kSlotOne;
+          // no count exceeds the explored arcs: wedges to ids at or above a
+          // source's cutoff for that count cannot pass and are not accumulated
           const bool live = kW ? v[u] : (v[u] && c[u] < L.cut_all[si]);
-          const bool ok = tab_insert<kW>(L.tab, L.keys, L.vals, S, live ? k : kEmpty32, key_slot(k, S), w, RT);
-          full = full | !ok;
+          key[u] = live ? (si << ib) | (c[u] & imask) : kEmpty32;
+          inc[u] = kW ? L.w[arc[u]] : kSlotOne;
+        }
+        if constexpr (kSplit) {
+#pragma unroll
+          for (int u = 0; u < kWin; u++)
+            full = full | !tab_insert<TM>(L.tab, L.keys, L.vals, S, key[u], key_slot(key[u], S), inc[u], RT, kmask);
+        } else {
+          full = full | !tab_insert_k<TM, kWin>(L.tab, S, key, inc, RT, kmask);
         }
       });
     }
@@ -853,15 +937,15 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
       uint32_t key = x0 == 0 ? xkey : kEmpty32;
       if (x0 != 0 && x < NX) {
         const uint32_t i = (uint32_t)batch_search<B>(L.xoff, x);
-        key = (i << KB::kIdBits) | g.adj[L.rec[i].x0 + (x - L.xoff[i])];
+        key = (i << ib) | g.adj[L.rec[i].x0 + (x - L.xoff[i])];
       }
       // no wedge key at or above the source's cutoff exists
-      if (!kW && key != kEmpty32 && (key & KB::kIdMask) >= L.cut_all[key >> KB::kIdBits]) key = kEmpty32;
-      const bool ok = tab_insert<kW>(L.tab, L.keys, L.vals, S, key, key_slot(key, S),
-                                     kW ? kBlocked64W : kBlocked64, RT);
+      if (!kW && key != kEmpty32 && (key & imask) >= L.cut_all[key >> ib]) key = kEmpty32;
+      const bool ok = tab_insert<TM>(L.tab, L.keys, L.vals, S, key, key_slot(key, S),
+                                     kW ? kBlocked64W : kBlocked64, RT, kmask);
       full = full | !ok;
     }
-    full = full | !retry_drain<kW>(L.tab, L.keys, L.vals, S, RT);
+    full = full | !retry_drain<TM>(L.tab, L.keys, L.vals, S, RT, kmask);
     if (full) L.ovf = 1;
     __syncthreads();
     if (L.ovf) {
@@ -879,7 +963,7 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
       __syncthreads();
       continue;
     }
-    if (tid < (int)nb) wk.source(L.rec[tid].da, L.rec[tid].na, L.rec[tid].U);
+    if (tid < (int)nb && (!kPacked || L.fits[tid])) wk.source(L.rec[tid].da, L.rec[tid].na, L.rec[tid].U);
     // stage every key that can still reach tau
     for (uint32_t t0 = 0; t0 < S; t0 += WGS) {
       const uint32_t t = t0 + tid;
@@ -887,7 +971,7 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
       uint32_t key, h = 0;
       uint64_t wsum = 0;
       bool ok;
-      if (kW) {
+      if (kSplit) {
         key = L.keys[tc];
         wsum = L.vals[tc];
         if (t < S) {
@@ -896,7 +980,16 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
         }
         ok = t < S && key != kEmpty32 && (wsum >> 63) == 0;
         wk.v[4] += ok ? 1u : 0u;
-        ok = ok && wsum >= L.wmin[ok ? key >> KB::kIdBits : 0u];
+        ok = ok && wsum >= L.wmin[ok ? key >> ib : 0u];
+      } else if (kPacked) {
+        const uint64_t v = L.tab[tc];
+        if (t < S) L.tab[t] = empty;
+        key = (uint32_t)v & kmask;
+        ok = t < S && key != kmask && (v >> 63) == 0;
+        wk.v[4] += ok ? 1u : 0u;
+        const uint32_t i = ok ? key >> ib : 0u;
+        wsum = ok ? packed_sum(v, kb) : 0ull;
+        ok = ok && wsum >= L.wmin[i];
       } else {
         const uint64_t v = L.tab[tc];
         if (t < S) L.tab[t] = kSlotEmpty;
@@ -905,12 +998,12 @@ __global__ __launch_bounds__(WGS) void acc_batch_kernel(GView g, Emit E, WorkLis
         ok = t < S && key != kEmpty32 && (h & kBlocked) == 0;
         wk.v[4] += ok ? 1u : 0u;
       }
-      const uint32_t i = ok ? key >> KB::kIdBits : 0u;
+      const uint32_t i = ok ? key >> ib : 0u;
       if (!kW) {
-        const uint32_t c = key & KB::kIdMask;
+        const uint32_t c = key & imask;
         ok = ok && h >= L.hmin[i] && !(h == 1 && c >= L.cut[i][0]) && !(h == 2 && c >= L.cut[i][1]);
       }
-      stage_add<false, kW>(E, g, SG, ok, key & KB::kIdMask, h, wsum, L.rec[i].key, L.rec[i].da, fa);
+      stage_add<false, kW>(E, g, SG, ok, key & imask, h, wsum, L.rec[i].key, L.rec[i].da, fa);
     }
     __syncthreads();
   }
@@ -984,7 +1077,7 @@ __global__ __launch_bounds__(kSpaThreads) void acc_spa_kernel(GView g, Emit E, W
     __syncthreads();
     for (uint32_t cb = 0; cb < s.na; cb += T) {
       uint32_t lo, hi;
-      load_chunk<T, kQuery, kW>(g, E, s, cb, s_excl, s_start, s_w, scan_tmp, &lo, &hi);
+      load_chunk<T, kQuery, kW>(g, E, s, cb, s_excl, s_start, s_w, scan_tmp, &lo, &hi, E.shift);
       __syncthreads();
       const uint32_t narcs = s.na - cb < (uint32_t)T ? s.na - cb : (uint32_t)T;
       walk_chunk<NW, T>(g, s_excl, s_start, narcs, lo, hi, (int)uniform(wv), mark,
@@ -1141,7 +1234,7 @@ __global__ __launch_bounds__(kSpaThreads) void spa_split_acc_kernel(GView g, Emi
     uint32_t* K = R.keys + (uint64_t)j * g.n;
     uint32_t lo, hi;
     __syncthreads();  // every wave is done with the previous piece
-    load_chunk<T, kQuery, kW>(g, E, s, cb, s_excl, s_start, s_w, scan_tmp, &lo, &hi);
+    load_chunk<T, kQuery, kW>(g, E, s, cb, s_excl, s_start, s_w, scan_tmp, &lo, &hi, E.shift);
     __syncthreads();
     const uint32_t narcs = s.na - cb < (uint32_t)T ? s.na - cb : (uint32_t)T;
     walk_chunk<NW, T>(g, s_excl, s_start, narcs, lo, hi, (int)uniform(wv), mark,
@@ -1583,7 +1676,7 @@ static GView view_of(const lp_graph* g) {
   v.off = g->off;
   v.adj = g->adj;
   v.hoff = g->hoff;
-  v.hb = g->hb;
+  v.hdeg = g->hdeg;
   v.hstart = g->hstart;
   v.hpsum = g->hpsum;
   v.deg = g->deg;
@@ -1628,11 +1721,95 @@ static AccConfig acc_config(const lp_graph* g) {
   return c;
 }
 
+template <int TM, bool kQuery, bool kSampled>
+static lp_status launch_bucket_tables(lp_graph* g, int bucket, const GView& gv, const Emit& E,
+                                      WorkList wl, uint64_t nitems, hipStream_t st);
+
+// Kernel shapes a tuning may pick for the small and mid1 buckets
+// (lp_tuning.kernel_shape; 0 keeps the default).
+enum : int {
+  kShapeBatch = 1,          // several sources share a workgroup and one table
+  kShapeWave = 2,           // one source per 64-lane wave, four per workgroup (small only)
+  kShapeWorkgroup128 = 3,   // one source per 128-lane workgroup
+  kShapeWorkgroup256 = 4    // one source per 256-lane workgroup
+};
+
 // Launch the accumulation of one work list in the given bucket.
-template <bool kW, bool kQuery, bool kSampled>
+template <int TM, bool kQuery, bool kSampled>
 static lp_status launch_bucket(lp_graph* g, int bucket, const GView& gv, const Emit& E,
                                WorkList wl, uint64_t nitems, hipStream_t st) {
   if (nitems == 0) return LP_OK;
+  const unsigned cus = (unsigned)num_cus();
+  // kernel shapes of the small and mid1 buckets (prediction orientation):
+  // batches of sources sharing a workgroup and a table, or one source per
+  // wave / per 128 / 256 lanes; the default depends on the table kind
+  if (!kQuery && (bucket == kBucketSmall || bucket == kBucketMid1)) {
+    const int64_t shape = g->tuning.kernel_shape[bucket == kBucketSmall ? 0 : 1];
+    // default: batches (fastest on R-MAT-22 with count tables and, taken
+    // over AA at L = 32 and RA at L = 256, on Chung-Lu 8M with packed ones)
+    const int sh = shape != 0 ? (int)shape : kShapeBatch;
+    bool done = true;
+    if (sh == kShapeWave)
+      hipLaunchKernelGGL((acc_lds_kernel<256, 64, 384, TM, false, 128, kSampled>),
+                         dim3(grid_for(nitems, 4, cus * 16)), dim3(256), 0, st, gv, E, wl);
+    else if (sh == kShapeWorkgroup128)
+      hipLaunchKernelGGL((acc_lds_kernel<128, 128, 1536, TM, false, 128, kSampled>),
+                         dim3(grid_for(nitems, 1, cus * 16)), dim3(128), 0, st, gv, E, wl);
+    else if (sh == kShapeWorkgroup256)
+      hipLaunchKernelGGL((acc_lds_kernel<256, 256, TM == kTabPacked ? 3008 : 3072, TM, false, 64, kSampled>),
+                         dim3(grid_for(nitems, 1, cus * 8)), dim3(256), 0, st, gv, E, wl);
+    else
+      done = false;
+    if (done) {
+      LP_HIP(hipGetLastError());
+      return LP_OK;
+    }
+  }
+  if constexpr (TM == kTabPacked) {
+    // packed AA / RA tables (prediction orientation; keys hold the batch
+    // position right above id_bits(n + 1) <= 25 bits).  Table sizes keep the
+    // workgroups per CU of the count kernels (the packed kernels also hold the
+    // 64-bit weight of each arc, retry entry and staged sum).
+    switch (bucket) {
+      case kBucketTiny:
+        hipLaunchKernelGGL((acc_batch_kernel<256, 48, 2432, TM, 64, kSampled>),
+                           dim3(grid_for((nitems + 47) / 48, 1, cus * 8)), dim3(256), 0, st, gv, E, wl);
+        break;
+      case kBucketSmall:
+        hipLaunchKernelGGL((acc_batch_kernel<256, 8, 2816, TM, 64, kSampled>),
+                           dim3(grid_for((nitems + 7) / 8, 1, cus * 8)), dim3(256), 0, st, gv, E, wl);
+        break;
+      case kBucketMid1:
+        hipLaunchKernelGGL((acc_batch_kernel<512, 4, 5760, TM, 64, kSampled>),
+                           dim3(grid_for((nitems + 3) / 4, 1, cus * 4)), dim3(512), 0, st, gv, E, wl);
+        break;
+      case kBucketMid2:
+        hipLaunchKernelGGL((acc_lds_kernel<256, 256, 3008, TM, false, 64, kSampled>),
+                           dim3(grid_for(nitems, 1, cus * 8)), dim3(256), 0, st, gv, E, wl);
+        break;
+      case kBucketMid3:
+        hipLaunchKernelGGL((acc_lds_kernel<512, 512, 6016, TM, false, 64, kSampled>),
+                           dim3(grid_for(nitems, 1, cus * 4)), dim3(512), 0, st, gv, E, wl);
+        break;
+      case kBucketLarge:
+        hipLaunchKernelGGL((acc_lds_kernel<1024, 1024, 12032, TM, false, 64, kSampled>),
+                           dim3(grid_for(nitems, 1, cus * 2)), dim3(1024), 0, st, gv, E, wl);
+        break;
+      default:
+        return set_error(LP_ERR_INVALID_ARGUMENT, "bad bucket");
+    }
+    LP_HIP(hipGetLastError());
+    return LP_OK;
+  } else {
+    return launch_bucket_tables<TM, kQuery, kSampled>(g, bucket, gv, E, wl, nitems, st);
+  }
+}
+
+// Count tables and 12-byte weighted tables.
+template <int TM, bool kQuery, bool kSampled>
+static lp_status launch_bucket_tables(lp_graph* g, int bucket, const GView& gv, const Emit& E,
+                                      WorkList wl, uint64_t nitems, hipStream_t st) {
+  constexpr bool kW = TM != kTabCount;
   const unsigned cus = (unsigned)num_cus();
   const uint64_t n = (uint64_t)g->n;
   if (!kQuery && bucket <= kBucketMid1) {
@@ -1644,22 +1821,22 @@ static lp_status launch_bucket(lp_graph* g, int bucket, const GView& gv, const E
     const bool small4 = g->tuning.batch_sources[1] == 4;
     bool done = true;
     if (bucket == kBucketTiny && !tiny32 && n <= BatchKey<48>::kMaxN)
-      hipLaunchKernelGGL((acc_batch_kernel<256, 48, 3072, kW, 64, kSampled>),
+      hipLaunchKernelGGL((acc_batch_kernel<256, 48, 3072, TM, 64, kSampled>),
                          dim3(grid_for((nitems + 47) / 48, 1, cus * 8)), dim3(256), 0, st, gv, E, wl);
     else if (bucket == kBucketTiny && n <= BatchKey<32>::kMaxN)
-      hipLaunchKernelGGL((acc_batch_kernel<256, 32, 3072, kW, 64, kSampled>),
+      hipLaunchKernelGGL((acc_batch_kernel<256, 32, 3072, TM, 64, kSampled>),
                          dim3(grid_for((nitems + 31) / 32, 1, cus * 8)), dim3(256), 0, st, gv, E, wl);
     else if (bucket == kBucketSmall && !small4 && n <= BatchKey<8>::kMaxN)
-      hipLaunchKernelGGL((acc_batch_kernel<256, 8, 3072, kW, 64, kSampled>),
+      hipLaunchKernelGGL((acc_batch_kernel<256, 8, 3072, TM, 64, kSampled>),
                          dim3(grid_for((nitems + 7) / 8, 1, cus * 8)), dim3(256), 0, st, gv, E, wl);
     else if (bucket == kBucketSmall && n <= BatchKey<4>::kMaxN)
-      hipLaunchKernelGGL((acc_batch_kernel<256, 4, 3072, kW, 64, kSampled>),
+      hipLaunchKernelGGL((acc_batch_kernel<256, 4, 3072, TM, 64, kSampled>),
                          dim3(grid_for((nitems + 3) / 4, 1, cus * 8)), dim3(256), 0, st, gv, E, wl);
     else if (bucket == kBucketMid1 && !kW && n <= BatchKey<4>::kMaxN)
-      hipLaunchKernelGGL((acc_batch_kernel<512, 4, 6144, kW, 64, kSampled>),
+      hipLaunchKernelGGL((acc_batch_kernel<512, 4, 6144, TM, 64, kSampled>),
                          dim3(grid_for((nitems + 3) / 4, 1, cus * 4)), dim3(512), 0, st, gv, E, wl);
     else if (bucket == kBucketMid1 && n <= BatchKey<2>::kMaxN)
-      hipLaunchKernelGGL((acc_batch_kernel<256, 2, 3072, kW, 64, kSampled>),
+      hipLaunchKernelGGL((acc_batch_kernel<256, 2, 3072, TM, 64, kSampled>),
                          dim3(grid_for((nitems + 1) / 2, 1, cus * 8)), dim3(256), 0, st, gv, E, wl);
     else
       done = false;
@@ -1670,27 +1847,27 @@ static lp_status launch_bucket(lp_graph* g, int bucket, const GView& gv, const E
   }
   switch (bucket) {
     case kBucketTiny:
-      hipLaunchKernelGGL((acc_lds_kernel<256, 64, 48, kW, kQuery, 128, kSampled>),
+      hipLaunchKernelGGL((acc_lds_kernel<256, 64, 48, TM, kQuery, 128, kSampled>),
                          dim3(grid_for(nitems, 4, cus * 16)), dim3(256), 0, st, gv, E, wl);
       break;
     case kBucketSmall:
-      hipLaunchKernelGGL((acc_lds_kernel<256, 64, 384, kW, kQuery, 128, kSampled>),
+      hipLaunchKernelGGL((acc_lds_kernel<256, 64, 384, TM, kQuery, 128, kSampled>),
                          dim3(grid_for(nitems, 4, cus * 16)), dim3(256), 0, st, gv, E, wl);
       break;
     case kBucketMid1:
-      hipLaunchKernelGGL((acc_lds_kernel<128, 128, 1536, kW, kQuery, 128, kSampled>),
+      hipLaunchKernelGGL((acc_lds_kernel<128, 128, 1536, TM, kQuery, 128, kSampled>),
                          dim3(grid_for(nitems, 1, cus * 16)), dim3(128), 0, st, gv, E, wl);
       break;
     case kBucketMid2:
-      hipLaunchKernelGGL((acc_lds_kernel<256, 256, 3072, kW, kQuery, 64, kSampled>),
+      hipLaunchKernelGGL((acc_lds_kernel<256, 256, 3072, TM, kQuery, 64, kSampled>),
                          dim3(grid_for(nitems, 1, cus * 8)), dim3(256), 0, st, gv, E, wl);
       break;
     case kBucketMid3:
-      hipLaunchKernelGGL((acc_lds_kernel<512, 512, kW ? 4608 : 6144, kW, kQuery, 64, kSampled>),
+      hipLaunchKernelGGL((acc_lds_kernel<512, 512, kW ? 4608 : 6144, TM, kQuery, 64, kSampled>),
                          dim3(grid_for(nitems, 1, cus * 4)), dim3(512), 0, st, gv, E, wl);
       break;
     case kBucketLarge:
-      hipLaunchKernelGGL((acc_lds_kernel<1024, 1024, kW ? 7680 : 14336, kW, kQuery, 64, kSampled>),
+      hipLaunchKernelGGL((acc_lds_kernel<1024, 1024, kW ? 7680 : 14336, TM, kQuery, 64, kSampled>),
                          dim3(grid_for(nitems, 1, cus * 2)), dim3(1024), 0, st, gv, E, wl);
       break;
     default:
@@ -1779,13 +1956,14 @@ static hipEvent_t* workspace_events(hipEvent_t* ev, int n) {
 
 struct LaunchClock {
   static_assert(kBuckets == kNumBuckets, "one clock slot pair per bucket");
-  // slots [0, kBuckets]: main pass; [kBuckets + 1, 2 kBuckets + 1]: sampling pass
+  // per pass (main, then sampling), kBuckets + 2 slots: the buckets, the
+  // global-path launch for overflowing LDS tables (counted as global), and
+  // the 12-byte-table launch for sources whose packed sums do not fit (split)
+  static constexpr int kSlots = kBuckets + 2;
   hipEvent_t* ev;
-  bool used[2 * (kBuckets + 1)] = {};
+  bool used[2 * kSlots] = {};
   lp_stats* stats = nullptr;
-  LaunchClock(lp_stats* s, Workspace& w)
-      : ev(workspace_events(w.clock_ev, 4 * (kBuckets + 1))), stats(s) {}
-  // slot kBuckets: the global-path launch for overflowing LDS tables
+  LaunchClock(lp_stats* s, Workspace& w) : ev(workspace_events(w.clock_ev, 4 * kSlots)), stats(s) {}
   lp_status start(int slot, hipStream_t st) {
     used[slot] = true;
     LP_HIP(hipEventRecord(ev[2 * slot], st));
@@ -1797,13 +1975,13 @@ struct LaunchClock {
   }
   // after the stream has passed every stop event
   void collect() {
-    for (int s = 0; s < 2 * (kBuckets + 1); s++) {
+    for (int s = 0; s < 2 * kSlots; s++) {
       if (!used[s]) continue;
       float t = 0;
       if (hipEventElapsedTime(&t, ev[2 * s], ev[2 * s + 1]) != hipSuccess) (void)hipGetLastError();
-      const int r = s % (kBuckets + 1);
-      lp_bucket_stats* arr = s > kBuckets ? stats->sampled : stats->bucket;
-      lp_bucket_stats& b = arr[r < kBuckets ? r : kBucketHuge];
+      const int r = s % kSlots;
+      lp_bucket_stats* arr = s >= kSlots ? stats->sampled : stats->bucket;
+      lp_bucket_stats& b = arr[r < kBuckets ? r : (r == kBuckets ? kBucketHuge : kStatRows - 1)];
       b.ms += t;
       b.launches += 1;
       used[s] = false;
@@ -1822,7 +2000,7 @@ static void fill_work(const unsigned long long* h, lp_stats* S) {
   for (int p = 0; p < 2; p++) {
     lp_bucket_stats* arr = p ? S->sampled : S->bucket;
     const unsigned long long* x = h + p * kSampledWork;
-    for (int b = 0; b < kBuckets; b++) {
+    for (int b = 0; b < kStatRows; b++) {
       arr[b].sources = x[b * 8 + 0];
       arr[b].first_order = x[b * 8 + 1];
       arr[b].arcs = x[b * 8 + 2];
@@ -1893,18 +2071,21 @@ static lp_status collect_work(Workspace& w, lp_stats* S, hipStream_t st) {
 }
 
 // The whole accumulation for one phase (all buckets, then overflow records).
-template <bool kW, bool kQuery>
+template <int TM, bool kQuery>
 static lp_status run_phase(lp_graph* g, Workspace& w, const GView& gv, const Emit& E0,
                            const SrcRec* lists, uint64_t list_stride, const uint32_t* counts_host,
                            uint32_t stride, int phase, uint32_t* ovf_host_count, LaunchClock* clk,
                            hipStream_t st, const uint32_t* first = nullptr,
                            const Readback* rb = nullptr) {
+  constexpr bool kW = TM != kTabCount;
   unsigned long long* work = work_counters(w);
   // The sampling phase launches every bucket with a few sources each: those
   // launches are latency bound and independent, so they run concurrently on
   // side streams forked from and joined back to st.  Full phases run in
   // order on st (concurrent full launches compete for LDS and lose).
   const bool fan = phase == 1;
+  // packed tables: this phase's list of sources whose sums do not fit starts empty
+  if (TM == kTabPacked && E0.unfit_rec) LP_HIP(hipMemsetAsync(E0.unfit_count, 0, 4, st));
   if (fan) {
     if (!w.fork) {
       LP_HIP(hipEventCreateWithFlags(&w.fork, hipEventDisableTiming));
@@ -1931,14 +2112,14 @@ static lp_status run_phase(lp_graph* g, Workspace& w, const GView& gv, const Emi
     E.work = work + (fan ? kSampledWork : 0) + b * 8;
     const int k = fan ? turn++ % (Workspace::kSide + 1) : 0;
     hipStream_t sb = k == 0 ? st : w.side[k - 1];
-    const int slot = fan ? kBuckets + 1 + b : b;
+    const int slot = fan ? LaunchClock::kSlots + b : b;
     if (clk) LP_TRY(clk->start(slot, sb));
     if constexpr (!kQuery) {
       if (fan) {
         if (b == kBucketHuge)
           LP_TRY((launch_spa<kW, kQuery, true>(g, w, gv, E, wl, SpaItem{nullptr, nullptr, 0, 0}, items, sb)));
         else
-          LP_TRY((launch_bucket<kW, kQuery, true>(g, b, gv, E, wl, items, sb)));
+          LP_TRY((launch_bucket<TM, kQuery, true>(g, b, gv, E, wl, items, sb)));
         if (clk) LP_TRY(clk->stop(slot, sb));
         continue;
       }
@@ -1946,7 +2127,7 @@ static lp_status run_phase(lp_graph* g, Workspace& w, const GView& gv, const Emi
     if (b == kBucketHuge) {
       LP_TRY((launch_spa<kW, kQuery, false>(g, w, gv, E, wl, SpaItem{nullptr, nullptr, 0, 0}, items, sb)));
     } else {
-      LP_TRY((launch_bucket<kW, kQuery, false>(g, b, gv, E, wl, items, sb)));
+      LP_TRY((launch_bucket<TM, kQuery, false>(g, b, gv, E, wl, items, sb)));
     }
     if (clk) LP_TRY(clk->stop(slot, sb));
   }
@@ -1954,6 +2135,27 @@ static lp_status run_phase(lp_graph* g, Workspace& w, const GView& gv, const Emi
     for (int j = 0; j < Workspace::kSide; j++) {
       LP_HIP(hipEventRecord(w.join[j], w.side[j]));
       LP_HIP(hipStreamWaitEvent(st, w.join[j], 0));
+    }
+  }
+  if constexpr (TM == kTabPacked && !kQuery) {
+    if (E0.unfit_rec) {
+      // the sources handed over for sums too wide for a packed slot, with
+      // 12-byte tables and the same fraction bits; the list's length is read
+      // on the device, so no round trip precedes the launch
+      Emit E = E0;
+      E.unfit_rec = nullptr;
+      E.work = work + (fan ? kSampledWork : 0) + (kStatRows - 1) * 8;
+      WorkList wl{static_cast<const SrcRec*>(E0.unfit_rec), 0, 1, 0, E0.unfit_count};
+      const int slot = (fan ? LaunchClock::kSlots : 0) + kBuckets + 1;
+      if (clk) LP_TRY(clk->start(slot, st));
+      if (fan)
+        hipLaunchKernelGGL((acc_lds_kernel<1024, 1024, 7680, kTabSplit, false, 64, true>),
+                           dim3((unsigned)num_cus() * 2), dim3(1024), 0, st, gv, E, wl);
+      else
+        hipLaunchKernelGGL((acc_lds_kernel<1024, 1024, 7680, kTabSplit, false, 64, false>),
+                           dim3((unsigned)num_cus() * 2), dim3(1024), 0, st, gv, E, wl);
+      LP_HIP(hipGetLastError());
+      if (clk) LP_TRY(clk->stop(slot, st));
     }
   }
   // overflow records written by this phase's LDS kernels (and, in the same
@@ -1986,11 +2188,17 @@ static lp_status run_phase_any(lp_graph* g, Workspace& w, const GView& gv, const
                                const uint32_t* counts_host, uint32_t stride, int phase,
                                uint32_t* ovf_host_count, LaunchClock* clk, hipStream_t st,
                                const uint32_t* first = nullptr, const Readback* rb = nullptr) {
+  // AA / RA: packed tables when the call set them up (pk_idbits > 0)
+  if constexpr (!kQuery) {
+    if ((E.measure == LP_AA || E.measure == LP_RA) && E.pk_idbits > 0)
+      return run_phase<kTabPacked, kQuery>(g, w, gv, E, lists, list_stride, counts_host, stride, phase,
+                                           ovf_host_count, clk, st, first, rb);
+  }
   if (E.measure == LP_AA || E.measure == LP_RA)
-    return run_phase<true, kQuery>(g, w, gv, E, lists, list_stride, counts_host, stride, phase,
-                                   ovf_host_count, clk, st, first, rb);
-  return run_phase<false, kQuery>(g, w, gv, E, lists, list_stride, counts_host, stride, phase,
-                                  ovf_host_count, clk, st, first, rb);
+    return run_phase<kTabSplit, kQuery>(g, w, gv, E, lists, list_stride, counts_host, stride, phase,
+                                        ovf_host_count, clk, st, first, rb);
+  return run_phase<kTabCount, kQuery>(g, w, gv, E, lists, list_stride, counts_host, stride, phase,
+                                      ovf_host_count, clk, st, first, rb);
 }
 
 // Radix select of the k largest keys among entries [base, count) of the
@@ -2090,12 +2298,13 @@ static lp_status run_plan(lp_graph* g, int64_t L, PlanResult* pr, hipStream_t st
   LP_TRY(w.stats.ensure(sizeof(PlanOut) + 64));
   LP_TRY(w.host_stats.ensure(kHostStatsBytes));
   pr->hub = hub_start(g, L);
+  const uint32_t hub_deg = L >= (int64_t)0xFFFFFFFE ? 0xFFFFFFFFu : (uint32_t)(L + 1);
   PlanOut* d_out = w.stats.as<PlanOut>();
   LP_HIP(hipMemsetAsync(d_out, 0, sizeof(PlanOut), st));
   const AccConfig cfg = acc_config(g);
   if (n > 0) {
     hipLaunchKernelGGL(plan_kernel, dim3(grid_for(n, 256 * kPlanItems, 0x7FFFFFFF)), dim3(256), 0, st,
-                       view_of(g), pr->hub, cfg.cuts, w.lists.as<SrcRec>(), d_out);
+                       view_of(g), hub_deg, cfg.cuts, w.lists.as<SrcRec>(), d_out);
     LP_HIP(hipGetLastError());
   }
   PlanOut* h = w.host_stats.as<PlanOut>();
@@ -2133,6 +2342,77 @@ static lp_status ensure_ovf(Workspace& w, uint32_t** ovf, void** ovf_rec, uint32
   *ovf_rec = base + 4096 + (size_t)ocap * 4;
   *cap = ocap;
   LP_HIP(hipMemsetAsync(base, 0, 4096, st));
+  return LP_OK;
+}
+
+// Fraction bits of a call's AA / RA fixed-point sums: the most that keep every
+// sum below 2^62 (a sum has at most max_deg terms, each at most 1/2 for RA
+// and 1/ln 2 for AA), capped at 44.  A sum's relative rounding error is at most
+// 2^-(F+1) / w_min, with w_min the weight of the largest explored degree; a
+// call whose bound would exceed 2^-24 is refused rather than answered outside
+// the 1e-6 tolerance.  That happens only for RA, when the largest explored
+// degree times the maximum degree exceeds about 2^40.
+static lp_status weighted_shift(const lp_graph* g, int m, int64_t L, int* shift) {
+  *shift = g->fixed_shift;
+  if (m != LP_AA && m != LP_RA) return LP_OK;
+  const double wmax = m == LP_RA ? 0.5 : 1.0 / std::log(2.0);
+  int F = 44;
+  while (F > 0 && (double)(g->max_deg + 1) * wmax * std::ldexp(1.0, F) >= std::ldexp(1.0, 62)) F--;
+  *shift = F;
+  const uint32_t hs = hub_start(g, L);
+  if (hs == 0) return LP_OK;
+  const double dmax = (double)g->host_deg[hs - 1];
+  if (dmax < 2.0) return LP_OK;
+  const double inv_wmin = m == LP_RA ? dmax : std::log(dmax);
+  if (std::ldexp(inv_wmin, -(F + 1)) > std::ldexp(1.0, -24))
+    return set_error(LP_ERR_INVALID_ARGUMENT,
+                     "%s sums in %d-bit fixed point cannot stay within 2^-24 of their value with "
+                     "intermediates of degree %.0f (maximum degree %lld); use a lower hub limit",
+                     m == LP_RA ? "RA" : "AA", F, dmax, (long long)g->max_deg);
+  return LP_OK;
+}
+
+// Packed AA / RA tables for a prediction call (key and fixed-point sum in one
+// 64-bit slot).  Every kernel and the global path of a call round the weights
+// to the same F fraction bits, so results do not depend on which kernel a
+// source lands in: F is what the tightest packed slot allows (48 sources of
+// at most 32 arcs share a tiny batch: key bits id_bits(n + 1) + 6), at most
+// the call's common shift.  Packing is used only when F keeps every sum within
+// 2^-22 of its value: each term is rounded by at most 2^-(F+1) and no term is
+// below the weight w_min of the largest explored degree, so F >= 21 +
+// log2(1 / w_min) suffices.  Otherwise (or for other measures, or above
+// 2^25 - 2 vertices) the call keeps 12-byte tables and its common shift.
+static void packed_params(const lp_graph* g, int m, int64_t L, Emit* E) {
+  E->pk_idbits = 0;
+  if (m != LP_AA && m != LP_RA) return;
+  const int ib = id_bits((uint64_t)g->n + 1);
+  if (ib > 25) return;
+  const uint32_t hs = hub_start(g, L);  // vertices of degree <= L form a prefix
+  if (hs == 0) return;
+  const double dmax = (double)g->host_deg[hs - 1];
+  if (dmax < 2.0) return;
+  const double inv_wmin = m == LP_RA ? dmax : std::log(dmax);
+  const int fmin = 21 + std::max(0, (int)std::ceil(std::log2(inv_wmin)));
+  const int e = m == LP_RA ? -1 : 1;
+  const int ftiny = (63 - (ib + BatchKey<48>::kSrcBits)) - 1 - 5 - e;  // ceil(log2 32) = 5
+  const int F = std::min(ftiny, E->shift);
+  if (F < fmin) return;
+  E->pk_idbits = ib;
+  E->shift = F;
+}
+
+// The list of sources handed over by a packed call (SrcRec each, count
+// first); empty for other calls.
+static lp_status unfit_list(Workspace& w, Emit* E) {
+  E->unfit_rec = nullptr;
+  E->unfit_count = nullptr;
+  E->unfit_cap = 0;
+  if (E->pk_idbits == 0) return LP_OK;
+  const uint32_t cap = 1u << 16;
+  LP_TRY(w.unfit.ensure(256 + (size_t)cap * sizeof(SrcRec)));
+  E->unfit_count = w.unfit.as<uint32_t>();
+  E->unfit_rec = w.unfit.as<char>() + 256;
+  E->unfit_cap = cap;
   return LP_OK;
 }
 
@@ -2244,9 +2524,11 @@ lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int3
   uint32_t* tc = ta + cap;
   Emit E{};
   E.measure = m;
-  E.shift = g->fixed_shift;
+  LP_TRY(weighted_shift(g, m, L, &E.shift));
   E.s_th = s_th;
   E.tau = tau;
+  packed_params(g, m, L, &E);
+  LP_TRY(unfit_list(w, &E));
   E.out_s = w.cand_s.as<uint32_t>();
   E.out_a = w.cand_a.as<uint32_t>();
   E.out_c = w.cand_c.as<uint32_t>();
@@ -2743,9 +3025,11 @@ lp_status run_predict_multi(lp_graph* g, int64_t ng, const int64_t* vstart, cons
   LP_TRY(ensure_select_bufs(w, cap));
   Emit E{};
   E.measure = m;
-  E.shift = g->fixed_shift;
+  LP_TRY(weighted_shift(g, m, L, &E.shift));
   E.s_th = s_th;
   E.tau = tau;
+  packed_params(g, m, L, &E);
+  LP_TRY(unfit_list(w, &E));
   E.out_s = w.cand_s.as<uint32_t>();
   E.out_a = w.cand_a.as<uint32_t>();
   E.out_c = w.cand_c.as<uint32_t>();
@@ -3032,7 +3316,7 @@ lp_status run_query(lp_graph* g, Workspace& w, const int32_t* sources, int64_t n
   LP_TRY(ensure_ovf(w, &ovf, &ovf_rec, &ovf_count, &ovf_cap, &err, &count, &fp, &tau, st));
   Emit E{};
   E.measure = m;
-  E.shift = g->fixed_shift;
+  LP_TRY(weighted_shift(g, m, L, &E.shift));
   E.s_th = s_th;
   E.tau = tau;
   E.out_s = w.cand_s.as<uint32_t>();

@@ -32,10 +32,15 @@ lp_status from_hip(hipError_t e, const char* what) {
 
 const char* last_error_text() { return g_last_error.c_str(); }
 
+thread_local size_t ScratchLimit::bytes = 0;
+
 lp_status DevBuf::ensure(size_t bytes) {
   if (bytes <= cap && p) return LP_OK;
-  release();
   size_t want = bytes ? bytes : 256;
+  if (ScratchLimit::bytes && want > ScratchLimit::bytes)
+    return set_error(LP_ERR_OUT_OF_MEMORY, "scratch allocation of %zu bytes above the limit of %zu",
+                     want, ScratchLimit::bytes);
+  release();
   hipError_t e = hipMalloc(&p, want);
   if (e != hipSuccess) {
     p = nullptr;

@@ -52,6 +52,8 @@ struct Request {
   float* out_s = nullptr;
   int32_t* out_n = nullptr;
   uint64_t paths = 0;
+  uint64_t bytes = 0;  // device scratch the request needs (see lp_server::need)
+  uint32_t hubs = 0;   // sources above the LDS capacity (dense global accumulators)
   Clock::time_point t_submit, t_start, t_done;
   lp_request_info info{};
   bool done = false;
@@ -87,8 +89,17 @@ struct lp_server {
     std::thread th;
   };
   std::vector<std::unique_ptr<Slot>> slots;
+  unsigned max_slabs = 1;  // dense accumulators one slot's workspace may hold
 
   void worker(Slot* sl);
+  // Device scratch of a batch: candidate and sort buffers of 24 bytes per
+  // two-hop path (the bound of its candidates), per-source records, counts
+  // and outputs, and one dense accumulator of 12 bytes per vertex for each
+  // source above the LDS capacity (at most max_slabs at once).
+  uint64_t need(uint64_t paths, uint64_t sources, uint32_t hubs, int32_t kq) const {
+    const uint64_t slabs = std::min<uint64_t>(hubs, max_slabs);
+    return 24 * paths + sources * (4 + 7 * 32 + 8 + 12 * (uint64_t)kq) + slabs * 12 * (uint64_t)g->n;
+  }
 };
 
 void lp_server::worker(Slot* sl) {
@@ -100,17 +111,21 @@ void lp_server::worker(Slot* sl) {
       std::unique_lock<std::mutex> lk(mu);
       cv_work.wait(lk, [&] { return stop || !queue.empty(); });
       if (queue.empty()) return;  // stop requested and nothing left
-      // the oldest request, then every queued one of the same kind that fits
+      // the oldest request, then every queued one of the same kind whose
+      // sources, paths and device scratch still fit the slot's budget
       Request* r0 = queue.front();
       queue.pop_front();
       batch.push_back(r0);
       uint64_t ns = r0->sources.size(), np = r0->paths;
+      uint32_t nh = r0->hubs;
       for (auto it = queue.begin(); it != queue.end();) {
         Request* r = *it;
         if (same_kind(*r, *r0) && ns + r->sources.size() <= (uint64_t)cfg.max_batch_sources &&
-            np + r->paths <= (uint64_t)cfg.max_batch_paths) {
+            np + r->paths <= (uint64_t)cfg.max_batch_paths &&
+            need(np + r->paths, ns + r->sources.size(), nh + r->hubs, r0->kq) <= (uint64_t)cfg.max_batch_bytes) {
           ns += r->sources.size();
           np += r->paths;
+          nh += r->hubs;
           batch.push_back(r);
           it = queue.erase(it);
         } else {
@@ -123,7 +138,14 @@ void lp_server::worker(Slot* sl) {
     const Clock::time_point t0 = Clock::now();
     const Request& k = *batch[0];
     size_t total = 0;
-    for (auto* r : batch) total += r->sources.size();
+    uint64_t bpaths = 0;
+    uint32_t bhubs = 0;
+    for (auto* r : batch) {
+      total += r->sources.size();
+      bpaths += r->paths;
+      bhubs += r->hubs;
+    }
+    const uint64_t batch_bytes = need(bpaths, total, bhubs, k.kq);
     sl->src.resize(total);
     size_t pos = 0;
     for (auto* r : batch) {
@@ -164,6 +186,7 @@ void lp_server::worker(Slot* sl) {
         r->info.batch = bid;
         r->info.batch_requests = (uint32_t)batch.size();
         r->info.batch_sources = total;
+        r->info.batch_bytes = batch_bytes;
         r->info.queue_ms = ms_between(r->t_submit, t0);
         r->info.run_ms = ms_between(t0, t1);
         r->info.total_ms = ms_between(r->t_submit, t1);
@@ -188,10 +211,16 @@ lp_status lp_server_create(lp_graph* g, const lp_server_config* cfg, lp_server**
     if (s->cfg.slots == 0) s->cfg.slots = 2;
     if (s->cfg.max_batch_sources == 0) s->cfg.max_batch_sources = 16384;
     if (s->cfg.max_batch_paths == 0) s->cfg.max_batch_paths = 1ll << 27;
-    if (s->cfg.slots < 1 || s->cfg.slots > 8 || s->cfg.max_batch_sources < 1 ||
-        s->cfg.max_batch_paths < 1)
-      return set_error(LP_ERR_INVALID_ARGUMENT, "server config out of range");
     LP_HIP(hipSetDevice(g->device));
+    // every slot's workspace keeps its global accumulators within an eighth of
+    // the device memory; the default scratch budget splits that eighth
+    s->max_slabs = (unsigned)std::max<uint64_t>(
+        1, std::min<uint64_t>((uint64_t)num_cus(), device_memory() / 8 / ((uint64_t)g->n * 12 + 1)));
+    if (s->cfg.max_batch_bytes == 0)
+      s->cfg.max_batch_bytes = (int64_t)(device_memory() / 8 / (uint64_t)std::max(1, s->cfg.slots));
+    if (s->cfg.slots < 1 || s->cfg.slots > 8 || s->cfg.max_batch_sources < 1 ||
+        s->cfg.max_batch_paths < 1 || s->cfg.max_batch_bytes < 1)
+      return set_error(LP_ERR_INVALID_ARGUMENT, "server config out of range");
     // path bounds, once, in original id order
     const int64_t n = g->n;
     s->paths.assign((size_t)n, 0);
@@ -267,16 +296,23 @@ lp_status lp_server_submit(lp_server* s, const int32_t* sources, int64_t n_sourc
     auto r = std::make_unique<Request>();
     r->sources.assign(sources, sources + n_sources);
     // every explored intermediate has degree <= L, so a source's wedges are
-    // also at most d_s * L
+    // also at most d_s * L; a source whose table bound (wedges plus degree)
+    // exceeds the LDS capacity takes a dense global accumulator
+    const uint64_t cap = s->g->tuning.lds_wedge_cap > 0 ? (uint64_t)s->g->tuning.lds_wedge_cap : 65536;
     uint64_t paths = 0;
+    uint32_t hubs = 0;
     for (int32_t v : r->sources) {
       if (v < 0 || (int64_t)v >= s->g->n)
         return set_error(LP_ERR_INVALID_ARGUMENT, "source %d outside [0, n)", (int)v);
       const unsigned long long by_limit =
           hub_limit >= (int64_t)UINT32_MAX ? ~0ull : (unsigned long long)s->degree[(size_t)v] * (uint64_t)hub_limit;
-      paths += std::min(s->paths[(size_t)v], by_limit);
+      const uint64_t p = std::min(s->paths[(size_t)v], by_limit);
+      paths += p;
+      hubs += p + s->degree[(size_t)v] > cap ? 1u : 0u;
     }
     r->paths = paths;
+    r->hubs = hubs;
+    r->bytes = s->need(paths, r->sources.size(), hubs, k_q);
     r->m = (int)m;
     r->L = hub_limit;
     r->kq = k_q;

@@ -5,7 +5,8 @@ The knobs move work between kernels without changing any result: the bucket
 bounds decide which kernel a source meets (48, 8 or 2 sources per 256-lane
 workgroup for the three batch buckets, one per 256, 512 or 1024 lanes above),
 the batch knobs set how many tiny (48 or 32) and small (8 or 4) sources share
-a workgroup,
+a workgroup, the shape knobs pick the kernel of the small and mid1 buckets
+(batches, one source per wave, per 128 or per 256 lanes),
 the LDS cap decides which sources take the global-memory accumulator, and the
 sample budget sizes the pass that sets the top-k threshold.  The tuner runs
 the caller's workload under each setting and keeps what is fastest, by
@@ -23,6 +24,8 @@ from . import BUCKET_MAX_DEFAULT, set_tuning
 DEFAULT_SPACE = {
     "tiny_batch": (48, 32),
     "small_batch": (8, 4),
+    "small_shape": (0, "batch", "wave", "workgroup128"),  # 0: the library's default
+    "mid1_shape": (0, "batch", "workgroup128", "workgroup256"),
     "bucket_max0": (32, 24, 16),
     "bucket_max1": (256, 192, 128, 64),
     "bucket_max2": (1024, 768, 512),
@@ -46,7 +49,8 @@ def apply(g, setting: dict) -> None:
                global_slots=int(setting.get("global_slots", 0)),
                sample_budget=int(setting.get("sample_budget", 0)), bucket_max=bm,
                tiny_batch=int(setting.get("tiny_batch", 0)),
-               small_batch=int(setting.get("small_batch", 0)))
+               small_batch=int(setting.get("small_batch", 0)),
+               small_shape=setting.get("small_shape", 0), mid1_shape=setting.get("mid1_shape", 0))
 
 
 def _median(xs):

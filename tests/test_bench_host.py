@@ -6,6 +6,7 @@ import subprocess
 import sys
 
 import numpy as np
+import pytest
 
 import bench
 
@@ -33,12 +34,20 @@ def test_traffic_lookup_requires_matching_sources(tmp_path, monkeypatch):
     assert bench.measured_traffic("k<1, 2>") is None
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.txt"))
     assert bench.measured_traffic("k<1, 2>") is None
+    # a workload that no summary covers
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "abc")
+    assert bench.measured_traffic("k<1, 2>", "") is None
+    assert bench.measured_traffic("k<1, 2>", str(f)) == 123.0
 
 
-def test_committed_traffic_summary_is_well_formed():
-    with open(bench.TRAFFIC_FILE) as fh:
+@pytest.mark.parametrize("which", ["jc", "aa", "ra"])
+def test_committed_traffic_summary_is_well_formed(which):
+    path = {"jc": bench.TRAFFIC_FILE, "aa": bench.TRAFFIC_FILES_CL8M[("AA", 32)],
+            "ra": bench.TRAFFIC_FILES_CL8M[("RA", 256)]}[which]
+    with open(path) as fh:
         lines = fh.read().splitlines()
     assert sum(l.startswith("source_sha256: ") for l in lines) == 1
+    assert any("rocprofv3 --pmc FETCH_SIZE" in l for l in lines)
     rows = [l for l in lines if l.startswith("traffic_bytes_per_launch ")]
     assert rows
     for l in rows:

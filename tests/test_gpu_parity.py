@@ -294,6 +294,70 @@ def test_edge_cases(lp, config1):
             assert lp.fingerprint(g, None) == (0, 0, 0, 0)
 
 
+def test_graph_usable_after_out_of_memory(lp, config1):
+    """Scratch allocations above the graph's scratch_limit fail as the device
+    running out would (LP_ERR_OUT_OF_MEMORY, no partial output); with the
+    limit lifted the same graph answers every call correctly."""
+    gr, k = config1
+    say("[gpu] out of memory, then usable")
+    with lp.Graph(gr.offsets, gr.indices) as g:
+        lp.set_tuning(g, scratch_limit=1 << 16)
+        for call in (lambda: lp.predict(g, "JC", 256, k), lambda: lp.query(g, [0, 1, 2], "AA", 256, 5),
+                     lambda: lp.fingerprint(g, 256), lambda: lp.predict(g, "RA", 32, k)):
+            with pytest.raises(lp.LpError) as e:
+                call()
+            assert e.value.name == "LP_ERR_OUT_OF_MEMORY"
+        lp.set_tuning(g)
+        for m in ("JC", "RA"):
+            ref = oracle.predict(gr, 256, m, k)
+            assert_same_list(run_predict(lp, g, m, 256, k), ref, m, f"after OOM {m}", graph=gr, L=256)
+        assert lp.fingerprint(g, 256) == oracle.fingerprint(gr, 256)
+        src = synth.sample_sources(gr, 20, seed=2, top=2)
+        refq = oracle.query(gr, 256, "AA", src, 5)
+        c, s, cnt = (to_np(x) for x in lp.query(g, src, "AA", 256, 5))
+        assert_query_rows(c, s, cnt, src, refq, "AA", "after OOM query", graph=gr, L=256)
+
+
+def test_busy_from_two_threads(lp, config1):
+    """Two threads calling into one graph: a call that finds the graph in use
+    returns LP_ERR_BUSY at once; every call that runs gives the right digest."""
+    import threading
+    import time
+    gr, _ = config1
+    ref = oracle.fingerprint(gr, 256)
+    say("[gpu] busy from two threads")
+    with lp.Graph(gr.offsets, gr.indices) as g:
+        assert lp.fingerprint(g, 256) == ref  # buffers at their working size
+        lock = threading.Lock()
+        seen = {"ok": 0, "busy": 0, "wrong": 0, "other": 0}
+        stop = threading.Event()
+
+        def worker():
+            while not stop.is_set():
+                try:
+                    key = "ok" if lp.fingerprint(g, 256) == ref else "wrong"
+                except lp.LpError as e:
+                    key = "busy" if e.name == "LP_ERR_BUSY" else "other"
+                with lock:
+                    seen[key] += 1
+
+        threads = [threading.Thread(target=worker) for _ in range(2)]
+        for t in threads:
+            t.start()
+        t0 = time.time()
+        while time.time() - t0 < 20:
+            time.sleep(0.05)
+            with lock:
+                if seen["busy"] > 0 and seen["ok"] >= 20:
+                    break
+        stop.set()
+        for t in threads:
+            t.join()
+        assert seen["wrong"] == 0 and seen["other"] == 0, seen
+        assert seen["busy"] > 0 and seen["ok"] > 0, seen
+        assert lp.fingerprint(g, 256) == ref
+
+
 def test_invalid_inputs(lp):
     say("[gpu] invalid inputs")
     good = synth.from_edges(4, [(0, 1), (1, 2), (2, 3)])
@@ -466,6 +530,36 @@ def test_server_invalid_requests(lp, config1):
                 srv.wait(t)
 
 
+def test_server_scratch_budget(lp, config1):
+    """Admission by device scratch: with a budget below any two requests'
+    need every batch holds one request; with the default budget requests
+    share batches; both give lp_query's results.  Each request reports its
+    batch's scratch bound."""
+    gr, _ = config1
+    rng = np.random.default_rng(5)
+    deg = gr.degrees()
+    nz = np.nonzero(deg > 0)[0]
+    reqs = [rng.choice(nz, size=int(rng.integers(5, 60))).astype(np.int32) for _ in range(16)]
+    say("[gpu] server scratch budget")
+    with lp.Graph(gr.offsets, gr.indices) as g:
+        ref = [tuple(to_np(x) for x in lp.query(g, r, "RA", 256, 5)) for r in reqs]
+        for budget, batched in ((1, False), (0, True)):
+            with lp.Server(g, slots=1, max_batch_bytes=budget) as srv:
+                tickets = [srv.submit(r, "RA", 256, 5) for r in reqs]
+                res = [srv.wait(t) for t in tickets]
+            sizes = {rec["batch"]: rec["batch_requests"] for _, rec in res}
+            assert all(rec["batch_bytes"] > 0 for _, rec in res)
+            if batched:
+                assert max(sizes.values()) > 1
+            else:
+                assert set(sizes.values()) == {1}
+            for (out, _), (c, s, n) in zip(res, ref):
+                assert np.array_equal(out[2], n)
+                for i in range(n.shape[0]):
+                    assert np.array_equal(out[0][i][: n[i]], c[i][: n[i]])
+                    assert np.array_equal(out[1][i][: n[i]], s[i][: n[i]])
+
+
 @pytest.fixture(scope="module")
 def chung_lu_8m():
     """The AA / RA workload: Chung-Lu, 8M vertices, exponent 2.1, weights capped
@@ -599,6 +693,9 @@ BUCKET_SETTINGS = [
     {"bucket_max": (1, 1, 1, 1, 1), "lds_wedge_cap": 200},
     {"tiny_batch": 32, "small_batch": 4},
     {"bucket_max": (16, 128), "tiny_batch": 32, "small_batch": 4, "lds_wedge_cap": 3000},
+    {"small_shape": "wave", "mid1_shape": "workgroup128"},
+    {"small_shape": "workgroup128", "mid1_shape": "batch"},
+    {"small_shape": "workgroup256", "mid1_shape": "workgroup256"},
 ]
 
 
@@ -656,6 +753,10 @@ def test_tuning_invalid(lp, config1):
             lp.set_tuning(g, tiny_batch=40)
         with pytest.raises(lp.LpError):
             lp.set_tuning(g, small_batch=16)
+        with pytest.raises(lp.LpError):
+            lp.set_tuning(g, mid1_shape="wave")
+        with pytest.raises(lp.LpError):
+            lp.set_tuning(g, small_shape=7)
         with pytest.raises(ValueError):
             lp.set_tuning(g, bucket_max=(1, 1, 1, 1, 1, 1))
         run_predict(lp, g, "JC", 256, k)

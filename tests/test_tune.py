@@ -73,6 +73,7 @@ def test_apply_maps_setting_to_set_tuning(monkeypatch):
 
     monkeypatch.setattr(tune, "set_tuning", fake_set_tuning)
     tune.apply("g", {"bucket_max0": 16, "bucket_max3": 1536, "lds_wedge_cap": 4096,
-                     "global_slots": 128, "sample_budget": 1 << 20})
+                     "global_slots": 128, "sample_budget": 1 << 20, "mid1_shape": "workgroup128"})
     assert seen == {"lds_wedge_cap": 4096, "global_slots": 128, "sample_budget": 1 << 20,
-                    "bucket_max": [16, 256, 1024, 1536, 4096], "tiny_batch": 0, "small_batch": 0}
+                    "bucket_max": [16, 256, 1024, 1536, 4096], "tiny_batch": 0, "small_batch": 0,
+                    "small_shape": 0, "mid1_shape": "workgroup128"}
