@@ -129,6 +129,33 @@ lp_status lp_query(lp_graph *g, const int32_t *sources, int64_t n_sources, lp_me
                    float *out_score, int32_t *out_count, void *hip_stream);
 
 /*
+ * lp_query without device allocation, for callers that cannot allocate
+ * device memory during the call: applications that capture HIP graphs on
+ * other streams meanwhile, tight serving loops, hosts that forbid hipMalloc
+ * after start-up.  (The call itself reads the plan back to the host, so it
+ * cannot be recorded into a HIP graph.)
+ * Arguments, results and errors are those of lp_query; results are identical
+ * to lp_query's on the same inputs.  Every piece of device scratch comes from
+ * one array of about 90 MB that the library holds per device until the
+ * process ends; the first call on a device looks its address up (nothing is
+ * allocated then either).  Inputs and outputs stay the caller's.
+ * Limits of the fixed scratch (LP_ERR_INVALID_ARGUMENT beyond them, with
+ * nothing written; the graph and the scratch stay usable):
+ *   n_sources <= 4096, n_sources * k_q <= 2^20, the sources' two-hop path
+ *   bound (the sum over sources of the wedges they may explore) <= 2^21, and
+ *   a source above the LDS capacity only when 12 * n <= 32 MiB.
+ * The scratch is shared by every graph on the device and keeps the last
+ * call's contents; a call clears what it needs.  One call per device at a
+ * time: a call that starts while another is running on the same device
+ * (from another thread) returns LP_ERR_BUSY instead of racing on it.  The
+ * call does not take g's own busy flag, and returns after the stream has
+ * finished its work, like lp_query.
+ */
+lp_status lp_query_static(lp_graph *g, const int32_t *sources, int64_t n_sources, lp_measure m,
+                          int64_t hub_limit, int32_t k_q, float score_threshold, int32_t *out_c,
+                          float *out_score, int32_t *out_count, void *hip_stream);
+
+/*
  * Order-independent digest of the whole candidate set for hub limit L (the
  * prediction orientation, unordered pairs): out[0] = number of candidates,
  * out[1] = sum of h, out[2] = sum over candidates of mix64(a, c, h) modulo

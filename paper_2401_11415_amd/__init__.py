@@ -19,7 +19,7 @@ import os
 import numpy as np
 
 __all__ = ["MEASURES", "HUB_NONE", "LpError", "Graph", "predict", "predict_multi", "query",
-           "fingerprint", "set_tuning", "last_stats", "Server", "library_path", "load",
+           "query_static", "fingerprint", "set_tuning", "last_stats", "Server", "library_path", "load",
            "BUCKET_MAX_DEFAULT"]
 
 MEASURES = ("CN", "JC", "SI", "SC", "HP", "HD", "LHN", "AA", "RA")
@@ -105,6 +105,8 @@ def load():
     lib.lp_predict_multi.argtypes = [vp, i64, vp, vp, ctypes.c_int, i64, f32, vp, vp, vp, vp, vp]
     lib.lp_query.restype = st
     lib.lp_query.argtypes = [vp, vp, i64, ctypes.c_int, i64, i32, f32, vp, vp, vp, vp]
+    lib.lp_query_static.restype = st
+    lib.lp_query_static.argtypes = [vp, vp, i64, ctypes.c_int, i64, i32, f32, vp, vp, vp, vp]
     lib.lp_fingerprint.restype = st
     lib.lp_fingerprint.argtypes = [vp, i64, vp, vp]
     lib.lp_set_tuning.restype = st
@@ -273,6 +275,38 @@ def query(g: Graph, sources, measure, hub_limit, k_q: int, score_threshold: floa
     on = torch.zeros(max(ns, 1), dtype=torch.int32, device=dev)
     _check(lib.lp_query(g.handle, _ptr(src), ns, _measure(measure), _hub(hub_limit), k_q,
                         float(score_threshold), _ptr(oc), _ptr(os_), _ptr(on), _stream(stream)))
+    return oc[:ns], os_[:ns], on[:ns]
+
+
+def query_static(g: Graph, sources, measure, hub_limit, k_q: int, score_threshold: float = 0.0,
+                 out=None, stream=None):
+    """lp_query_static: query() with every piece of device scratch taken from
+    the library's fixed per-device array (no device allocation in the call).
+    out = (c [ns, k_q] int32, score [ns, k_q] float32, count [ns] int32) CUDA
+    tensors to fill; with out and sources given as CUDA int32 tensors the
+    binding allocates nothing either.  Returns (c, score, count)."""
+    import torch
+    lib = load()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if isinstance(sources, np.ndarray) or isinstance(sources, (list, tuple)):
+        src = torch.as_tensor(np.asarray(sources, dtype=np.int32), device=dev)
+    elif sources.dtype == torch.int32 and sources.is_cuda and sources.is_contiguous():
+        src = sources
+    else:
+        src = sources.to(device=dev, dtype=torch.int32).contiguous()
+    ns = int(src.shape[0])
+    k_q = int(k_q)
+    if out is None:
+        out = (torch.empty((max(ns, 1), k_q), dtype=torch.int32, device=dev),
+               torch.empty((max(ns, 1), k_q), dtype=torch.float32, device=dev),
+               torch.zeros(max(ns, 1), dtype=torch.int32, device=dev))
+    oc, os_, on = out
+    if ns > 0 and (oc.dtype != torch.int32 or os_.dtype != torch.float32 or on.dtype != torch.int32 or
+                   oc.numel() < ns * k_q or os_.numel() < ns * k_q or on.numel() < ns or
+                   not (oc.is_contiguous() and os_.is_contiguous() and on.is_contiguous())):
+        raise ValueError("out must be contiguous (int32 [ns, k_q], float32 [ns, k_q], int32 [ns]) tensors")
+    _check(lib.lp_query_static(g.handle, _ptr(src), ns, _measure(measure), _hub(hub_limit), k_q,
+                               float(score_threshold), _ptr(oc), _ptr(os_), _ptr(on), _stream(stream)))
     return oc[:ns], os_[:ns], on[:ns]
 
 

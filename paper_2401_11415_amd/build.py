@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblp.so")
-SOURCES = ["api.hip", "graph.hip", "predict.hip", "prim.hip", "serve.hip"]
+SOURCES = ["api.hip", "graph.hip", "predict.hip", "prim.hip", "serve.hip", "static_query.hip"]
 ARCH = os.environ.get("LP_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

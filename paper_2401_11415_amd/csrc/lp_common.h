@@ -40,19 +40,23 @@ void clear_error();
 // ---------------------------------------------------------------------------
 
 // A growable device allocation.  ensure() keeps the contents only when no
-// reallocation is needed.
+// reallocation is needed.  A fixed buffer is a view of memory owned
+// elsewhere: ensure() never allocates and fails (LP_ERR_INVALID_ARGUMENT)
+// when asked for more than cap; release() leaves it alone.
 struct DevBuf {
   void* p = nullptr;
   size_t cap = 0;
+  bool fixed = false;
   lp_status ensure(size_t bytes);
   void release();
   template <class T> T* as() const { return static_cast<T*>(p); }
 };
 
-// Pinned host staging for small device -> host reads.
+// Pinned host staging for small device -> host reads (fixed: as for DevBuf).
 struct HostBuf {
   void* p = nullptr;
   size_t cap = 0;
+  bool fixed = false;
   lp_status ensure(size_t bytes);
   void release();
   template <class T> T* as() const { return static_cast<T*>(p); }

@@ -1887,7 +1887,16 @@ static lp_status launch_spa(lp_graph* g, Workspace& w, const GView& gv, const Em
   // lists of 4n; it grows to the launch's workgroup count (at most
   // cfg.spa_wgs, and at most an eighth of the device memory, since every
   // server slot has a workspace of its own) and never shrinks
-  const uint64_t mem_cap = std::max<uint64_t>(1, device_memory() / 8 / (n * 12 + 1));
+  uint64_t mem_cap = std::max<uint64_t>(1, device_memory() / 8 / (n * 12 + 1));
+  if (w.global_tab.fixed) {
+    // a workspace over fixed memory holds as many slabs as fit
+    mem_cap = w.global_tab.cap / (n * 12);
+    if (mem_cap == 0)
+      return set_error(LP_ERR_INVALID_ARGUMENT,
+                       "a source above the LDS capacity needs a dense accumulator of %zu bytes; the fixed "
+                       "scratch holds %zu",
+                       n * 12, w.global_tab.cap);
+  }
   const unsigned slabs = (unsigned)std::min<uint64_t>(std::min<uint64_t>(cfg.spa_wgs, nitems), mem_cap);
   if (w.global_slabs < slabs) {
     w.global_tab.release();
@@ -3302,6 +3311,10 @@ lp_status run_query(lp_graph* g, Workspace& w, const int32_t* sources, int64_t n
   if (po.bad_source) return set_error(LP_ERR_INVALID_ARGUMENT, "a source id is outside [0, n)");
   uint64_t cap = std::max<uint64_t>(po.wedges, 1);
   if (cap > (1ull << 32) - 1) return set_error(LP_ERR_OUT_OF_MEMORY, "query batch too large");
+  if (w.cand_s.fixed && cap * 4 > w.cand_s.cap)
+    return set_error(LP_ERR_INVALID_ARGUMENT,
+                     "the sources' two-hop path bound (%llu) exceeds the fixed scratch's candidate capacity (%zu)",
+                     (unsigned long long)cap, w.cand_s.cap / 4);
   LP_TRY(w.cand_s.ensure(cap * 4));
   LP_TRY(w.cand_a.ensure(cap * 4));
   LP_TRY(w.cand_c.ensure(cap * 4));

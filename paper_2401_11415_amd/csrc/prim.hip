@@ -36,6 +36,9 @@ thread_local size_t ScratchLimit::bytes = 0;
 
 lp_status DevBuf::ensure(size_t bytes) {
   if (bytes <= cap && p) return LP_OK;
+  if (fixed)
+    return set_error(LP_ERR_INVALID_ARGUMENT, "needs %zu bytes of a fixed scratch buffer of %zu bytes",
+                     bytes, cap);
   size_t want = bytes ? bytes : 256;
   if (ScratchLimit::bytes && want > ScratchLimit::bytes)
     return set_error(LP_ERR_OUT_OF_MEMORY, "scratch allocation of %zu bytes above the limit of %zu",
@@ -52,6 +55,7 @@ lp_status DevBuf::ensure(size_t bytes) {
 }
 
 void DevBuf::release() {
+  if (fixed) return;
   if (p) (void)hipFree(p);
   p = nullptr;
   cap = 0;
@@ -59,6 +63,9 @@ void DevBuf::release() {
 
 lp_status HostBuf::ensure(size_t bytes) {
   if (bytes <= cap && p) return LP_OK;
+  if (fixed)
+    return set_error(LP_ERR_INVALID_ARGUMENT, "needs %zu bytes of a fixed host staging buffer of %zu bytes",
+                     bytes, cap);
   release();
   size_t want = bytes ? bytes : 256;
   hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
@@ -72,6 +79,7 @@ lp_status HostBuf::ensure(size_t bytes) {
 }
 
 void HostBuf::release() {
+  if (fixed) return;
   if (p) (void)hipHostFree(p);
   p = nullptr;
   cap = 0;

@@ -55,6 +55,7 @@ def test_host_side_argument_errors(lib):
     assert lib.lp_predict(None, 1, 256, 10, 0.0, None, None, None, ctypes.byref(cnt), None) == 1
     assert cnt.value == 0
     assert lib.lp_query(None, None, 0, 1, 256, 10, 0.0, None, None, None, None) == 1
+    assert lib.lp_query_static(None, None, 0, 1, 256, 10, 0.0, None, None, None, None) == 1
     assert lib.lp_fingerprint(None, 256, None, None) == 1
     assert lib.lp_graph_destroy(None) == 0
 
