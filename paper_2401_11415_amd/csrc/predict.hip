@@ -2475,6 +2475,25 @@ __global__ __launch_bounds__(256) void count_ge_kernel(const uint32_t* __restric
   }
 }
 
+// Keys among the first n of the candidate buffer that are >= tau (read back).
+static lp_status count_ge(Workspace& w, const Emit& E, unsigned long long n, const uint32_t* tau,
+                          unsigned long long* out, hipStream_t st) {
+  unsigned long long* ge = E.fp;  // scratch counter
+  LP_HIP(hipMemsetAsync(ge, 0, 8, st));
+  if (n > 0) {
+    hipLaunchKernelGGL(count_ge_kernel, dim3(grid_for(n, 256 * kGeItems, num_cus() * 2)), dim3(256), 0, st,
+                       E.out_s, E.out_a, E.out_c, n, tau, ge);
+    LP_HIP(hipGetLastError());
+  }
+  PinnedReads reads(w);
+  LP_TRY(reads.add(out, ge, 8, st));
+  return reads.finish(st);
+}
+
+// A sampled threshold keeps only the score unless the keys tied with it
+// would exceed this many times k.
+constexpr unsigned long long kTieLimit = 3;
+
 lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int32_t* out_a,
                       int32_t* out_c, float* out_score, int64_t* out_count, hipStream_t st) {
   Workspace& w = g->ws;
@@ -2573,8 +2592,19 @@ lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int3
       if (retries > 0) LP_HIP(hipMemcpyAsync(count, &n_sample, 8, hipMemcpyHostToDevice, st));
       if (need_tau) {
         if (r_target >= n_sample) LP_HIP(hipMemsetAsync(tau, 0, 12, st));
-        else
+        else {
           LP_TRY(run_select(g, E.out_s, E.out_a, E.out_c, count, cap, 0, r_target, ts, ta, tc, tau, st));
+          // The score alone admits every key tied with the r-th one.  With
+          // integer-like scores (CN at small hub limits) that run can hold
+          // many times k keys, overflow the buffer and force a second pass;
+          // then the sample's r-th key itself (score and ids) is the bound,
+          // which the sample places about 1.5 k keys deep.
+          unsigned long long nge = 0;
+          LP_TRY(count_ge(w, E, n_sample, tau, &nge, st));
+          if (nge * (unsigned long long)stride > kTieLimit * (unsigned long long)k)
+            LP_TRY(run_select(g, E.out_s, E.out_a, E.out_c, count, cap, 0, r_target, ts, ta, tc, tau, st,
+                              true));
+        }
       }
     }
     unsigned long long n_total = 0;
@@ -2608,16 +2638,8 @@ lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int3
     if (!tau_zero) {
       // every candidate >= tau is in the buffer; the answer is there iff
       // at least k of them are
-      unsigned long long* ge = fp;  // scratch counter
-      LP_HIP(hipMemsetAsync(ge, 0, 8, st));
-      hipLaunchKernelGGL(count_ge_kernel, dim3(grid_for(n_total, 256 * kGeItems, num_cus() * 2)),
-                         dim3(256), 0, st, E.out_s, E.out_a, E.out_c, n_total,
-                         (const uint32_t*)tau, ge);
-      LP_HIP(hipGetLastError());
       unsigned long long nge = 0;
-      PinnedReads reads(w);
-      LP_TRY(reads.add(&nge, ge, 8, st));
-      LP_TRY(reads.finish(st));
+      LP_TRY(count_ge(w, E, n_total, tau, &nge, st));
       if (nge < (unsigned long long)k) {
         r_target = r_target >= n_sample / 4 ? n_sample : r_target * 4;
         need_tau = true;

@@ -444,6 +444,23 @@ def test_full_size_rmat22_topk_measures(lp, rmat22, m):
     assert_same_list(got, ref, m, f"R-MAT-22/{m}/L=256", graph=gr, L=256)
 
 
+@pytest.mark.parametrize("L", [32, 64])
+def test_full_size_rmat22_cn_ties(lp, rmat22, L):
+    """CN at small hub limits on the benchmark graph: counts are small
+    integers, so the keys tied with the sampled threshold's count number many
+    times k.  The list is still exact, and the call needs one pass (the
+    sampled key with its ids bounds the ties)."""
+    gr, k = rmat22
+    say(f"[gpu] R-MAT-22 predict CN L={L} k={k}")
+    with lp.Graph(gr.offsets, gr.indices) as g:
+        got = run_predict(lp, g, "CN", L, k)
+        st = lp.last_stats(g)
+    assert st["retries"] == 0, st["retries"]
+    assert st["appended"] < 4 * k, st["appended"]
+    ref = oracle.predict(gr, L, "CN", k)
+    assert_same_list(got, ref, "CN", f"R-MAT-22/CN/L={L}")
+
+
 @pytest.mark.parametrize("L", [1024, None])
 @pytest.mark.parametrize("m", ["JC", "AA"])
 def test_full_size_rmat22_query_wide(lp, rmat22, m, L):
