@@ -148,6 +148,8 @@ def main():
     ap.add_argument("--qps", type=float, default=200.0, help="--serve: request arrival rate")
     ap.add_argument("--requests", type=int, default=600, help="--serve: requests in the stream")
     ap.add_argument("--slots", type=int, default=2, help="--serve: concurrent batches")
+    ap.add_argument("--host-launches", action="store_true",
+                    help="--serve: launch every batch from the host instead of replaying captured graphs")
     ap.add_argument("--sweep", action="store_true",
                     help="hub-limit sweep instead: time and holdout precision / recall / F1 per "
                          "measure and L")
@@ -437,17 +439,18 @@ def sweep(args, lp, synth, torch):
 def serve(args, lp, synth, torch):
     measure = "AA" if args.measure.upper() == "JC" else args.measure.upper()
     res = run_serve(lp, synth, torch, args.scale, args.hub, measure, args.qps, args.requests, args.slots,
-                    args.cache)
+                    args.cache, host_launches=args.host_launches)
     print(json.dumps(res), flush=True)
 
 
-def run_serve(lp, synth, torch, scale, L, measure, qps, n_requests, slots, cache=""):
+def run_serve(lp, synth, torch, scale, L, measure, qps, n_requests, slots, cache="", host_launches=False):
     """Serving workload: a device-resident R-MAT graph (scale `scale`, edge
     factor 16, symmetrised, no holdout); requests arrive as a Poisson stream at
     `qps`, each with a log-uniform number of sources in [1, 4096] drawn with
     probability proportional to degree; each asks for the top 10 per source
     by DLH `measure` (hub limit L).  Latency is submit -> results in the
-    caller's buffers, on the host clock."""
+    caller's buffers, on the host clock.  Batches replay captured HIP graphs
+    unless host_launches."""
     import threading
     t0 = time.time()
     path = os.path.join(cache, f"rmat{scale}_full.npz") if cache else None
@@ -472,7 +475,7 @@ def run_serve(lp, synth, torch, scale, L, measure, qps, n_requests, slots, cache
     reqs = [nz[np.minimum(np.searchsorted(cdf, rng.uniform(0, cdf[-1], int(s))), nz.shape[0] - 1)]
             .astype(np.int32) for s in sizes]
     gaps = rng.exponential(1.0 / qps, n_requests)
-    srv = lp.Server(g, slots=slots)
+    srv = lp.Server(g, slots=slots, host_launches=host_launches)
     for r in reqs[:8]:  # warm-up: buffers grow to their working size
         srv.wait(srv.submit(r, measure, L, kq))
     tickets = [None] * len(reqs)
@@ -489,14 +492,16 @@ def run_serve(lp, synth, torch, scale, L, measure, qps, n_requests, slots, cache
     t_start = time.perf_counter()
     th = threading.Thread(target=producer)
     th.start()
-    lat, rows, batches = [], 0, {}
+    lat, run, rows, batches, replayed = [], [], 0, {}, 0
     for i in range(len(reqs)):
         while tickets[i] is None:
             time.sleep(0.0002)
         out, rec = srv.wait(tickets[i])
         lat.append(rec["total_ms"])
+        run.append(rec["run_ms"])
         rows += int(out[2].sum())
         batches[rec["batch"]] = rec["batch_requests"]
+        replayed += rec["replayed"] == 1
         if (i + 1) % 100 == 0:
             log(f"served {i + 1}/{len(reqs)}")
     th.join()
@@ -508,6 +513,8 @@ def run_serve(lp, synth, torch, scale, L, measure, qps, n_requests, slots, cache
     return {"metric": f"query latency p50/p99 and predicted edges/s (served, DLH {measure} top-{kq})",
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "mean_ms": float(lat.mean()), "value": rows / wall, "unit": "edges/s",
+            "batch_run_ms_p50": float(np.percentile(run, 50)),
+            "replayed_share": replayed / len(reqs), "host_launches": bool(host_launches),
             "sources_per_s": float(sizes.sum()) / wall, "requests": len(reqs),
             "offered_qps": qps, "achieved_qps": len(reqs) / wall, "slots": slots,
             "batches": len(batches), "mean_requests_per_batch": float(np.mean(list(batches.values()))),

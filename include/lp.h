@@ -269,14 +269,23 @@ lp_status lp_predict_multi(lp_graph *g, int64_t ngraphs, const int64_t *vstart, 
  * and every other queued request with the same measure, hub limit, k_q and
  * threshold whose sources, two-hop paths and device scratch still fit the
  * caps below, and runs them as one query.  The path count of a source s under
- * hub limit L is min(sum over b in Gamma(s) of d_b, d_s * L), an upper bound
- * of its wedges; it bounds the batch's candidate buffer.  A batch's device
+ * hub limit L is the sum of d_b over its neighbours b with d_b <= L: the
+ * wedges it explores, which bound its candidates (computed for all vertices
+ * on the first request with a given L and kept).  A batch's device
  * scratch is 24 bytes per path (candidates and sort space), the per-source
  * records and outputs, and 12 bytes per vertex for each source whose paths
  * plus degree exceed the LDS capacity (a dense global accumulator; at most as
  * many as a workspace holds).  A request above any cap runs alone.  Each request's result equals lp_query on that request alone.
  * Requests that arrive while batches run join the next batch of the slot that
  * frees first, so work of several requests overlaps on the device.
+ * By default a batch runs as a replayed HIP graph: the first batch of a
+ * shape (kind of request; source, candidate and dense-accumulator capacities
+ * in coarse classes) records the whole query, with every count read on the
+ * device, into a graph of its slot; later batches of that shape copy their
+ * sources in and replay it, with no host round trip between the copies.  A
+ * batch that outgrows the candidate capacity recorded for its kind runs on
+ * host launches, and the kind's capacity grows.  Results do not depend on
+ * the path taken.
  * ------------------------------------------------------------------------- */
 typedef struct lp_server lp_server;
 
@@ -286,12 +295,20 @@ typedef struct {
   int64_t max_batch_paths;   /* two-hop paths per batch (0: 2^27) */
   int64_t max_batch_bytes;   /* device scratch per batch (0: an eighth of the device
                                 memory divided among the slots) */
+  int64_t host_launches;     /* nonzero: every batch is launched from the host, as
+                                lp_query does, instead of replaying captured HIP graphs */
 } lp_server_config;
 
 typedef struct {
   lp_status status;        /* of the batch that served the request */
   uint64_t batch;          /* batch id (in launch order, from 1) */
   uint32_t batch_requests; /* requests served by that batch */
+  uint32_t replayed;       /* how that batch ran: 1 as a replayed HIP graph; 0 launched
+                              from the host (by configuration, or a shape beyond the
+                              scratch budget); 2 from the host after the replay
+                              outgrew the capacities recorded for its kind (the
+                              next batches get more); 3 from the host after a
+                              failed capture or replay */
   uint64_t batch_sources;  /* sources in that batch */
   uint64_t batch_bytes;    /* that batch's device scratch bound (bytes) */
   double queue_ms;         /* submit -> batch start (host clock) */

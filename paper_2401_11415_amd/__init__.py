@@ -68,12 +68,14 @@ class _Stats(ctypes.Structure):
 
 class _ServerConfig(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_int32), ("max_batch_sources", ctypes.c_int64),
-                ("max_batch_paths", ctypes.c_int64), ("max_batch_bytes", ctypes.c_int64)]
+                ("max_batch_paths", ctypes.c_int64), ("max_batch_bytes", ctypes.c_int64),
+                ("host_launches", ctypes.c_int64)]
 
 
 class _RequestInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("batch", ctypes.c_uint64),
-                ("batch_requests", ctypes.c_uint32), ("batch_sources", ctypes.c_uint64),
+                ("batch_requests", ctypes.c_uint32), ("replayed", ctypes.c_uint32),
+                ("batch_sources", ctypes.c_uint64),
                 ("batch_bytes", ctypes.c_uint64),
                 ("queue_ms", ctypes.c_double), ("run_ms", ctypes.c_double),
                 ("total_ms", ctypes.c_double)]
@@ -367,9 +369,10 @@ class Server:
     count [n]) numpy arrays and the request's timing / batch record."""
 
     def __init__(self, g: Graph, slots: int = 0, max_batch_sources: int = 0,
-                 max_batch_paths: int = 0, max_batch_bytes: int = 0):
+                 max_batch_paths: int = 0, max_batch_bytes: int = 0, host_launches: bool = False):
         lib = load()
-        cfg = _ServerConfig(slots, max_batch_sources, max_batch_paths, max_batch_bytes)
+        cfg = _ServerConfig(slots, max_batch_sources, max_batch_paths, max_batch_bytes,
+                            1 if host_launches else 0)
         h = ctypes.c_void_p()
         _check(lib.lp_server_create(g.handle, ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

@@ -152,6 +152,8 @@ uint32_t hub_start(const lp_graph* g, int64_t L);
 // Device primitives (prim.hip)
 // ---------------------------------------------------------------------------
 
+// scratch bytes that a scan of n entries needs (either scan below)
+size_t scan_scratch_bytes(int64_t n);
 // exclusive scan of n uint32 into out (n entries), optional total
 lp_status scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, DevBuf& tmp,
                              hipStream_t st);
@@ -170,6 +172,48 @@ struct SortSpec {
 };
 lp_status radix_sort(const SortSpec& spec, int64_t n, DevBuf tmp[4], DevBuf& counts,
                      DevBuf& scan_tmp, hipStream_t st);
+// The same over at most n_cap records whose count is read on the device
+// (*n_dev), with no host round trip; the sorted words are left where the
+// last pass put them (where[k]).  Buffers must already hold n_cap records.
+lp_status radix_sort_device_count(const SortSpec& spec, int64_t n_cap, const unsigned long long* n_dev,
+                                  DevBuf tmp[4], DevBuf& counts, DevBuf& scan_tmp, hipStream_t st,
+                                  uint32_t** where);
+
+// ---------------------------------------------------------------------------
+// The per-source query with every count on the device (predict.hip), for
+// replay as a HIP graph: reserve() sizes the workspace for a shape (moved:
+// some buffer was reallocated, so launches recorded earlier are stale; new
+// dense slabs are cleared on st, before anything recorded later runs there);
+// enqueue() issues the whole call with no host round trip, allocation or
+// memset, reading the query count and sources from pinned host_in
+// (query_device_in_bytes: u32 count at 0, sources from byte 64) and writing
+// status words and results to pinned host_out (query_device_out_bytes:
+// results from byte 512: c and score, qcap * kq each, then the per-query
+// counts); status() checks the status words after the stream has finished.
+// ---------------------------------------------------------------------------
+struct QueryShape {
+  int m;
+  int64_t L;
+  int32_t kq;
+  float s_th;
+  uint32_t qcap;   // sources per call, at most
+  uint64_t pcap;   // two-hop paths (candidates) per call, at most
+  unsigned slabs;  // dense accumulators (sources above the LDS capacity, overflowing tables)
+  unsigned rounds; // rounds of `slabs` such sources (more of them: run again on the host-driven path)
+};
+size_t query_device_in_bytes(uint32_t qcap);
+// a digest of the workspace buffers (and dense slabs) that recorded launches
+// point into: recorded launches are stale once it changes
+uint64_t query_device_layout(const Workspace& w);
+size_t query_device_out_bytes(uint32_t qcap, int32_t kq);
+lp_status query_device_reserve(lp_graph* g, Workspace& w, const QueryShape& sh, bool* moved, hipStream_t st);
+lp_status query_device_enqueue(lp_graph* g, Workspace& w, const QueryShape& sh, const void* host_in,
+                               void* host_out, hipStream_t st);
+// LP_ERR_OUT_OF_MEMORY (with no message) when the call exceeded the shape's
+// capacities and must run again on the host-driven path; *candidates: the
+// candidates the call emitted
+lp_status query_device_status(const void* host_out, const QueryShape& sh, uint32_t nq,
+                              uint64_t* candidates);
 
 int num_cus();
 // total memory of the current device in bytes (cached on first use)

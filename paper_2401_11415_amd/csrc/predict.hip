@@ -216,9 +216,13 @@ __global__ __launch_bounds__(256) void query_plan_kernel(GView g, uint32_t hub_s
                                                          const int32_t* __restrict__ src,
                                                          const uint32_t* __restrict__ rank,
                                                          uint32_t nq, SrcRec* __restrict__ lists,
-                                                         PlanOut* __restrict__ out) {
+                                                         PlanOut* __restrict__ out,
+                                                         const uint32_t* __restrict__ nq_dev) {
   __shared__ unsigned long long part[4];
-  for (uint32_t q = blockIdx.x; q < nq; q += gridDim.x) {
+  // nq: the stride of the bucket lists; with nq_dev the queries themselves
+  // are counted on the device (at most nq)
+  const uint32_t nreq = nq_dev ? min(*nq_dev, nq) : nq;
+  for (uint32_t q = blockIdx.x; q < nreq; q += gridDim.x) {
     const int32_t so = src[q];
     const bool ok = so >= 0 && (uint32_t)so < g.n;
     if (!ok && threadIdx.x == 0) atomicOr(&out->bad_source, 1u);
@@ -1023,6 +1027,7 @@ struct SpaItem {
   const uint32_t* ovf;  // if non-null: overflow entries (pass | P << 8) ...
   const SrcRec* recs;   // ... and their source records
   uint32_t ovf_begin, ovf_end;
+  const uint32_t* end_dev = nullptr;  // if set: the end is read on the device (at most ovf_end)
 };
 
 constexpr int kSpaThreads = 1024;
@@ -1058,7 +1063,9 @@ __global__ __launch_bounds__(kSpaThreads) void acc_spa_kernel(GView g, Emit E, W
   uint32_t* K = spa_keys + (uint64_t)blockIdx.x * g.n;
   FpAcc fa;
   WorkAcc wk;
-  const uint32_t total = ov.ovf ? (ov.ovf_end - ov.ovf_begin) : uniform(work_count(wl));
+  uint32_t ovf_end = ov.ovf_end;
+  if (ov.ovf && ov.end_dev) ovf_end = uniform(min(*ov.end_dev, ovf_end));
+  const uint32_t total = ov.ovf ? (ovf_end > ov.ovf_begin ? ovf_end - ov.ovf_begin : 0u) : uniform(work_count(wl));
   for (uint32_t i = blockIdx.x; i < total; i += gridDim.x) {
     SrcRec s;
     uint32_t p0 = 0, P = 1;
@@ -1176,7 +1183,17 @@ struct SpaRound {
   uint32_t* keys;    // key list j at keys + j * n
   uint32_t* hist;    // query with sums: n x kSumBins bins of the sources' sums (zeroed) ...
   unsigned long long* floor_sum;  // ... and n per-source floors: the k_q-th largest sum's bin
+  // if set: the work list's length, read on the device; the round then holds
+  // min(n, length - i0) items (n is the slab count)
+  const uint32_t* len_dev = nullptr;
 };
+
+__device__ inline uint32_t round_items(const SpaRound& R) {
+  if (!R.len_dev) return R.n;
+  const uint32_t len = *R.len_dev;
+  const uint32_t left = len > R.i0 ? len - R.i0 : 0u;
+  return left < R.n ? left : R.n;
+}
 
 constexpr uint32_t kSpaPiece = kSpaThreads;  // arcs or keys per piece
 
@@ -1184,6 +1201,7 @@ constexpr uint32_t kSpaPiece = kSpaThreads;  // arcs or keys per piece
 // ceil(keys / 1024) (mode 1); one workgroup
 __global__ __launch_bounds__(1024) void spa_pieces_kernel(SpaRound R, int mode) {
   __shared__ uint32_t tmp[16];
+  R.n = round_items(R);
   uint32_t* out = mode == 0 ? R.poff : R.koff;
   uint32_t run = 0;
   for (uint32_t j0 = 0; j0 < R.n; j0 += 1024) {
@@ -1214,6 +1232,7 @@ __device__ inline uint32_t spa_piece_source(const uint32_t* off, uint32_t n, uin
 
 template <bool kW, bool kQuery, bool kSampled>
 __global__ __launch_bounds__(kSpaThreads) void spa_split_acc_kernel(GView g, Emit E, SpaRound R) {
+  R.n = uniform(round_items(R));
   constexpr int T = kSpaThreads;
   constexpr int NW = T / 64;
   __shared__ uint32_t s_excl[T], s_start[T], scan_tmp[NW];
@@ -1267,6 +1286,7 @@ __global__ __launch_bounds__(kSpaThreads) void spa_split_acc_kernel(GView g, Emi
 // workgroup per source; the source's work counters are taken here)
 template <bool kW, bool kQuery, bool kSampled>
 __global__ __launch_bounds__(kSpaThreads) void spa_split_excl_kernel(GView g, Emit E, SpaRound R) {
+  R.n = uniform(round_items(R));
   WorkAcc wk;
   for (uint32_t j = blockIdx.x; j < R.n; j += gridDim.x) {
     const SrcRec s = uniform_rec(load_rec(R.wl, R.i0 + j));
@@ -1291,6 +1311,7 @@ __global__ __launch_bounds__(kSpaThreads) void spa_split_excl_kernel(GView g, Em
 // only sums at or above it, so a hub no longer emits millions of candidates.
 template <bool kW, bool kQuery, bool kSampled>
 __global__ __launch_bounds__(kSpaThreads) void spa_split_hist_kernel(GView g, Emit E, SpaRound R) {
+  R.n = uniform(round_items(R));
   __shared__ uint32_t lh[kSumBins];
   const uint32_t total = uniform(R.koff[R.n]);
   for (uint32_t q = blockIdx.x; q < total; q += gridDim.x) {
@@ -1314,6 +1335,7 @@ __global__ __launch_bounds__(kSpaThreads) void spa_split_hist_kernel(GView g, Em
 
 // one wave per source of the round
 __global__ __launch_bounds__(64) void spa_split_floor_kernel(SpaRound R, uint32_t kq) {
+  R.n = round_items(R);
   const uint32_t j = blockIdx.x;
   if (j >= R.n) return;
   const uint64_t f = sum_floor_wave(R.hist + (uint64_t)j * kSumBins, kq);
@@ -1323,6 +1345,7 @@ __global__ __launch_bounds__(64) void spa_split_floor_kernel(SpaRound R, uint32_
 // score and emit pieces of 1024 keys, clearing the slab behind them
 template <bool kW, bool kQuery, bool kSampled>
 __global__ __launch_bounds__(kSpaThreads) void spa_split_sweep_kernel(GView g, Emit E, SpaRound R) {
+  R.n = uniform(round_items(R));
   constexpr int NW = kSpaThreads / 64;
   __shared__ uint32_t st_c[NW][kSpaStage], st_h[NW][kSpaStage], st_k[NW][kSpaStage],
       st_d[NW][kSpaStage], st_w2[kW ? NW : 1][kW ? kSpaStage : 1];
@@ -1654,13 +1677,18 @@ __global__ void query_take_kernel(const uint32_t* __restrict__ s, const uint32_t
                                   const uint32_t* __restrict__ seg_start,
                                   const uint32_t* __restrict__ seg_count, uint32_t nq, int32_t kq,
                                   int32_t* __restrict__ out_c, float* __restrict__ out_s,
-                                  int32_t* __restrict__ out_count) {
+                                  int32_t* __restrict__ out_count, const uint32_t* __restrict__ nq_dev,
+                                  uint64_t cap) {
+  // nq_dev: the query count is read on the device (at most nq); cap: the
+  // candidate buffer's size (a call whose candidates outgrew it is discarded
+  // by the host, but its reads stay inside the buffer)
+  if (nq_dev) nq = min(*nq_dev, nq);
   for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (uint64_t)nq * kq;
        t += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t q = (uint32_t)(t / (uint32_t)kq), j = (uint32_t)(t % (uint32_t)kq);
     const uint32_t m = seg_count[q] < (uint32_t)kq ? seg_count[q] : (uint32_t)kq;
     if (j == 0) out_count[q] = (int32_t)m;
-    if (j < m) {
+    if (j < m && (uint64_t)seg_start[q] + j < cap) {
       out_c[t] = (int32_t)c[seg_start[q] + j];
       out_s[t] = __uint_as_float(s[seg_start[q] + j]);
     }
@@ -2336,11 +2364,14 @@ struct Timer {
   }
 };
 
-static lp_status ensure_ovf(Workspace& w, uint32_t** ovf, void** ovf_rec, uint32_t** ovf_count,
-                            uint32_t* cap, uint32_t** err, unsigned long long** count,
-                            unsigned long long** fp, uint32_t** tau, hipStream_t st) {
-  const uint32_t ocap = 1u << 16;
-  LP_TRY(w.counters.ensure(4096 + (size_t)ocap * (4 + sizeof(SrcRec))));
+constexpr uint32_t kOvfCap = 1u << 16;  // overflow records of a call
+constexpr size_t kCountersBytes = 4096 + (size_t)kOvfCap * (4 + sizeof(SrcRec));
+
+// The counters block: call-wide counters in its first 4096 bytes (zeroed
+// per call), then the overflow list.
+static void ovf_layout(Workspace& w, uint32_t** ovf, void** ovf_rec, uint32_t** ovf_count, uint32_t* cap,
+                       uint32_t** err, unsigned long long** count, unsigned long long** fp, uint32_t** tau) {
+  const uint32_t ocap = kOvfCap;
   char* base = w.counters.as<char>();
   *count = reinterpret_cast<unsigned long long*>(base);   // [0]
   *fp = reinterpret_cast<unsigned long long*>(base + 64);  // [3]
@@ -2350,7 +2381,14 @@ static lp_status ensure_ovf(Workspace& w, uint32_t** ovf, void** ovf_rec, uint32
   *ovf = reinterpret_cast<uint32_t*>(base + 4096);
   *ovf_rec = base + 4096 + (size_t)ocap * 4;
   *cap = ocap;
-  LP_HIP(hipMemsetAsync(base, 0, 4096, st));
+}
+
+static lp_status ensure_ovf(Workspace& w, uint32_t** ovf, void** ovf_rec, uint32_t** ovf_count,
+                            uint32_t* cap, uint32_t** err, unsigned long long** count,
+                            unsigned long long** fp, uint32_t** tau, hipStream_t st) {
+  LP_TRY(w.counters.ensure(kCountersBytes));
+  ovf_layout(w, ovf, ovf_rec, ovf_count, cap, err, count, fp, tau);
+  LP_HIP(hipMemsetAsync(w.counters.p, 0, 4096, st));
   return LP_OK;
 }
 
@@ -3324,7 +3362,8 @@ lp_status run_query(lp_graph* g, Workspace& w, const int32_t* sources, int64_t n
   const AccConfig cfg = acc_config(g);
   const GView gv = view_of(g);
   hipLaunchKernelGGL(query_plan_kernel, dim3(grid_for(Q, 1, 65536)), dim3(256), 0, st, gv, hub,
-                     cfg.cuts, w.q_src.as<int32_t>(), g->rank, (uint32_t)Q, qlists, d_out);
+                     cfg.cuts, w.q_src.as<int32_t>(), g->rank, (uint32_t)Q, qlists, d_out,
+                     (const uint32_t*)nullptr);
   LP_HIP(hipGetLastError());
   PlanOut* hp = w.host_stats.as<PlanOut>();
   LP_HIP(hipMemcpyAsync(hp, d_out, sizeof(PlanOut), hipMemcpyDeviceToHost, st));
@@ -3421,7 +3460,8 @@ lp_status run_query(lp_graph* g, Workspace& w, const int32_t* sources, int64_t n
     dn = reinterpret_cast<int32_t*>(ds + tot);
   }
   hipLaunchKernelGGL(query_take_kernel, dim3(grid_for(tot, 256, 65536)), dim3(256), 0, st,
-                     E.out_s, E.out_c, seg_start, seg_count, (uint32_t)Q, kq, dc, ds, dn);
+                     E.out_s, E.out_c, seg_start, seg_count, (uint32_t)Q, kq, dc, ds, dn,
+                     (const uint32_t*)nullptr, (uint64_t)cap);
   LP_HIP(hipGetLastError());
   if (!dev_out) {
     LP_HIP(hipMemcpyAsync(out_c, dc, tot * 4, hipMemcpyDefault, st));
@@ -3432,6 +3472,261 @@ lp_status run_query(lp_graph* g, Workspace& w, const int32_t* sources, int64_t n
   LP_HIP(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, st));
   LP_HIP(hipStreamSynchronize(st));
   if (herr) return set_error(LP_ERR_DEVICE, "device error flags 0x%x", herr);
+  return LP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The query path with every count on the device, for replay as a HIP graph:
+// no host round trip, no allocation and no memset node between its first
+// and last operation.  Sizes come from capacities fixed by the caller (the
+// server's admission): at most qcap sources, a two-hop path bound (candidate
+// capacity) of pcap, and `slabs` dense accumulators for sources above the LDS
+// capacity and for overflowing tables (one workgroup each).  The host reads
+// the call's status words afterwards; a batch whose candidates exceeded pcap
+// or whose overflow list filled is run again by run_query.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+__global__ void zero_words_kernel(uint32_t* __restrict__ a, uint32_t na, uint32_t* __restrict__ b, uint32_t nb,
+                                  uint32_t* __restrict__ c, uint32_t nc) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < na + nb + nc; i += stride) {
+    if (i < na) a[i] = 0;
+    else if (i < na + nb) b[i - na] = 0;
+    else c[i - na - nb] = 0;
+  }
+}
+
+// Scratch layout of the device query path (byte offsets into w.q_src and
+// w.q_out; the pinned buffers mirror the first 64 bytes of each).
+constexpr size_t kQHead = 64;     // q_src: the query count (u32), then the sources at kQHead
+constexpr size_t kDqStatus = 512;  // host output: counters (256 B) and the plan record, then results
+
+size_t dq_out_bytes(uint32_t qcap, int32_t kq) { return (size_t)qcap * kq * 8 + (size_t)qcap * 4; }
+
+}  // namespace
+
+// Layout of w.spa_meta for `slabs` sources per round: piece offsets of arcs
+// and keys and the key counts (u32, slabs + 1 each), then per-source floors
+// (u64) and sum histograms (u32, kSumBins each).
+static size_t spa_meta_u32(unsigned slabs) { return ((size_t)slabs * 3 + 8 + 1) & ~(size_t)1; }
+static size_t spa_meta_bytes(unsigned slabs) {
+  return spa_meta_u32(slabs) * 4 + (size_t)slabs * 8 + (size_t)slabs * kSumBins * 4;
+}
+
+size_t query_device_in_bytes(uint32_t qcap) { return kQHead + (size_t)qcap * 4; }
+size_t query_device_out_bytes(uint32_t qcap, int32_t kq) { return kDqStatus + dq_out_bytes(qcap, kq); }
+
+uint64_t query_device_layout(const Workspace& w) {
+  const void* p[16] = {w.q_src.p,      w.q_rows.p,      w.stats.p,       w.counters.p,    w.cand_s.p,
+                       w.cand_a.p,     w.cand_c.p,      w.q_cnt.p,       w.global_tab.p,  w.sort_tmp[0].p,
+                       w.sort_tmp[1].p, w.sort_tmp[2].p, w.sort_counts.p, w.scan_tmp.p,    w.q_out.p,
+                       w.spa_meta.p};
+  uint64_t h = 0x9E3779B97F4A7C15ull ^ w.global_slabs;
+  for (const void* q : p) {
+    h ^= (uint64_t)(uintptr_t)q;
+    h *= 0xBF58476D1CE4E5B9ull;
+    h ^= h >> 31;
+  }
+  return h;
+}
+
+lp_status query_device_reserve(lp_graph* g, Workspace& w, const QueryShape& sh, bool* moved, hipStream_t st) {
+  const uint64_t before = query_device_layout(w);
+  const uint64_t Q = sh.qcap;
+  LP_TRY(w.q_src.ensure(query_device_in_bytes(sh.qcap)));
+  LP_TRY(w.q_rows.ensure(Q * sizeof(SrcRec) * kBuckets + 256));
+  LP_TRY(w.stats.ensure(sizeof(PlanOut) + 64));
+  LP_TRY(w.counters.ensure(kCountersBytes));
+  LP_TRY(w.cand_s.ensure(sh.pcap * 4));
+  LP_TRY(w.cand_a.ensure(sh.pcap * 4));
+  LP_TRY(w.cand_c.ensure(sh.pcap * 4));
+  LP_TRY(w.q_cnt.ensure(Q * 8 + 64));
+  const size_t n = (size_t)g->n;
+  if (w.global_slabs < sh.slabs) {
+    w.global_tab.release();
+    w.global_slabs = 0;
+    LP_TRY(w.global_tab.ensure((size_t)sh.slabs * n * 12));
+    // accumulators start at zero and every workgroup leaves its slab so; the
+    // clearing is ordered before the launches on the same stream (a
+    // non-blocking stream does not wait for the null stream)
+    LP_HIP(hipMemsetAsync(w.global_tab.p, 0, (size_t)sh.slabs * n * 8, st));
+    w.global_slabs = sh.slabs;
+  }
+  LP_TRY(w.spa_meta.ensure(spa_meta_bytes(std::max(1u, w.global_slabs))));
+  const int64_t ntiles = ((int64_t)sh.pcap + 2047) / 2048;
+  for (int k = 0; k < 3; k++) LP_TRY(w.sort_tmp[k].ensure(sh.pcap * 4));
+  LP_TRY(w.sort_counts.ensure((size_t)ntiles * 256 * 4 * 2));
+  // the scans: sort counts (ntiles * 256 words) and the per-query counts
+  const int64_t nscan = std::max<int64_t>(ntiles * 256, (int64_t)Q);
+  LP_TRY(w.scan_tmp.ensure(scan_scratch_bytes(nscan)));
+  LP_TRY(w.q_out.ensure(dq_out_bytes(sh.qcap, sh.kq) + 64));
+  *moved = query_device_layout(w) != before;
+  return LP_OK;
+}
+
+// `rounds` split rounds over the work list wl, sizes read on the device.
+template <bool kW>
+static lp_status split_rounds_device(lp_graph* g, Workspace& w, const GView& gv, const Emit& E, const WorkList& wl,
+                                     unsigned slabs, unsigned rounds, hipStream_t st) {
+  uint32_t* meta = w.spa_meta.as<uint32_t>();
+  const size_t u32_meta = spa_meta_u32(slabs);
+  unsigned long long* floor_sum = reinterpret_cast<unsigned long long*>(meta + u32_meta);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(floor_sum + slabs);
+  const bool floors = kW && E.kq > 0;
+  char* base = w.global_tab.as<char>();
+  uint32_t* spa_keys = reinterpret_cast<uint32_t*>(base + (size_t)w.global_slabs * (size_t)g->n * 8);
+  const unsigned grid = (unsigned)num_cus() * 4;
+  for (unsigned r = 0; r < rounds; r++) {
+    SpaRound R{wl,   r * slabs, slabs, meta, meta + slabs + 1, meta + 2 * (slabs + 1), base, spa_keys,
+               hist, floors ? floor_sum : nullptr, wl.count_dev};
+    const uint32_t nh = floors ? slabs * kSumBins : 0u;
+    hipLaunchKernelGGL(zero_words_kernel, dim3(grid_for((uint64_t)slabs + nh, 256, 1024)), dim3(256), 0, st,
+                       R.nkeys, slabs, floors ? hist : nullptr, nh, (uint32_t*)nullptr, 0u);
+    hipLaunchKernelGGL(spa_pieces_kernel, dim3(1), dim3(1024), 0, st, R, 0);
+    hipLaunchKernelGGL((spa_split_acc_kernel<kW, true, false>), dim3(grid), dim3(kSpaThreads), 0, st, gv, E, R);
+    hipLaunchKernelGGL((spa_split_excl_kernel<kW, true, false>), dim3(slabs), dim3(kSpaThreads), 0, st, gv, E, R);
+    hipLaunchKernelGGL(spa_pieces_kernel, dim3(1), dim3(1024), 0, st, R, 1);
+    if (floors) {
+      hipLaunchKernelGGL((spa_split_hist_kernel<kW, true, false>), dim3(grid), dim3(kSpaThreads), 0, st, gv, E, R);
+      hipLaunchKernelGGL(spa_split_floor_kernel, dim3(slabs), dim3(64), 0, st, R, E.kq);
+    }
+    hipLaunchKernelGGL((spa_split_sweep_kernel<kW, true, false>), dim3(grid), dim3(kSpaThreads), 0, st, gv, E, R);
+    LP_HIP(hipGetLastError());
+  }
+  return LP_OK;
+}
+
+lp_status query_device_enqueue(lp_graph* g, Workspace& w, const QueryShape& sh, const void* host_in,
+                               void* host_out, hipStream_t st) {
+  const uint32_t Q = sh.qcap;
+  const int32_t kq = sh.kq;
+  // inputs: the query count and the sources, from pinned host memory
+  LP_HIP(hipMemcpyAsync(w.q_src.p, host_in, query_device_in_bytes(Q), hipMemcpyHostToDevice, st));
+  const uint32_t* nq_dev = w.q_src.as<uint32_t>();
+  const int32_t* src = reinterpret_cast<const int32_t*>(w.q_src.as<char>() + kQHead);
+  SrcRec* qlists = w.q_rows.as<SrcRec>();
+  PlanOut* d_out = w.stats.as<PlanOut>();
+  uint32_t* seg_count = w.q_cnt.as<uint32_t>();
+  uint32_t* seg_start = seg_count + Q;
+  uint32_t *ovf, *ovf_count, *err, *tau;
+  void* ovf_rec;
+  unsigned long long *count, *fp;
+  uint32_t ovf_cap;
+  ovf_layout(w, &ovf, &ovf_rec, &ovf_count, &ovf_cap, &err, &count, &fp, &tau);
+  hipLaunchKernelGGL(zero_words_kernel, dim3(grid_for((uint64_t)Q + 2048, 256, 1024)), dim3(256), 0, st,
+                     reinterpret_cast<uint32_t*>(d_out), (uint32_t)(sizeof(PlanOut) / 4), seg_count, Q,
+                     w.counters.as<uint32_t>(), 1024u);
+  LP_HIP(hipGetLastError());
+  const uint32_t hub = hub_start(g, sh.L);
+  const AccConfig cfg = acc_config(g);
+  const GView gv = view_of(g);
+  hipLaunchKernelGGL(query_plan_kernel, dim3(grid_for(Q, 1, 65536)), dim3(256), 0, st, gv, hub, cfg.cuts, src,
+                     g->rank, Q, qlists, d_out, nq_dev);
+  LP_HIP(hipGetLastError());
+  Emit E{};
+  E.measure = sh.m;
+  LP_TRY(weighted_shift(g, sh.m, sh.L, &E.shift));
+  E.s_th = sh.s_th;
+  E.tau = tau;
+  E.out_s = w.cand_s.as<uint32_t>();
+  E.out_a = w.cand_a.as<uint32_t>();
+  E.out_c = w.cand_c.as<uint32_t>();
+  E.out_count = count;
+  E.cap = sh.pcap;
+  E.q_count = seg_count;
+  E.kq = (uint32_t)kq;
+  E.fp = fp;
+  E.ovf = ovf;
+  E.ovf_rec = ovf_rec;
+  E.ovf_count = ovf_count;
+  E.ovf_cap = ovf_cap;
+  E.err = err;
+  unsigned long long* work = work_counters(w);
+  const bool kw = sh.m == LP_AA || sh.m == LP_RA;
+  char* base = w.global_tab.as<char>();
+  uint32_t* spa_keys = reinterpret_cast<uint32_t*>(base + (size_t)w.global_slabs * (size_t)g->n * 8);
+  const unsigned slabs = std::max(1u, w.global_slabs);
+  for (int b = kBuckets - 1; b >= 0; b--) {
+    WorkList wl{qlists + (uint64_t)b * Q, 0, 1, 0, &d_out->count[b]};
+    E.work = work + b * 8;
+    if (b == kBucketHuge) {
+      // sources above the LDS capacity: rounds of one dense slab each, every
+      // source split over all CUs (as the host-driven path does for a few);
+      // a shape with no rounds has none of them
+      if (sh.rounds == 0) continue;
+      if (kw) LP_TRY(split_rounds_device<true>(g, w, gv, E, wl, slabs, sh.rounds, st));
+      else LP_TRY(split_rounds_device<false>(g, w, gv, E, wl, slabs, sh.rounds, st));
+    } else if (kw) {
+      LP_TRY((launch_bucket_tables<kTabSplit, true, false>(g, b, gv, E, wl, Q, st)));
+    } else {
+      LP_TRY((launch_bucket_tables<kTabCount, true, false>(g, b, gv, E, wl, Q, st)));
+    }
+  }
+  // partitions of sources whose LDS table filled up, on the dense accumulators
+  E.work = work + kBucketHuge * 8;
+  {
+    const WorkList none{nullptr, 0, 1, 0};
+    const SpaItem ov{ovf, static_cast<const SrcRec*>(ovf_rec), 0, ovf_cap, ovf_count};
+    if (kw)
+      hipLaunchKernelGGL((acc_spa_kernel<true, true, false>), dim3(slabs), dim3(kSpaThreads), 0, st, gv, E, none,
+                         ov, base, spa_keys);
+    else
+      hipLaunchKernelGGL((acc_spa_kernel<false, true, false>), dim3(slabs), dim3(kSpaThreads), 0, st, gv, E,
+                         none, ov, base, spa_keys);
+    LP_HIP(hipGetLastError());
+  }
+  // by (query index asc, score desc, c asc), over the candidates counted on the device
+  SortSpec sp{};
+  sp.w[0] = E.out_a;
+  sp.w[1] = E.out_s;
+  sp.w[2] = E.out_c;
+  sp.nwords = 3;
+  sp.nkeys = 3;
+  sp.key_bits[0] = id_bits(Q);
+  sp.key_bits[1] = 32;
+  sp.key_bits[2] = id_bits((uint64_t)g->n);
+  sp.invert[0] = false;
+  sp.invert[1] = true;
+  sp.invert[2] = false;
+  uint32_t* where[4];
+  LP_TRY(radix_sort_device_count(sp, (int64_t)sh.pcap, count, w.sort_tmp, w.sort_counts, w.scan_tmp, st, where));
+  LP_TRY(scan_exclusive_u32(seg_count, seg_start, (int64_t)Q, w.scan_tmp, st));
+  const uint64_t tot = (uint64_t)Q * (uint64_t)kq;
+  int32_t* dc = w.q_out.as<int32_t>();
+  float* ds = reinterpret_cast<float*>(dc + tot);
+  int32_t* dn = reinterpret_cast<int32_t*>(ds + tot);
+  hipLaunchKernelGGL(query_take_kernel, dim3(grid_for(tot, 256, 65536)), dim3(256), 0, st, where[1], where[2],
+                     seg_start, seg_count, Q, kq, dc, ds, dn, nq_dev, (uint64_t)sh.pcap);
+  LP_HIP(hipGetLastError());
+  // status words (counters block: candidate count, overflow count, error
+  // flags) and the plan's record, then the results
+  char* ho = static_cast<char*>(host_out);
+  LP_HIP(hipMemcpyAsync(ho, w.counters.p, 256, hipMemcpyDeviceToHost, st));
+  LP_HIP(hipMemcpyAsync(ho + 256, d_out, sizeof(PlanOut), hipMemcpyDeviceToHost, st));
+  LP_HIP(hipMemcpyAsync(ho + kDqStatus, dc, dq_out_bytes(Q, kq), hipMemcpyDeviceToHost, st));
+  return LP_OK;
+}
+
+lp_status query_device_status(const void* host_out, const QueryShape& sh, uint32_t nq,
+                              uint64_t* candidates) {
+  const char* ho = static_cast<const char*>(host_out);
+  unsigned long long n_total;
+  uint32_t ovf_total, herr;
+  PlanOut po;
+  std::memcpy(&n_total, ho, 8);
+  std::memcpy(&ovf_total, ho + 128, 4);
+  std::memcpy(&herr, ho + 192, 4);
+  std::memcpy(&po, ho + 256, sizeof(PlanOut));
+  if (candidates) *candidates = n_total;
+  if (po.bad_source) return set_error(LP_ERR_INVALID_ARGUMENT, "a source id is outside [0, n)");
+  if (herr) return set_error(LP_ERR_DEVICE, "device error flags 0x%x", herr);
+  (void)nq;
+  // beyond the capacities of the replayed launches: the caller runs the
+  // batch again on the host-driven path
+  if (n_total > sh.pcap || ovf_total > kOvfCap || po.count[kBucketHuge] > (uint64_t)sh.rounds * sh.slabs)
+    return LP_ERR_OUT_OF_MEMORY;
   return LP_OK;
 }
 

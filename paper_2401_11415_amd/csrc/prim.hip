@@ -227,6 +227,8 @@ static size_t scan_tmp_bytes(int64_t n, size_t elem) {
   return total;
 }
 
+size_t scan_scratch_bytes(int64_t n) { return scan_tmp_bytes(n, sizeof(uint64_t)); }
+
 lp_status scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, DevBuf& tmp,
                              hipStream_t st) {
   LP_TRY(tmp.ensure(scan_tmp_bytes(n, sizeof(uint32_t))));
@@ -257,8 +259,15 @@ struct PassArgs {
   int nwords;
   int key_word;
   int shift;
-  uint32_t invert;  // all-ones to complement the key word
+  uint32_t invert;                 // all-ones to complement the key word
+  const unsigned long long* n_dev;  // if set: the record count, read on the device (at most n)
 };
+
+__device__ inline int64_t records_of(const PassArgs& p, int64_t n) {
+  if (!p.n_dev) return n;
+  const unsigned long long d = *p.n_dev;
+  return d < (unsigned long long)n ? (int64_t)d : n;
+}
 
 __device__ inline uint32_t digit_of(const PassArgs& p, int64_t i) {
   uint32_t k = p.in[p.key_word][i] ^ p.invert;
@@ -275,6 +284,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_count_kernel(PassArgs p, i
                                                                    uint32_t* __restrict__ counts,
                                                                    int64_t ntiles) {
   __shared__ uint32_t hist[kCountCopies][257];
+  n = records_of(p, n);
   for (int j = 0; j < kCountCopies; j++) hist[j][threadIdx.x] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
@@ -314,6 +324,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(PassArgs p,
   constexpr int kRounds = kSortTile / kWaves / 64;  // rounds of 64 records per wave
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  n = records_of(p, n);
   for (int w = 0; w < kWaves; w++) L.wcnt[w][threadIdx.x] = 0;
   L.gbase[threadIdx.x] = offs[(int64_t)threadIdx.x * ntiles + blockIdx.x];
   __syncthreads();
@@ -378,9 +389,18 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(PassArgs p,
   }
 }
 
-lp_status radix_sort(const SortSpec& spec, int64_t n, DevBuf tmp[4], DevBuf& counts,
-                     DevBuf& scan_tmp, hipStream_t st) {
-  if (n <= 1) return LP_OK;
+// n: the record count, or with n_dev its upper bound (the count itself is
+// read on the device, so no host round trip is needed).  Sorted records end
+// in spec.w, or with where != nullptr wherever the last pass left them
+// (where[k] receives word k's buffer).
+static lp_status radix_sort_impl(const SortSpec& spec, int64_t n, const unsigned long long* n_dev,
+                                 DevBuf tmp[4], DevBuf& counts, DevBuf& scan_tmp, hipStream_t st,
+                                 uint32_t** where) {
+  if (n <= 1) {
+    if (where)
+      for (int k = 0; k < 4; k++) where[k] = spec.w[k];
+    return LP_OK;
+  }
   if (n >= (int64_t)UINT32_MAX) return set_error(LP_ERR_INVALID_ARGUMENT, "sort too large");
   const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
   for (int k = 0; k < spec.nwords; k++) LP_TRY(tmp[k].ensure((size_t)n * 4));
@@ -402,6 +422,7 @@ lp_status radix_sort(const SortSpec& spec, int64_t n, DevBuf tmp[4], DevBuf& cou
       pa.key_word = kw;
       pa.shift = shift;
       pa.invert = spec.invert[kw] ? 0xFFFFFFFFu : 0u;
+      pa.n_dev = n_dev;
       hipLaunchKernelGGL(radix_count_kernel, dim3((unsigned)ntiles), dim3(kSortThreads), 0, st, pa,
                          n, cnts, ntiles);
       LP_HIP(hipGetLastError());
@@ -433,11 +454,24 @@ lp_status radix_sort(const SortSpec& spec, int64_t n, DevBuf tmp[4], DevBuf& cou
       passes++;
     }
   }
-  if (passes & 1) {
+  if (where) {
+    for (int k = 0; k < 4; k++) where[k] = cur[k];
+  } else if (passes & 1) {
     for (int k = 0; k < spec.nwords; k++)
       LP_HIP(hipMemcpyAsync(spec.w[k], cur[k], (size_t)n * 4, hipMemcpyDeviceToDevice, st));
   }
   return LP_OK;
+}
+
+lp_status radix_sort(const SortSpec& spec, int64_t n, DevBuf tmp[4], DevBuf& counts,
+                     DevBuf& scan_tmp, hipStream_t st) {
+  return radix_sort_impl(spec, n, nullptr, tmp, counts, scan_tmp, st, nullptr);
+}
+
+lp_status radix_sort_device_count(const SortSpec& spec, int64_t n_cap, const unsigned long long* n_dev,
+                                  DevBuf tmp[4], DevBuf& counts, DevBuf& scan_tmp, hipStream_t st,
+                                  uint32_t** where) {
+  return radix_sort_impl(spec, n_cap, n_dev, tmp, counts, scan_tmp, st, where);
 }
 
 }  // namespace lp

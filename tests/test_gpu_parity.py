@@ -490,10 +490,13 @@ def test_full_size_rmat22_query(lp, rmat22, m):
     assert_query_rows(c, s, cnt, src, refq, m, f"R-MAT-22 query {m}", graph=gr, L=256)
 
 
-def test_server_mix_equals_alone(lp, config1):
+@pytest.mark.parametrize("host_launches", [False, True])
+def test_server_mix_equals_alone(lp, config1, host_launches):
     """Serving loop: requests of uneven size and two kinds, submitted together
     and batched by the server across three slots, each get exactly what
-    lp_query returns for that request alone (and what the oracle returns)."""
+    lp_query returns for that request alone (and what the oracle returns).
+    By default batches replay captured HIP graphs (the device-count query
+    path); host_launches runs every batch as lp_query does."""
     gr, _ = config1
     rng = np.random.default_rng(11)
     deg = gr.degrees()
@@ -504,11 +507,15 @@ def test_server_mix_equals_alone(lp, config1):
         size = int(np.exp(rng.uniform(0, np.log(400))))
         p = deg[nz] / deg[nz].sum()  # degree-biased sources, repeats allowed
         reqs.append((rng.choice(nz, size=size, p=p).astype(np.int32), kinds[i % 2]))
-    say(f"[gpu] server mix of {len(reqs)} requests")
+    say(f"[gpu] server mix of {len(reqs)} requests, host_launches={host_launches}")
     with lp.Graph(gr.offsets, gr.indices) as g:
-        with lp.Server(g, slots=3, max_batch_sources=300) as srv:
+        with lp.Server(g, slots=3, max_batch_sources=300, host_launches=host_launches) as srv:
             tickets = [srv.submit(src, m, L, kq) for src, (m, L, kq) in reqs]
             results = [srv.wait(t) for t in tickets]
+            # a second round of the same requests: batches of shapes seen
+            # before replay the graphs recorded then
+            tickets = [srv.submit(src, m, L, kq) for src, (m, L, kq) in reqs]
+            again = [srv.wait(t) for t in tickets]
         batches = {}
         for (out, rec) in results:
             assert rec["status"] == 0
@@ -516,6 +523,23 @@ def test_server_mix_equals_alone(lp, config1):
             assert rec["total_ms"] >= rec["run_ms"] >= 0
         assert max(batches.values()) > 1, "no request was batched with another"
         assert sum(batches.values()) == len(reqs)
+        first = [rec["replayed"] for _, rec in results]
+        second = [rec["replayed"] for _, rec in again]
+        if host_launches:
+            assert not any(first + second)
+        else:
+            # 1: replayed; 2: a batch outgrew the candidate capacity recorded
+            # for its kind so far and ran on host launches (batches form by
+            # timing, so a second-round batch can still be the largest); a
+            # failed capture or replay (3) never happens
+            assert first.count(1) > 0 and second.count(1) > len(second) // 2, (first, second)
+            assert set(first + second) <= {1, 2}, (first, second)
+        for (out, _), (out2, _) in zip(results, again):
+            assert np.array_equal(out[2], out2[2])
+            for i in range(out[2].shape[0]):
+                n = out[2][i]
+                assert np.array_equal(out[0][i][:n], out2[0][i][:n])
+                assert np.array_equal(out[1][i][:n], out2[1][i][:n])
         for (src, (m, L, kq)), (out, rec) in zip(reqs, results):
             c, s, cnt = lp.query(g, src, m, L, kq)
             assert np.array_equal(out[2], to_np(cnt))
@@ -568,8 +592,12 @@ def test_server_scratch_budget(lp, config1):
             assert all(rec["batch_bytes"] > 0 for _, rec in res)
             if batched:
                 assert max(sizes.values()) > 1
+                assert any(rec["replayed"] == 1 for _, rec in res)
+                assert all(rec["replayed"] in (1, 2) for _, rec in res)
             else:
                 assert set(sizes.values()) == {1}
+                # no replayed shape fits a budget below one request's need
+                assert not any(rec["replayed"] for _, rec in res)
             for (out, _), (c, s, n) in zip(res, ref):
                 assert np.array_equal(out[2], n)
                 for i in range(n.shape[0]):
@@ -649,11 +677,21 @@ def test_full_size_rmat24_server(lp):
             .astype(np.int32) for n in (1, 37, 512, 200)]
     with lp.Graph(gr.offsets, gr.indices) as g:
         with lp.Server(g, slots=2) as srv:
-            tickets = [srv.submit(r, "AA", 32, 10) for r in reqs]
-            outs = [srv.wait(t)[0] for t in tickets]
-    for r, out in zip(reqs, outs):
+            # twice: the second round replays graphs recorded in the first
+            rounds = []
+            for rnd in range(2):
+                tickets = [srv.submit(r, "AA", 32, 10) for r in reqs]
+                rounds.append([srv.wait(t) for t in tickets])
+    flags = [[rec["replayed"] for _, rec in res] for res in rounds]
+    say(f"replayed per round: {flags}")
+    for j, r in enumerate(reqs):
         ref = oracle.query(gr, 32, "AA", r, 10)
-        assert_query_rows(out[0], out[1], out[2], r, ref, "AA", "R-MAT-24 server", graph=gr, L=32)
+        for rnd, res in enumerate(rounds):
+            out = res[j][0]
+            assert_query_rows(out[0], out[1], out[2], r, ref, "AA",
+                              f"R-MAT-24 server, request {j}, round {rnd}, replayed {flags[rnd][j]}",
+                              graph=gr, L=32)
+    assert all(f in (1, 2) for f in flags[0] + flags[1]) and flags[1].count(1) >= 2, flags
 
 
 @pytest.mark.parametrize("budget", [-1, 3000])
