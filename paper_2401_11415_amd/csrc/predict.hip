@@ -396,11 +396,10 @@ struct WalkRound {
       }
     }
     // every lane loads (idx 0 where the lane has no wedge), so the loads need
-    // no branches
+    // no branches; the ids are masked where the round is consumed, so that
+    // nothing waits for the loads before then
 #pragma unroll
     for (int u = 0; u < kWin; u++) c[u] = g.adj[idx[u]];
-#pragma unroll
-    for (int u = 0; u < kWin; u++) c[u] = v[u] ? c[u] : kEmpty32;
   }
 };
 
@@ -415,14 +414,24 @@ __device__ inline void walk_chunk(const GView& g, const uint32_t* excl, const ui
   const uint32_t f0 = (uint32_t)f0l;
   const uint32_t f1 = (uint32_t)(f0l + q < (uint64_t)hi ? f0l + q : (uint64_t)hi);
   uint32_t j = uniform((uint32_t)seg_search<GA>(excl, f0));
-  WalkRound<NWG, GA> cur;
-  cur.start(g, excl, start, narcs, mark, f0, f1, j);
-  for (uint32_t base = f0; base < f1; base += 64 * kWin) {
-    const uint32_t nbase = base + 64 * kWin;
-    WalkRound<NWG, GA> nxt;
-    if (nbase < f1) nxt.start(g, excl, start, narcs, mark, nbase, f1, j);
-    fn(cur.c, cur.arc, cur.v);
-    cur = nxt;
+  // Two rounds in turn, so that no register copy of loaded ids (which would
+  // wait for the loads) sits between issuing a round and consuming it.  A
+  // round past the slice's end is still issued (no valid window, loads of
+  // entry 0): a conditional issue would make the compiler wait for every
+  // load in flight where the two paths meet.
+  constexpr uint32_t R = 64 * kWin;
+  WalkRound<NWG, GA> A, B;
+  A.start(g, excl, start, narcs, mark, f0, f1, j);
+  for (uint32_t base = f0; base < f1; base += 2 * R) {
+    B.start(g, excl, start, narcs, mark, base + R, f1, j);
+#pragma unroll
+    for (int u = 0; u < kWin; u++) A.c[u] = A.v[u] ? A.c[u] : kEmpty32;
+    fn(A.c, A.arc, A.v);
+    if (base + R >= f1) break;
+    A.start(g, excl, start, narcs, mark, base + 2 * R, f1, j);
+#pragma unroll
+    for (int u = 0; u < kWin; u++) B.c[u] = B.v[u] ? B.c[u] : kEmpty32;
+    fn(B.c, B.arc, B.v);
   }
 }
 
