@@ -94,9 +94,14 @@ struct BucketCuts {
   uint32_t t[kBucketHuge];
 };
 
-__device__ inline int bucket_of(uint32_t U, uint32_t T, const BucketCuts& cut) {
+// keys: a bound of the source's distinct keys (prediction orientation: the
+// ids above it, which can be far fewer than its wedges); a source above the
+// LDS capacity by wedges still takes an LDS table, in a few partitions, when
+// its keys fit the capacity and its wedges are at most 4 times it
+__device__ inline int bucket_of(uint32_t U, uint32_t T, const BucketCuts& cut, uint32_t keys = 0xFFFFFFFFu) {
   if (U == 0) return -1;
-  if (T > cut.t[kBucketLarge]) return kBucketHuge;
+  if (T > cut.t[kBucketLarge])
+    return keys <= cut.t[kBucketLarge] && T / 4 <= cut.t[kBucketLarge] ? kBucketLarge : kBucketHuge;
 #pragma unroll
   for (int b = kBucketTiny; b < kBucketLarge; b++)
     if (T <= cut.t[b]) return b;
@@ -136,7 +141,8 @@ __global__ __launch_bounds__(256) void plan_kernel(GView g, uint32_t hub_deg, Bu
         const uint64_t t = (uint64_t)U + (g.off[a + 1] - g.off[a] - g.below[a]);
         T = t > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)t;
       }
-      const int b = bucket_of(U, T, cuts);
+      const uint32_t room = (uint32_t)(g.n - 1 - a);  // keys lie in (a, n)
+      const int b = bucket_of(U, T, cuts, T < room ? T : room);
       if (b >= 0) {
         bk[j] = (uint8_t)b;
         nb[b]++;
