@@ -170,7 +170,9 @@ lp_status lp_fingerprint(lp_graph *g, int64_t hub_limit, uint64_t *out, void *hi
  * calls on g (host pointer; copied).
  *   lds_wedge_cap: T = U + d_a (wedges plus degree of a source) above which a
  *     source uses the global-memory accumulator instead of an LDS table
- *     (default 65536);
+ *     (default 65536); in lp_predict and lp_fingerprint a source keeps an LDS
+ *     table (in partitions) while its keys, at most min(T, ids above its own),
+ *     fit the cap and T is at most 4 times it;
  *   global_slots: workgroups of the global-memory path, each holding a dense
  *     accumulator of 12 bytes per vertex (default: one per compute unit; the
  *     pool of each workspace is also kept within an eighth of the device

@@ -444,6 +444,21 @@ def test_full_size_rmat22_topk_measures(lp, rmat22, m):
     assert_same_list(got, ref, m, f"R-MAT-22/{m}/L=256", graph=gr, L=256)
 
 
+def test_full_size_rmat22_topk_global(lp, rmat22):
+    """The benchmark's call with the LDS cap lowered to 2048, so that sources
+    above it (and above the key bound that keeps hubs on LDS tables) run on
+    the dense global accumulator at full size: the same list as the oracle."""
+    gr, k = rmat22
+    say(f"[gpu] R-MAT-22 predict JC k={k}, lds_wedge_cap 2048")
+    with lp.Graph(gr.offsets, gr.indices) as g:
+        lp.set_tuning(g, lds_wedge_cap=2048)
+        got = run_predict(lp, g, "JC", 256, k)
+        st = lp.last_stats(g)
+    assert st["launches"]["global"]["sources"] > 0
+    ref = oracle.predict(gr, 256, "JC", k)
+    assert_same_list(got, ref, "JC", "R-MAT-22/JC/L=256, dense accumulator")
+
+
 @pytest.mark.parametrize("L", [32, 64])
 def test_full_size_rmat22_cn_ties(lp, rmat22, L):
     """CN at small hub limits on the benchmark graph: counts are small
