@@ -424,7 +424,10 @@ def sweep(args, lp, synth, torch):
             rec = hits / max(k, 1)
             f1 = 2 * prec * rec / (prec + rec) if prec + rec > 0 else 0.0
             row = {"L": L if L is not None else "IBase", "ms": float(np.median(ms)), "wedges": st["wedges"],
-                   "k_out": k_out, "hits": hits, "precision": prec, "recall": rec, "f1": f1}
+                   "k_out": k_out, "hits": hits, "precision": prec, "recall": rec, "f1": f1,
+                   "ms_accumulate": st["ms_accumulate"], "ms_select": st["ms_select"],
+                   "appended": st["appended"], "retries": st["retries"],
+                   "ms_calls": [float(x) for x in ms]}
             rows.append(row)
             log(measure, json.dumps(row))
         ib = rows[-1]["ms"]

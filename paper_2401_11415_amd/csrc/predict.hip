@@ -2650,12 +2650,15 @@ lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int3
           // The score alone admits every key tied with the r-th one.  With
           // integer-like scores (CN at small hub limits) that run can hold
           // many times k keys, overflow the buffer and force a second pass;
-          // then the sample's r-th key itself (score and ids) is the bound,
-          // which the sample places about 1.5 k keys deep.
+          // then a key of the sample itself (score and ids) is the bound,
+          // taken twice as deep (about 3 k keys): which sources the sample
+          // holds varies with the order of the bucket lists, and a tied run
+          // that a few sources dominate makes the ids' estimate noisy.
           unsigned long long nge = 0;
           LP_TRY(count_ge(w, E, n_sample, tau, &nge, st));
-          if (nge * (unsigned long long)stride > kTieLimit * (unsigned long long)k)
-            LP_TRY(run_select(g, E.out_s, E.out_a, E.out_c, count, cap, 0, r_target, ts, ta, tc, tau, st,
+          const unsigned long long r_full = 2 * r_target;
+          if (nge * (unsigned long long)stride > kTieLimit * (unsigned long long)k && r_full < n_sample)
+            LP_TRY(run_select(g, E.out_s, E.out_a, E.out_c, count, cap, 0, r_full, ts, ta, tc, tau, st,
                               true));
         }
       }
