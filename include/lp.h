@@ -215,7 +215,9 @@ lp_status lp_set_tuning(lp_graph *g, const lp_tuning *t);
  * call, summed over the call's launches of that bucket in one kind of pass
  * (the main pass and any repeat of it; the sampling pass is kept apart).
  * Sources whose LDS table overflowed are counted under the global bucket,
- * which re-runs them.  Times are HIP events on the stream of each launch
+ * which re-runs them.  AA / RA with a threshold: a source of the tiny, small
+ * or mid1 bucket whose explored arcs' weights sum below the threshold has no
+ * key that can reach it; such sources are skipped whole and not counted.  Times are HIP events on the stream of each launch
  * (sampling-pass launches run concurrently on internal streams). */
 typedef struct {
   uint64_t launches;    /* kernel launches */

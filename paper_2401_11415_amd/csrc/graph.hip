@@ -426,7 +426,7 @@ void release_workspace(Workspace& w) {
   DevBuf* all[] = {&w.cnt, &w.wedges, &w.lists, &w.counters, &w.stats, &w.cand_s, &w.cand_a,
                    &w.cand_c, &w.tmp_s[0], &w.tmp_s[1], &w.tmp_a[0], &w.tmp_a[1], &w.tmp_c[0],
                    &w.tmp_c[1], &w.hist, &w.sel_state, &w.sort_tmp[0], &w.sort_tmp[1],
-                   &w.sort_tmp[2], &w.sort_tmp[3], &w.sort_counts, &w.scan_tmp, &w.global_tab, &w.unfit, &w.q_src,
+                   &w.sort_tmp[2], &w.sort_tmp[3], &w.sort_counts, &w.scan_tmp, &w.global_tab, &w.unfit, &w.kept, &w.q_src,
                    &w.q_cnt, &w.q_wedges, &w.q_rows, &w.q_out, &w.m_graph, &w.m_gid,
                    &w.m_lists, &w.spa_meta};
   for (auto b : all) b->release();

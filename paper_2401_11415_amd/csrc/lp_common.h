@@ -92,6 +92,7 @@ struct Workspace {
   DevBuf hist, sel_state, sort_tmp[4], sort_counts, scan_tmp;
   DevBuf global_tab, spa_meta;
   DevBuf unfit;  // packed AA / RA calls: sources whose sums do not fit a packed slot
+  DevBuf kept;   // AA / RA with a threshold: batched-bucket sources that can reach it
   unsigned global_slabs = 0;  // accumulator slabs in global_tab
   // query
   DevBuf q_src, q_cnt, q_wedges, q_rows, q_out;

@@ -2123,14 +2123,137 @@ static lp_status collect_work(Workspace& w, lp_stats* S, hipStream_t st) {
 }
 
 // The whole accumulation for one phase (all buckets, then overflow records).
+// ---------------------------------------------------------------------------
+// AA / RA with a threshold (Section 3.1 sums): every sum a source accumulates
+// adds the fixed-point weights of a subset of its explored arcs, so a source
+// whose arcs' weights together stay below the threshold sum has no key that
+// can pass.  This kernel copies the other records of a work list to out (in
+// any order; their count lands in *out_count), so that the accumulation
+// launch skips the rest whole.  A workgroup takes tiles of kPruneTile
+// records, each wave groups of 64: their arcs are walked as one flat range,
+// kWin windows of 64 at a time, each arc's weight added to its record's sum
+// in LDS.  The survivors of a tile take their output slots with one atomic.
+// ---------------------------------------------------------------------------
+constexpr int kPruneGroups = 4;                        // groups of 64 records per wave and tile
+constexpr uint32_t kPruneTile = 4 * 64 * kPruneGroups;  // records per workgroup and tile
+
+__global__ __launch_bounds__(256) void prune_weighted_kernel(GView g, Emit E, WorkList wl,
+                                                             SrcRec* __restrict__ out,
+                                                             uint32_t* __restrict__ out_count) {
+  __shared__ uint32_t s_excl[4][64];
+  __shared__ uint32_t s_h0[4][64];
+  __shared__ unsigned long long s_sum[4][64];
+  __shared__ uint8_t s_mark[4][64];
+  __shared__ uint32_t s_kept[4];
+  __shared__ uint32_t s_at;
+  const int wv = threadIdx.x >> 6;
+  const uint32_t lane = (uint32_t)lane_id();
+  uint32_t* excl = s_excl[wv];
+  uint32_t* h0 = s_h0[wv];
+  unsigned long long* sum = s_sum[wv];
+  uint8_t* mark = s_mark[wv];
+  mark[lane] = 0;
+  const uint32_t total = uniform(work_count(wl));
+  for (uint32_t tile = blockIdx.x * kPruneTile; tile < total; tile += gridDim.x * kPruneTile) {
+    SrcRec rec[kPruneGroups];
+    uint64_t M[kPruneGroups];
+    uint32_t nkept = 0;
+#pragma unroll
+    for (int q = 0; q < kPruneGroups; q++) {
+      const uint32_t base = tile + (uint32_t)(wv * kPruneGroups + q) * 64u;
+      const uint32_t i = base + lane;
+      const bool in = i < total;
+      SrcRec r{};
+      if (in) r = load_rec(wl, i);
+      const uint32_t nrec = base < total ? uniform(total - base < 64u ? total - base : 64u) : 0u;
+      // a listed source has wedges, so it explores at least one arc: the
+      // records' arc ranges are never empty, as the window decoder needs
+      uint32_t x = r.na;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= (uint32_t)o) x += y;
+      }
+      const uint32_t NA = uniform(__shfl(x, 63, 64));
+      excl[lane] = x - r.na;
+      h0[lane] = r.h0;
+      sum[lane] = 0;
+      wave_fence();
+      uint32_t j = 0;
+      for (uint32_t f = 0; f < NA; f += 64 * kWin) {
+        uint32_t d[kWin], ri[kWin];
+        bool v[kWin];
+#pragma unroll
+        for (int u = 0; u < kWin; u++) {
+          const uint32_t fb = f + 64u * u;
+          ri[u] = 0;
+          v[u] = false;
+          uint32_t e = 0;
+          if (fb < NA) {
+            ri[u] = decode_window(excl, nrec, mark, fb, j);
+            v[u] = fb + lane < NA;
+            if (v[u]) e = h0[ri[u]] + (fb + lane - excl[ri[u]]);
+          }
+          d[u] = g.hdeg[e];
+        }
+#pragma unroll
+        for (int u = 0; u < kWin; u++)
+          if (v[u]) atomicAdd(&sum[ri[u]], (unsigned long long)weight_of(E.measure, d[u], E.shift));
+      }
+      wave_fence();
+      const bool keep = in && sum[lane] >= min_wsum(E.measure, tau_of(E, r.key)[0], E.shift);
+      wave_fence();  // the sums are read before the next group resets them
+      rec[q] = r;
+      M[q] = __ballot(keep);
+      nkept += (uint32_t)__popcll(M[q]);
+    }
+    if (lane == 0) s_kept[wv] = nkept;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const uint32_t t = s_kept[0] + s_kept[1] + s_kept[2] + s_kept[3];
+      s_at = t ? atomicAdd(out_count, t) : 0u;
+    }
+    __syncthreads();
+    uint32_t at = s_at;
+    for (int w = 0; w < wv; w++) at += s_kept[w];
+    at = uniform(at);
+#pragma unroll
+    for (int q = 0; q < kPruneGroups; q++) {
+      if ((M[q] >> lane) & 1) out[at + rank_lt(M[q])] = rec[q];
+      at += (uint32_t)__popcll(M[q]);
+    }
+    __syncthreads();  // s_kept and s_at are read before the next tile writes them
+  }
+}
+
 template <int TM, bool kQuery>
 static lp_status run_phase(lp_graph* g, Workspace& w, const GView& gv, const Emit& E0,
                            const SrcRec* lists, uint64_t list_stride, const uint32_t* counts_host,
                            uint32_t stride, int phase, uint32_t* ovf_host_count, LaunchClock* clk,
                            hipStream_t st, const uint32_t* first = nullptr,
-                           const Readback* rb = nullptr) {
+                           const Readback* rb = nullptr, bool prune = false) {
   constexpr bool kW = TM != kTabCount;
   unsigned long long* work = work_counters(w);
+  auto items_of = [&](int b) -> uint64_t {
+    if (phase == 0 || stride <= 1) return phase == 2 ? 0 : counts_host[b];
+    const uint64_t ns = (counts_host[b] + stride - 1) / stride;
+    return phase == 1 ? ns : counts_host[b] - ns;
+  };
+  // AA / RA with a threshold: the batched buckets (tiny, small, mid1) first
+  // drop the sources whose arcs' weights cannot reach it; the survivors go to
+  // per-bucket lists whose lengths the accumulation kernels read on the device
+  SrcRec* kept = nullptr;
+  uint32_t* kept_count = nullptr;
+  uint64_t kept_off[kBucketMid1 + 2] = {};
+  if (kW && !kQuery && prune && phase != 1) {
+    for (int b = 0; b <= kBucketMid1; b++) kept_off[b + 1] = kept_off[b] + items_of(b);
+    if (kept_off[kBucketMid1 + 1] > 0) {
+      LP_TRY(w.kept.ensure(256 + kept_off[kBucketMid1 + 1] * sizeof(SrcRec)));
+      kept_count = w.kept.as<uint32_t>();
+      kept = reinterpret_cast<SrcRec*>(w.kept.as<char>() + 256);
+      LP_HIP(hipMemsetAsync(kept_count, 0, 4 * (kBucketMid1 + 1), st));
+    }
+  }
   // The sampling phase launches every bucket with a few sources each: those
   // launches are latency bound and independent, so they run concurrently on
   // side streams forked from and joined back to st.  Full phases run in
@@ -2153,18 +2276,21 @@ static lp_status run_phase(lp_graph* g, Workspace& w, const GView& gv, const Emi
   // largest buckets first: their long-running workgroups start early
   for (int b = kBuckets - 1; b >= 0; b--) {
     WorkList wl{lists + (uint64_t)b * list_stride + (first ? first[b] : 0u), counts_host[b], stride, phase};
-    uint64_t items;
-    if (phase == 0 || stride <= 1) items = phase == 2 ? 0 : counts_host[b];
-    else {
-      uint64_t ns = (counts_host[b] + stride - 1) / stride;
-      items = phase == 1 ? ns : counts_host[b] - ns;
-    }
+    const uint64_t items = items_of(b);
     if (items == 0) continue;
     Emit E = E0;
     E.work = work + (fan ? kSampledWork : 0) + b * 8;
     const int k = fan ? turn++ % (Workspace::kSide + 1) : 0;
     hipStream_t sb = k == 0 ? st : w.side[k - 1];
     const int slot = fan ? LaunchClock::kSlots + b : b;
+    if (kept && b <= kBucketMid1) {
+      // (not timed with the bucket: its clock covers the accumulation kernel)
+      SrcRec* dst = kept + kept_off[b];
+      hipLaunchKernelGGL(prune_weighted_kernel, dim3(grid_for(items, kPruneTile, (unsigned)num_cus() * 8)), dim3(256),
+                         0, sb, gv, E, wl, dst, kept_count + b);
+      LP_HIP(hipGetLastError());
+      wl = WorkList{dst, 0, 1, 0, kept_count + b};
+    }
     if (clk) LP_TRY(clk->start(slot, sb));
     if constexpr (!kQuery) {
       if (fan) {
@@ -2239,16 +2365,17 @@ static lp_status run_phase_any(lp_graph* g, Workspace& w, const GView& gv, const
                                const SrcRec* lists, uint64_t list_stride,
                                const uint32_t* counts_host, uint32_t stride, int phase,
                                uint32_t* ovf_host_count, LaunchClock* clk, hipStream_t st,
-                               const uint32_t* first = nullptr, const Readback* rb = nullptr) {
+                               const uint32_t* first = nullptr, const Readback* rb = nullptr,
+                               bool prune = false) {
   // AA / RA: packed tables when the call set them up (pk_idbits > 0)
   if constexpr (!kQuery) {
     if ((E.measure == LP_AA || E.measure == LP_RA) && E.pk_idbits > 0)
       return run_phase<kTabPacked, kQuery>(g, w, gv, E, lists, list_stride, counts_host, stride, phase,
-                                           ovf_host_count, clk, st, first, rb);
+                                           ovf_host_count, clk, st, first, rb, prune);
   }
   if (E.measure == LP_AA || E.measure == LP_RA)
     return run_phase<kTabSplit, kQuery>(g, w, gv, E, lists, list_stride, counts_host, stride, phase,
-                                        ovf_host_count, clk, st, first, rb);
+                                        ovf_host_count, clk, st, first, rb, prune);
   return run_phase<kTabCount, kQuery>(g, w, gv, E, lists, list_stride, counts_host, stride, phase,
                                       ovf_host_count, clk, st, first, rb);
 }
@@ -2674,7 +2801,7 @@ lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int3
     rb.bytes[1] = 12;
     if (sample)
       LP_TRY(run_phase_any<false>(g, w, gv, E, lists, (uint64_t)g->n, pr.out.count,
-                                  stride, 2, &ovf_host, &clk, st, nullptr, &rb));
+                                  stride, 2, &ovf_host, &clk, st, nullptr, &rb, true));
     else
       LP_TRY(run_phase_any<false>(g, w, gv, E, lists, (uint64_t)g->n, pr.out.count,
                                   1, 0, &ovf_host, &clk, st, nullptr, &rb));
@@ -3176,7 +3303,7 @@ lp_status run_predict_multi(lp_graph* g, int64_t ng, const int64_t* vstart, cons
     if (sample) {
       LP_HIP(hipMemcpyAsync(count, &n_sample, 8, hipMemcpyHostToDevice, st));
       LP_TRY(run_phase_any<false>(g, w, gv, E, split_lists, nl, n_rest, 1, 0, &ovf_host, &clk, st, nullptr,
-                                  &rb));
+                                  &rb, true));
     } else {
       LP_TRY(run_phase_any<false>(g, w, gv, E, lists, (uint64_t)g->n, pr.out.count, 1, 0, &ovf_host,
                                   &clk, st, nullptr, &rb));

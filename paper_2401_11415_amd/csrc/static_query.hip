@@ -107,7 +107,7 @@ lp_status init_device(DeviceScratch& d) {
   // the remaining buffers of a workspace stay empty and fixed: nothing grows
   DevBuf* none[] = {&w.cnt,      &w.wedges,   &w.lists,     &w.tmp_s[0],   &w.tmp_s[1], &w.tmp_a[0],
                     &w.tmp_a[1], &w.tmp_c[0], &w.tmp_c[1],  &w.hist,       &w.sel_state, &w.sort_tmp[3],
-                    &w.unfit,    &w.q_wedges, &w.q_out,     &w.m_graph,    &w.m_gid,    &w.m_lists};
+                    &w.unfit,    &w.kept,      &w.q_wedges, &w.q_out,     &w.m_graph,    &w.m_gid,    &w.m_lists};
   for (DevBuf* b : none) {
     b->p = d.ptr;  // non-null so that a zero-byte request succeeds; cap 0 refuses any other
     b->cap = 0;
