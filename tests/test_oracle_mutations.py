@@ -21,6 +21,7 @@ MUTATIONS = {
     "skip_rule": ("if (c == a || (mode == 0 && c < a)) continue;", "if (mode == 0 && c < a) continue;"),
     "no_first_order_clear": ("for (int64_t e = off[a]; e < off[a + 1]; e++) t->adj_a[idx[e]] = 1;", ""),
     "tie_order": ("if (x->a != y->a) return x->a < y->a;", "if (x->a != y->a) return x->a > y->a;"),
+    "subset_ignores_list": ("const int64_t a = sources ? sources[i] : i;", "const int64_t a = i;"),
     "threshold_inclusive": ("if (!(s32 > s_th)) continue; /* strictly above the score threshold */",
                             "if (!(s32 >= s_th)) continue;"),
 }
@@ -40,6 +41,6 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
                         "-k", "closed_forms or hub_limit or worked or topk_matches or random_graphs"
-                              " or wedge_identity"],
+                              " or wedge_identity or source_subset"],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"planted mistake {name} was not caught:\n{r.stdout[-2000:]}"

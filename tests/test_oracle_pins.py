@@ -359,6 +359,28 @@ def test_topk_matches_full_sort(m):
             assert np.array_equal(got["s32"], np.array([r[0] for r in want], np.float32))
 
 
+@pytest.mark.parametrize("m", MEAS)
+def test_topk_of_source_subset(m):
+    """The subset form (what the CPU baseline times): the top k of the
+    candidates owned by the listed sources, i.e. pairs a < c with a listed,
+    against the full sort of the brute-force candidates so restricted.  A
+    list taken in any order; an empty list gives nothing."""
+    g = synth.chung_lu(500, 8.0, 2.3, 4)
+    cands = cands_c(g, 32, m)
+    rng = np.random.default_rng(7)
+    for frac in (0.0, 0.1, 0.5, 1.0):
+        src = rng.choice(g.n, int(frac * g.n), replace=False).astype(np.int32)
+        listed = set(src.tolist())
+        ref = sort_reference({p: v for p, v in cands.items() if p[0] in listed})
+        for k in (1, 50, len(ref) + 5):
+            got = oracle.predict_sources(g, 32, m, k, src, threads=3)
+            want = ref[:k]
+            assert len(got["a"]) == len(want)
+            assert [(int(a), int(c)) for a, c in zip(got["a"], got["c"])] == [(r[1], r[2]) for r in want]
+            assert np.array_equal(got["s32"], np.array([r[0] for r in want], np.float32))
+            assert np.allclose(got["s64"], [r[3] for r in want], rtol=1e-12, atol=0)
+
+
 def test_topk_thread_count_invariant(config1):
     g, held = config1
     k = held.shape[0]
