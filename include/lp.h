@@ -179,7 +179,9 @@ lp_status lp_fingerprint(lp_graph *g, int64_t hub_limit, uint64_t *out, void *hi
  *     memory);
  *   sample_budget: wedge budget of the sampling pass that sets the top-k
  *     filter threshold (default: about 0.1% of the call's wedges, clamped to
- *     [2^20, 2^22]; a negative value disables sampling);
+ *     [2^20, 2^22]; a negative value disables sampling); the sample also
+ *     takes at least one in 1024 of the sources with wedges, whatever the
+ *     budget;
  *   bucket_max[b]: upper bound of T for the scheduling buckets tiny, small,
  *     mid1, mid2, mid3 (defaults 32, 256, 1024, 2048, 4096, the table sizes
  *     the kernels are built for; a value may only lower its default, moving

@@ -12,20 +12,22 @@
 //    list, since intermediates are ordered by degree) and its exact wedge
 //    count U(a); sources go to seven buckets by T = U + (first-order
 //    neighbours after a).
-//  * accumulation: small sources run in batches (48, 8 or 4 per workgroup)
-//    that share one LDS hash table keyed by (position in the batch, c);
-//    larger ones get a whole workgroup (256, 512 or 1024 lanes) and a table
-//    sized by a bound on their distinct keys, split into hash partitions when
-//    it exceeds the LDS; sources above the LDS capacity use a dense
-//    accumulator in global memory.  A window decoder turns 64 consecutive
-//    flat wedge indices into (arc, position) pairs with one ballot, so lanes
-//    read consecutive ids of the same neighbour list (coalesced).
+//  * accumulation: small sources run in batches (48 or 8 per 256-lane
+//    workgroup, 4 per 512 lanes) that share one LDS hash table keyed by
+//    (position in the batch, c); larger ones get a whole workgroup (256, 512
+//    or 1024 lanes) and a table sized by a bound on their distinct keys,
+//    split into hash partitions when it exceeds the LDS; sources whose keys
+//    exceed the LDS capacity use a dense accumulator in global memory.  A
+//    window decoder turns 64 consecutive flat wedge indices into (arc,
+//    position) pairs with one ballot, so lanes read consecutive ids of the
+//    same neighbour list (coalesced).
 //  * count tables (CN ... LHN) hold (count << 32 | key) per 64-bit slot; AA /
 //    RA tables hold key and fixed-point sum in one 64-bit slot when the
 //    per-source precision bound allows, else 12-byte slots.
 //  * with a top-k threshold, the normalised measures bound the degree (hence
-//    the id) of any candidate that can still pass; rows ascend, so only the
-//    part of each row below that id is read.
+//    the id) of any candidate that can still pass: wedges to ids at or above
+//    that cutoff are loaded but not inserted.  AA / RA sources whose arc
+//    weights sum below the threshold are dropped before their batch runs.
 //  * scoring is fused into the table sweep; survivors of S_th and of a key
 //    threshold tau are appended with one atomic per wave.
 //  * top-k: MSD radix select over the 96-bit key (score bits, ~a, ~c), then a
@@ -49,11 +51,11 @@ namespace lp {
 enum : int {
   kBucketTiny = 0,   // T <= 32:      48 sources per 256-lane workgroup
   kBucketSmall = 1,  // T <= 256:     8 sources per workgroup
-  kBucketMid1 = 2,   // T <= 1024:    2 sources per workgroup
+  kBucketMid1 = 2,   // T <= 1024:    4 sources per 512-lane workgroup (12-byte tables: 2 per 256)
   kBucketMid2 = 3,   // T <= 2048:    256 lanes per source
   kBucketMid3 = 4,   // T <= 4096:    512 lanes per source
   kBucketLarge = 5,  // T <= cap:     1024 lanes, hash partitions
-  kBucketHuge = 6,   // T >  cap:     dense accumulator in global memory
+  kBucketHuge = 6,   // T >  cap:     dense accumulator in global memory (unless few keys: large)
   kBuckets = 7
 };
 
@@ -2673,6 +2675,8 @@ static lp_status count_ge(Workspace& w, const Emit& E, unsigned long long n, con
 // A sampled threshold keeps only the score unless the keys tied with it
 // would exceed this many times k.
 constexpr unsigned long long kTieLimit = 3;
+// The sample holds at least one in this many sources (of those with wedges).
+constexpr uint64_t kMinSampleShare = 1024;
 
 lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int32_t* out_a,
                       int32_t* out_c, float* out_score, int64_t* out_count, hipStream_t st) {
@@ -2709,10 +2713,16 @@ lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int3
   // threshold; tau is then a lower bound of its r-th best key with
   // r = 1.5 k / stride, and the remaining sources only keep keys >= tau.
   const bool sample = budget > 0 && total_w > budget && total_w > 8ull * (uint64_t)k;
+  // The stride also keeps at least one in kMinSampleShare sources in the
+  // sample: with few hub intermediates cut (IBase, large L) the wedge budget
+  // alone left a few dozen sampled sources, which miss the hubs that own the
+  // best pairs, so the estimated threshold fell far too low and the main
+  // pass overflowed its buffer.
   uint32_t stride = 1;
   if (sample) {
     const uint64_t s = (total_w + budget - 1) / budget;
-    stride = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(s, 2), 1u << 20);
+    const uint64_t by_sources = std::max<uint64_t>(pr.out.sources / kMinSampleShare, 2);
+    stride = (uint32_t)std::min<uint64_t>(std::min<uint64_t>(std::max<uint64_t>(s, 2), by_sources), 1u << 20);
   }
   uint64_t cap = sample ? 2 * (total_w / stride) + 4 * (uint64_t)k + (1u << 20) : total_w;
   cap = std::min<uint64_t>(cap, total_w);
