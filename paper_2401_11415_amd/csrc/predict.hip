@@ -2706,6 +2706,10 @@ lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int3
     S.ms_total = tm.ms(0, 3);
     return LP_OK;
   }
+  // the fixed-point precision bound of AA / RA is checked before any buffer
+  // is sized from the wedge count
+  int wshift = 0;
+  LP_TRY(weighted_shift(g, m, L, &wshift));
   const uint64_t total_w = pr.out.wedges;
   const uint64_t budget = sample_budget(g, total_w);
   // Sampling pays off only when candidates far outnumber k: a sampled subset
@@ -2742,7 +2746,7 @@ lp_status run_predict(lp_graph* g, int m, int64_t L, int64_t k, float s_th, int3
   uint32_t* tc = ta + cap;
   Emit E{};
   E.measure = m;
-  LP_TRY(weighted_shift(g, m, L, &E.shift));
+  E.shift = wshift;
   E.s_th = s_th;
   E.tau = tau;
   packed_params(g, m, L, &E);
@@ -3191,6 +3195,10 @@ lp_status run_predict_multi(lp_graph* g, int64_t ng, const int64_t* vstart, cons
     return LP_OK;
   }
   const GView gv = view_of(g);
+  // the fixed-point precision bound of AA / RA is checked before any buffer
+  // is sized from the wedge count
+  int wshift = 0;
+  LP_TRY(weighted_shift(g, m, L, &wshift));
   const uint64_t total_w = pr.out.wedges;
   const uint64_t budget = sample_budget(g, total_w);
   const bool sample = budget > 0 && total_w > budget && total_w > 8ull * ktot;
@@ -3249,7 +3257,7 @@ lp_status run_predict_multi(lp_graph* g, int64_t ng, const int64_t* vstart, cons
   LP_TRY(ensure_select_bufs(w, cap));
   Emit E{};
   E.measure = m;
-  LP_TRY(weighted_shift(g, m, L, &E.shift));
+  E.shift = wshift;
   E.s_th = s_th;
   E.tau = tau;
   packed_params(g, m, L, &E);
@@ -3525,6 +3533,8 @@ lp_status run_query(lp_graph* g, Workspace& w, const int32_t* sources, int64_t n
   LP_HIP(hipStreamSynchronize(st));
   const PlanOut po = *hp;
   if (po.bad_source) return set_error(LP_ERR_INVALID_ARGUMENT, "a source id is outside [0, n)");
+  int wshift = 0;
+  LP_TRY(weighted_shift(g, m, L, &wshift));
   uint64_t cap = std::max<uint64_t>(po.wedges, 1);
   if (cap > (1ull << 32) - 1) return set_error(LP_ERR_OUT_OF_MEMORY, "query batch too large");
   if (w.cand_s.fixed && cap * 4 > w.cand_s.cap)
@@ -3545,7 +3555,7 @@ lp_status run_query(lp_graph* g, Workspace& w, const int32_t* sources, int64_t n
   LP_TRY(ensure_ovf(w, &ovf, &ovf_rec, &ovf_count, &ovf_cap, &err, &count, &fp, &tau, st));
   Emit E{};
   E.measure = m;
-  LP_TRY(weighted_shift(g, m, L, &E.shift));
+  E.shift = wshift;
   E.s_th = s_th;
   E.tau = tau;
   E.out_s = w.cand_s.as<uint32_t>();

@@ -392,6 +392,25 @@ def test_invalid_inputs(lp):
         assert to_np(a).tolist() == [0, 1] and to_np(c).tolist() == [2, 3]
 
 
+def test_weighted_precision_bound(lp):
+    """AA / RA sums are fixed point with as many fraction bits as the largest
+    degree allows.  With an explored intermediate of degree 3,000,000 an RA
+    term (1/d_b) cannot keep 2^-24 of its value, so the call refuses with
+    LP_ERR_INVALID_ARGUMENT instead of rounding terms away; with a hub limit
+    below that degree the same graph runs (and, on a star, has no wedges)."""
+    say("[gpu] weighted fixed-point bound")
+    leaves = 3_000_000
+    n = leaves + 1
+    off = np.concatenate([[0], leaves + np.arange(0, n, dtype=np.int64)]).astype(np.int64)
+    idx = np.concatenate([np.arange(1, n, dtype=np.int32), np.zeros(leaves, np.int32)])
+    with lp.Graph(off, idx) as g:
+        with pytest.raises(lp.LpError) as e:
+            lp.predict(g, "RA", None, 10)
+        assert e.value.name == "LP_ERR_INVALID_ARGUMENT" and "hub limit" in e.value.detail
+        a, c, s = lp.predict(g, "RA", 1000, 10)
+        assert len(to_np(a)) == 0
+
+
 @pytest.fixture(scope="module")
 def rmat22():
     """The benchmark workload: R-MAT scale 22, edge factor 16, seed 1, 10% holdout."""
