@@ -346,12 +346,26 @@ __device__ inline void load_chunk(const GView& g, const Emit& E, const SrcRec& s
   if (kW) s_w[gl] = w;
 }
 
-// Table geometry of a source: P hash partitions, S slots each (load <= 2/3).
-__device__ inline void table_geometry(uint32_t U, uint32_t slots, uint32_t* P, uint32_t* S) {
+// Linear probing slows down sharply as a table fills, so a table that fits
+// its workgroup's slots in one partition takes up to a spread times its key
+// bound, in halves: kSpreadHalves[batched][weighted].  Sums spread most
+// (load <= 1/3): on the AA / RA workloads nearly every wedge is a new key, so
+// their tables come close to the bound.  R-MAT count tables hold about one
+// key per 1.3 wedges, so a wider table mostly lengthens the sweep: per-source
+// tables take 2x, batch tables keep 1.5x.  (Chung-Lu 8M RA at L = 256: 47.0
+// ms per call with 1.5x everywhere, 39.7 with 2x, 38.5 with 3x; R-MAT-22 JC
+// mid1 batches 1.83, 1.87, 2.0 ms; its per-source kernels gain with 2x.)
+constexpr uint32_t kSpreadHalves[2][2] = {{4, 6}, {3, 6}};
+
+// Table geometry of a source with at most U keys: P hash partitions (each
+// loaded at most 2/3), S slots each.
+__device__ inline void table_geometry(uint32_t U, uint32_t slots, uint32_t* P, uint32_t* S,
+                                      uint32_t spread_halves) {
   const uint64_t need = ((uint64_t)U * 3 + 1) / 2;
   if (need <= slots) {
     *P = 1;
-    *S = need < 16 ? 16u : (uint32_t)need;
+    const uint64_t roomy = std::min<uint64_t>((uint64_t)U * spread_halves / 2, slots);
+    *S = roomy < 16 ? 16u : (uint32_t)roomy;
     return;
   }
   uint32_t p = (uint32_t)((need + slots - 1) / slots);
@@ -559,7 +573,7 @@ __global__ __launch_bounds__(WGS, TM == kTabPacked ? 4 : 1) void acc_lds_kernel(
       keys_max = room < keys_max ? room : keys_max;
     }
     uint32_t P, S;
-    table_geometry(keys_max, SLOTS, &P, &S);
+    table_geometry(keys_max, SLOTS, &P, &S, kSpreadHalves[0][kW ? 1 : 0]);
     // packed sums: a source whose sums may not fit is handed over whole
     if (kPacked && !packed_fits(E.measure, s.na, kb, E.shift)) {
       if (gl == 0) hand_unfit(E, s);
@@ -878,9 +892,11 @@ __global__ __launch_bounds__(WGS, TM == kTabPacked ? 4 : 1) void acc_batch_kerne
     }
     __syncthreads();
     const uint32_t NA = uniform(L.arcoff[B]), NX = uniform(L.xoff[B]);
-    uint32_t S = (uint32_t)(((uint64_t)uniform(L.keys_max) * 3 + 1) / 2);
+    // the batch's table, spread like a source's (table_geometry) and capped
+    // at the kernel's slots
+    uint32_t S = (uint32_t)std::min<uint64_t>(
+        (uint64_t)uniform(L.keys_max) * kSpreadHalves[1][kW ? 1 : 0] / 2, SLOTS);
     if (S < 16) S = 16;
-    if (S > (uint32_t)SLOTS) S = SLOTS;  // cannot happen within the bucket's bounds
     // first batch of first-order keys, in flight during the accumulation
     uint32_t xkey = kEmpty32;
     if ((uint32_t)(WGS - 1 - tid) < NX) {
