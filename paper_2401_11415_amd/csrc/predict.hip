@@ -110,7 +110,7 @@ __device__ inline int bucket_of(uint32_t U, uint32_t T, const BucketCuts& cut, u
   return kBucketLarge;
 }
 
-constexpr int kPlanItems = 16;  // sources per thread of the plan kernel
+constexpr int kPlanItems = 8;  // sources per thread of the plan kernel
 
 // Bucket a tile of 256 * kPlanItems sources with one global atomic per
 // (workgroup, bucket); records land in lists[bucket * stride + position].
@@ -128,6 +128,41 @@ __global__ __launch_bounds__(256) void plan_kernel(GView g, uint32_t hub_deg, Bu
   uint8_t bk[kPlanItems];
   uint32_t nb[kBuckets] = {};
   unsigned long long w_sum = 0, s_sum = 0;
+  // explored prefix of every item's two-hop arcs: the binary searches of a
+  // thread's items run in lockstep, so each step has kPlanItems independent
+  // loads in flight instead of one dependent chain per item
+  uint32_t lo[kPlanItems], hi[kPlanItems], na[kPlanItems];
+#pragma unroll
+  for (int j = 0; j < kPlanItems; j++) {
+    const uint64_t a = tile + (uint64_t)j * 256 + threadIdx.x;
+    lo[j] = hi[j] = 0;
+    if (a < g.n) {
+      lo[j] = g.hoff[a];
+      hi[j] = g.hoff[a + 1];
+    }
+    na[j] = lo[j];  // row start, until the search ends
+  }
+  for (;;) {
+    bool more = false;
+#pragma unroll
+    for (int j = 0; j < kPlanItems; j++) more = more | (lo[j] < hi[j]);
+    if (!more) break;
+    // an item whose search has ended reads entry 0, which exists: some item
+    // of this thread still has arcs
+    uint32_t v[kPlanItems];
+#pragma unroll
+    for (int j = 0; j < kPlanItems; j++) v[j] = g.hdeg[lo[j] < hi[j] ? lo[j] + ((hi[j] - lo[j]) >> 1) : 0u];
+#pragma unroll
+    for (int j = 0; j < kPlanItems; j++) {
+      if (lo[j] < hi[j]) {
+        const uint32_t mid = lo[j] + ((hi[j] - lo[j]) >> 1);
+        if (v[j] < hub_deg) lo[j] = mid + 1;
+        else hi[j] = mid;
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kPlanItems; j++) na[j] = lo[j] - na[j];
 #pragma unroll
   for (int j = 0; j < kPlanItems; j++) {
     const uint64_t a = tile + (uint64_t)j * 256 + threadIdx.x;
@@ -136,7 +171,7 @@ __global__ __launch_bounds__(256) void plan_kernel(GView g, uint32_t hub_deg, Bu
       const uint32_t h0 = g.hoff[a], h1 = g.hoff[a + 1];
       uint32_t U = 0, T = 0;
       if (h1 > h0) {
-        const uint32_t k = lower_bound_dev(g.hdeg, h0, h1, hub_deg) - h0;
+        const uint32_t k = na[j];
         U = k ? g.hpsum[h0 + k - 1] : 0u;
         // the bucket follows the work (wedges), not the key bound: a source
         // with many wedges but few reachable keys still needs many lanes
@@ -198,9 +233,9 @@ __global__ __launch_bounds__(256) void plan_kernel(GView g, uint32_t hub_deg, Bu
   for (int j = 0; j < kPlanItems; j++) {
     if (bk[j] == 0xFF) continue;
     const uint32_t a = (uint32_t)(tile + (uint64_t)j * 256 + threadIdx.x);
-    // second read of the row bounds: cheap (cached) and keeps registers low
-    const uint32_t h0 = g.hoff[a], h1 = g.hoff[a + 1];
-    const uint32_t k = lower_bound_dev(g.hdeg, h0, h1, hub_deg) - h0;
+    // second read of the row start: cheap (cached)
+    const uint32_t h0 = g.hoff[a];
+    const uint32_t k = na[j];
     SrcRec r;
     r.a = a;
     r.key = g.perm[a];
