@@ -110,7 +110,7 @@ __device__ inline int bucket_of(uint32_t U, uint32_t T, const BucketCuts& cut, u
   return kBucketLarge;
 }
 
-constexpr int kPlanItems = 8;  // sources per thread of the plan kernel
+constexpr int kPlanItems = 4;  // sources per thread of the plan kernel
 
 // Bucket a tile of 256 * kPlanItems sources with one global atomic per
 // (workgroup, bucket); records land in lists[bucket * stride + position].
